@@ -1,0 +1,228 @@
+/*
+ * adc.h -- C ABI of the MI355X (gfx950) accelerated divide-and-conquer
+ * tridiagonal eigensolver.
+ *
+ * The problem (Section 2, eq. T): a real symmetric tridiagonal matrix T with
+ * diagonal a[0..n) and off-diagonal b[0..n-1); all eigenvalues Lambda and an
+ * orthonormal eigenvector matrix Q with T Q = Q Lambda (Algorithm 1, ADC(T,Q,
+ * Lambda)).  The merge step of Algorithm 1 solves the secular equation of
+ * D + rho z z^T (Theorem 1), recomputes z by Loewner's formula (eq. ev_z),
+ * forms the Cauchy-like eigenvector matrix Q' from its generators (eq. Ev-Q,
+ * eq. cauchylike, Remark 1) and updates the eigenvectors either by a dense
+ * product diag(Q1,Q2) Q' or through an HSS approximation of Q' built by
+ * Algorithm 2 and applied by Algorithm 3.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (HIP global memory of the
+ *    context's device) unless the comment says "host".  Matrices are FP64,
+ *    column-major, with the stated leading dimension.
+ *  - The caller owns every array it passes.  The library never keeps a
+ *    pointer to caller memory after the call returns.
+ *  - Calls are ordered on the context's HIP stream.  Entry points marked
+ *    "blocking" synchronise that stream before returning; the others only
+ *    enqueue work.
+ *  - The library never aborts and never prints.  Errors are reported by the
+ *    return value; adc_status_string() names them.  Invalid arguments give
+ *    ADC_ERR_ARG before any work is enqueued.
+ *  - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef ADC_H
+#define ADC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum adc_status {
+  ADC_OK = 0,
+  ADC_ERR_ARG = 1,          /* invalid argument or non-finite input          */
+  ADC_ERR_NOMEM = 2,        /* device allocation failed                      */
+  ADC_ERR_HIP = 3,          /* a HIP runtime call failed                     */
+  ADC_ERR_NOCONV = 4,       /* a secular root did not converge (info_index)  */
+  ADC_ERR_ACCURACY = 5,     /* HSS check failed and opts.strict was set      */
+  ADC_ERR_UNSUPPORTED = 6   /* size or option outside what is implemented    */
+} adc_status;
+
+typedef struct adc_ctx_s* adc_ctx;
+typedef struct adc_hss_s* adc_hss;
+
+/* How the HSS sample count s = r + p is chosen for one merge.
+ * BOUND: r from eq. (bounds) over neighbouring leaf segments (Section 4.1).
+ * MLP:   r from the learned rank predictor (adc_mlp_*), BOUND as a floor of 8.
+ * FIXED: r = opts.fixed_rank. */
+typedef enum adc_rank_mode { ADC_RANK_BOUND = 0, ADC_RANK_MLP = 1, ADC_RANK_FIXED = 2 } adc_rank_mode;
+
+/* Options.  adc_opts_default() fills the values in brackets. */
+typedef struct adc_opts {
+  int32_t dc_leaf;       /* [32] DC leaf size m (Algorithm 1); 2..64            */
+  int32_t hss_min_k;     /* [2048] HSS update only if the deflated size K >= this
+                            (Section 4.3 uses "larger than 2000")             */
+  int32_t hss_levels;    /* [3] only the top hss_levels merge levels may use HSS;
+                            <0 means every level                              */
+  int32_t hss_leaf;      /* [128] HSS leaf size (rows per leaf node)          */
+  double  id_tol;        /* [1e-14] ID truncation |R_kk| <= id_tol |R_11|       */
+  int32_t oversample;    /* [10] p (Section 3: "p = 10")                       */
+  int32_t rank_mode;     /* [ADC_RANK_BOUND] adc_rank_mode                      */
+  int32_t fixed_rank;    /* [0] r for ADC_RANK_FIXED                            */
+  int32_t max_retries;   /* [2] sample doublings before the dense fallback     */
+  int32_t max_iter;      /* [60] secular iterations per root                   */
+  uint64_t seed;         /* [20151015] seed of the Gaussian sampling matrices  */
+  int32_t force_dense;   /* [0] 1: plain DC, never HSS                          */
+  int32_t strict;        /* [0] 1: a failed HSS check is ADC_ERR_ACCURACY       */
+  double  check_tol;     /* [1e-12] relative error allowed by the HSS check     */
+  int32_t nprobe;        /* [4] Gaussian probe vectors of the HSS check         */
+  int32_t shift_max;     /* [5] max boundary move of the rank estimate          */
+  double  shift_thresh;  /* [1e-10] move a boundary when its distance is below  */
+  int32_t r_cap;         /* [100] cap of the estimated rank                     */
+  double  rank_eps;      /* [1e-16] epsilon of eq. (bounds)                     */
+} adc_opts;
+
+/* Report of one solve (host struct, optional). */
+typedef struct adc_report {
+  int32_t levels;            /* merge levels of the DC tree                    */
+  int32_t merges;            /* merges performed                               */
+  int32_t hss_merges;        /* merges updated through HSS                     */
+  int32_t retries;           /* HSS sample doublings                           */
+  int32_t hss_fallbacks;     /* HSS merges that fell back to the dense update  */
+  int32_t info_index;        /* failing argument / root index, else -1         */
+  int64_t n_per_level[64];   /* sum of merge sizes n per level (top = 0)       */
+  int64_t K_per_level[64];   /* sum of deflated sizes K per level               */
+  int32_t hss_per_level[64]; /* HSS merges per level                            */
+  int32_t max_rank;          /* largest HSS node rank seen                      */
+  int32_t samples;           /* largest sample count s used                     */
+  double  t_phase[12];       /* seconds: 0 leaves, 1 deflation, 2 secular,
+                                3 loewner+v, 4 dense Cauchy+GEMM, 5 HSS sampling,
+                                6 HSS compression, 7 HSS check, 8 HSS multiply,
+                                9 permute/copy, 10 total, 11 host overhead
+                                (filled only when timing is requested by
+                                a non-null report with t_phase[0] = -1)       */
+  double  flops_model;       /* algorithmic flops of the chosen updates        */
+  double  bytes_model;       /* algorithmic HBM bytes of the chosen updates    */
+  double  check_err_max;     /* largest HSS check error accepted               */
+} adc_report;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, ordered on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context. */
+adc_status adc_create(adc_ctx* out, int device, void* hip_stream);
+/* Release the context and its device memory pool. */
+adc_status adc_destroy(adc_ctx ctx);
+/* Fill *opts with the defaults listed above. */
+adc_status adc_opts_default(adc_opts* opts);
+/* Static string naming a status. */
+const char* adc_status_string(adc_status s);
+/* Device bytes adc_stedc needs for size n with the given options.  Passing a
+ * caller workspace of that size avoids the context's own pool. */
+adc_status adc_workspace_query(adc_ctx ctx, int64_t n, const adc_opts* opts, size_t* bytes);
+
+/* ----------------------------------------------------------------- solve */
+
+/* Eigendecomposition of T (Algorithm 1).  Blocking.
+ *   diag[n], offdiag[n-1] : input (read-only); offdiag may be NULL iff n == 1
+ *   w[n]                  : eigenvalues, ascending
+ *   Z[ldz*n]              : eigenvectors, column j belongs to w[j]; ldz >= n
+ *   ws, ws_bytes          : optional workspace (NULL: the context pool)
+ *   opts                  : host struct, NULL = defaults
+ *   rep                   : host struct, may be NULL
+ * Non-finite input returns ADC_ERR_ARG.  A root that fails to converge
+ * returns ADC_ERR_NOCONV with rep->info_index = its global index. */
+adc_status adc_stedc(adc_ctx ctx, int64_t n, const double* diag, const double* offdiag,
+                     double* w, double* Z, int64_t ldz, void* ws, size_t ws_bytes,
+                     const adc_opts* opts, adc_report* rep);
+
+/* Many independent eigendecompositions (level-batched).  Blocking.
+ *   count                 : number of matrices
+ *   n[count]              : host array of sizes
+ *   diag, offdiag, w, Z   : host arrays of `count` device pointers
+ *   ldz[count]            : host array of leading dimensions
+ * Every DC level of every matrix runs as one launch per merge phase over a
+ * device work queue; with opts->force_dense = 1 (or all K < hss_min_k) the
+ * level sequence is captured once in a HIP graph keyed by the size set and
+ * replayed by later calls with the same sizes.  reps may be NULL (one report
+ * for the whole batch otherwise). */
+adc_status adc_stedc_batched(adc_ctx ctx, int32_t count, const int64_t* n,
+                             const double* const* diag, const double* const* offdiag,
+                             double* const* w, double* const* Z, const int64_t* ldz,
+                             const adc_opts* opts, adc_report* rep);
+
+/* ------------------------------------------- merge-step kernels (parity) */
+
+/* Secular roots of D + rho z z^T (Theorem 1), d strictly increasing,
+ * ||z|| = 1, rho > 0.  Outputs gam[i] = lam_i - d_i and mu[i] = d_{i+1} -
+ * lam_i (mu[K-1] = +inf), each taken from the iterate relative to the nearer
+ * pole (Remark 1; Section 4.3).  lam may be NULL.  Asynchronous. */
+adc_status adc_secular(adc_ctx ctx, int64_t K, const double* d, const double* z, double rho,
+                       double* lam, double* gam, double* mu);
+
+/* Loewner recompute (eq. ev_z): uh[i] = sign(z_i) sqrt(prod_j (lam_j - d_i) /
+ * (rho prod_{j!=i} (d_j - d_i))), every difference by eq. (d-lambda); and the
+ * column scales v[j] = 1/||(uh_i/(d_i - lam_j))_i|| of eq. (EVec).
+ * Asynchronous. */
+adc_status adc_lowner(adc_ctx ctx, int64_t K, const double* d, const double* z, double rho,
+                      const double* gam, const double* mu, double* uh, double* v);
+
+/* Dense Cauchy update (the plain DC update): Y[P x K] = X[P x K] * Q', with
+ * Q'_{ij} = uh_i v_j / (d_i - lam_j) (eq. Ev-Q, differences by eq. d-lambda),
+ * on the FP64 MFMA GEMM.  Y must not overlap X.  Asynchronous. */
+adc_status adc_cauchy_gemm(adc_ctx ctx, int64_t P, int64_t K, const double* d, const double* gam,
+                           const double* mu, const double* uh, const double* v,
+                           const double* X, int64_t ldx, double* Y, int64_t ldy);
+
+/* Randomized HSS approximation H ~ Q' (Algorithm 2) of the Cauchy-like matrix
+ * with generators (d, gam, mu, uh, v).  omega: K x s row-major Gaussian
+ * sampling matrix, or NULL to draw it (Philox4x32-10, opts->seed) with s from
+ * the rank estimate (s argument ignored).  The adaptive check (Gaussian
+ * probes; sample doubling up to max_retries) runs unless omega is given.
+ * Blocking.  *out is released by adc_hss_free. */
+adc_status adc_hss_build(adc_ctx ctx, int64_t K, const double* d, const double* gam,
+                         const double* mu, const double* uh, const double* v,
+                         const double* omega, int32_t s, const adc_opts* opts, adc_hss* out);
+
+/* Y[P x K] = X[P x K] * H (Algorithm 3, HSS times a general matrix from the
+ * right).  Y must not overlap X.  Asynchronous. */
+adc_status adc_hss_apply(adc_ctx ctx, adc_hss h, int64_t P, const double* X, int64_t ldx,
+                         double* Y, int64_t ldy);
+
+/* Host summary of an HSS matrix: levels below the root, leaves, max rank,
+ * samples used, retries, check error (any pointer may be NULL). */
+adc_status adc_hss_info(adc_hss h, int32_t* levels, int32_t* leaves, int32_t* max_rank,
+                        int32_t* samples, int32_t* retries, double* check_err);
+adc_status adc_hss_free(adc_hss h);
+
+/* -------------------------------------------- learned rank predictor (MLP) */
+
+/* The predictor is a 16-64-64-1 FP32 MLP with ReLU (weights owned by the
+ * context).  Features (16 per HSS block boundary) are produced by
+ * adc_mlp_features; targets are log2 of the ID rank observed at that boundary.
+ *
+ * adc_mlp_features: for the generators (d, gam, mu) of a merge of size K and
+ *   the leaf boundaries bounds[nb+2] (host, first 0, last K), writes the
+ *   feature matrix feat[nb x 16] (device, FP32, row-major).
+ * adc_mlp_init:  random init from `seed` (host call; weights on device).
+ * adc_mlp_train: `epochs` passes of Adam (lr, beta1 0.9, beta2 0.999, eps
+ *   1e-8) over B samples (X[B x 16], y[B], device FP32) in minibatches of
+ *   `batch`; *loss_out (host) receives the final-epoch mean squared error.
+ * adc_mlp_infer: y[B] = MLP(X[B x 16]).
+ * adc_mlp_grad:  loss and gradients of one minibatch, for checking
+ *   (g_out: device FP32 array of the 5377 parameters, layer order W1 b1 W2 b2
+ *   W3 b3, row-major W[out x in]).
+ * adc_mlp_get/set: copy the 5377 parameters to/from a device FP32 array. */
+adc_status adc_mlp_features(adc_ctx ctx, int64_t K, const double* d, const double* gam,
+                            const double* mu, const int64_t* bounds, int32_t nb, float* feat);
+adc_status adc_mlp_init(adc_ctx ctx, uint64_t seed);
+adc_status adc_mlp_train(adc_ctx ctx, int32_t B, const float* X, const float* y, int32_t epochs,
+                         int32_t batch, float lr, float* loss_out);
+adc_status adc_mlp_infer(adc_ctx ctx, int32_t B, const float* X, float* y);
+adc_status adc_mlp_grad(adc_ctx ctx, int32_t B, const float* X, const float* y, float* g_out,
+                        float* loss_out);
+adc_status adc_mlp_get(adc_ctx ctx, float* params);
+adc_status adc_mlp_set(adc_ctx ctx, const float* params);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADC_H */

@@ -1,0 +1,277 @@
+// Host driver of the ADC library: context, memory pool, the DC tree
+// (Algorithm 1) and the kernel-level entry points of the C ABI.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "adc_internal.hpp"
+
+// ---------------------------------------------------------------- status
+extern "C" const char* adc_status_string(adc_status s) {
+  switch (s) {
+    case ADC_OK: return "ADC_OK";
+    case ADC_ERR_ARG: return "ADC_ERR_ARG: invalid argument or non-finite input";
+    case ADC_ERR_NOMEM: return "ADC_ERR_NOMEM: device allocation failed";
+    case ADC_ERR_HIP: return "ADC_ERR_HIP: HIP runtime error";
+    case ADC_ERR_NOCONV: return "ADC_ERR_NOCONV: secular root did not converge";
+    case ADC_ERR_ACCURACY: return "ADC_ERR_ACCURACY: HSS accuracy check failed";
+    case ADC_ERR_UNSUPPORTED: return "ADC_ERR_UNSUPPORTED: size or option not supported";
+  }
+  return "ADC_UNKNOWN";
+}
+
+extern "C" adc_status adc_opts_default(adc_opts* o) {
+  if (!o) return ADC_ERR_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->dc_leaf = 32;
+  o->hss_min_k = 2048;
+  o->hss_levels = 3;
+  o->hss_leaf = 128;
+  o->id_tol = 1e-14;
+  o->oversample = 10;
+  o->rank_mode = ADC_RANK_BOUND;
+  o->fixed_rank = 0;
+  o->max_retries = 2;
+  o->max_iter = 60;
+  o->seed = 20151015ull;
+  o->force_dense = 0;
+  o->strict = 0;
+  o->check_tol = 1e-12;
+  o->nprobe = 4;
+  o->shift_max = 5;
+  o->shift_thresh = 1e-10;
+  o->r_cap = 100;
+  o->rank_eps = 1e-16;
+  return ADC_OK;
+}
+
+adc_status validate_opts_ext(const adc_opts& o) {
+  if (o.dc_leaf < 2 || o.dc_leaf > 64) return ADC_ERR_ARG;
+  if (o.hss_leaf < 16 || o.hss_leaf > 512) return ADC_ERR_ARG;
+  if (!(o.id_tol >= 0.0) || o.oversample < 0 || o.max_retries < 0 || o.max_iter < 1) return ADC_ERR_ARG;
+  if (o.nprobe < 1 || o.nprobe > 64 || o.r_cap < 1 || !(o.rank_eps > 0.0)) return ADC_ERR_ARG;
+  if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
+  return ADC_OK;
+}
+
+// ---------------------------------------------------------------- context
+extern "C" adc_status adc_create(adc_ctx* out, int device, void* stream) {
+  if (!out) return ADC_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  HIP_OK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return ADC_ERR_ARG;
+  adc_ctx c = new (std::nothrow) adc_ctx_s();
+  if (!c) return ADC_ERR_NOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_destroy(adc_ctx c) {
+  if (!c) return ADC_ERR_ARG;
+  DeviceGuard g(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  c->release();
+  delete c;
+  return ADC_OK;
+}
+
+void adc_ctx_s::release() {
+  for (auto& b : bufs) {
+    if (b.ptr) hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  if (host_stage) hipHostFree(host_stage);
+  host_stage = nullptr;
+  host_stage_bytes = 0;
+  mlp_release(this);
+}
+
+adc_status adc_ctx_s::buffer(int slot, size_t bytes, void** p) {
+  if (slot < 0 || slot >= NSLOT) return ADC_ERR_ARG;
+  Buf& b = bufs[slot];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      hipStreamSynchronize(stream);
+      hipFree(b.ptr);
+    }
+    b.ptr = nullptr;
+    b.bytes = 0;
+    size_t want = std::max(bytes, (size_t)256);
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+      b.ptr = nullptr;
+      return ADC_ERR_NOMEM;
+    }
+    b.bytes = want;
+  }
+  *p = b.ptr;
+  return ADC_OK;
+}
+
+adc_status adc_ctx_s::stage(size_t bytes, void** p) {
+  if (host_stage_bytes < bytes) {
+    if (host_stage) {
+      hipStreamSynchronize(stream);
+      hipHostFree(host_stage);
+    }
+    host_stage = nullptr;
+    host_stage_bytes = 0;
+    size_t want = std::max(bytes, (size_t)(1 << 20));
+    if (hipHostMalloc(&host_stage, want, hipHostMallocDefault) != hipSuccess) return ADC_ERR_NOMEM;
+    host_stage_bytes = want;
+  }
+  *p = host_stage;
+  return ADC_OK;
+}
+
+// ---------------------------------------------------------------- helpers
+adc_status check_finite(adc_ctx c, const double* x, int64_t n, bool* ok) {
+  int* flag;
+  ADC_TRY(c->buffer(SLOT_FLAG, 64, (void**)&flag));
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c->stream, flag, 0);
+  if (n > 0) {
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks), dim3(256), 0, c->stream, x, n, flag);
+    HIP_OK(hipGetLastError());
+  }
+  int h = 0;
+  HIP_OK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  *ok = (h == 0);
+  return ADC_OK;
+}
+
+int pick_waves(int64_t K) {
+  if (K <= 128) return 1;
+  if (K <= 1024) return 4;
+  if (K <= 4096) return 8;
+  return 16;
+}
+
+// ---------------------------------------------------------------- kernel-level entries
+extern "C" adc_status adc_secular(adc_ctx c, int64_t K, const double* d, const double* z, double rho,
+                                  double* lam, double* gam, double* mu) {
+  if (!c || K < 0 || K > (int64_t)INT32_MAX / 2) return ADC_ERR_ARG;
+  if (K == 0) return ADC_OK;
+  if (!d || !z || !gam || !mu || !(rho > 0.0) || !std::isfinite(rho)) return ADC_ERR_ARG;
+  DeviceGuard g(c->device);
+  MergeDev md{};
+  md.s0 = 0;
+  md.gbase = 0;
+  md.n = (int32_t)K;
+  md.K = (int32_t)K;
+  md.rho = rho;
+  std::vector<RootBlock> rbs;
+  for (int64_t i0 = 0; i0 < K; i0 += 64) rbs.push_back(RootBlock{0, (int32_t)i0});
+  void* dev;
+  const size_t need = sizeof(MergeDev) + rbs.size() * sizeof(RootBlock) + 64;
+  ADC_TRY(c->buffer(SLOT_DESC, need, &dev));
+  MergeDev* dm = (MergeDev*)dev;
+  RootBlock* drb = (RootBlock*)((char*)dev + sizeof(MergeDev));
+  HIP_OK(hipMemcpyAsync(dm, &md, sizeof(md), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipMemcpyAsync(drb, rbs.data(), rbs.size() * sizeof(RootBlock), hipMemcpyHostToDevice, c->stream));
+  int* noconv;
+  ADC_TRY(c->buffer(SLOT_FLAG, 64, (void**)&noconv));
+  const int W = pick_waves(K);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c->stream, noconv, INT32_MAX);
+  hipLaunchKernelGGL(k_secular, dim3((unsigned)rbs.size()), dim3(64 * W), 0, c->stream, dm, drb, d, z, lam, gam, mu,
+                     60, noconv);
+  HIP_OK(hipGetLastError());
+  // the host-side structures above were copied from stack memory: wait
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_lowner(adc_ctx c, int64_t K, const double* d, const double* z, double rho,
+                                 const double* gam, const double* mu, double* uh, double* v) {
+  if (!c || K < 0 || K > (int64_t)INT32_MAX / 2) return ADC_ERR_ARG;
+  if (K == 0) return ADC_OK;
+  if (!d || !z || !gam || !mu || !uh || !(rho > 0.0)) return ADC_ERR_ARG;
+  DeviceGuard g(c->device);
+  MergeDev md{};
+  md.n = (int32_t)K;
+  md.K = (int32_t)K;
+  md.rho = rho;
+  std::vector<RootBlock> rbs;
+  for (int64_t i0 = 0; i0 < K; i0 += 64) rbs.push_back(RootBlock{0, (int32_t)i0});
+  void* dev;
+  ADC_TRY(c->buffer(SLOT_DESC, sizeof(MergeDev) + rbs.size() * sizeof(RootBlock) + 64, &dev));
+  MergeDev* dm = (MergeDev*)dev;
+  RootBlock* drb = (RootBlock*)((char*)dev + sizeof(MergeDev));
+  HIP_OK(hipMemcpyAsync(dm, &md, sizeof(md), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipMemcpyAsync(drb, rbs.data(), rbs.size() * sizeof(RootBlock), hipMemcpyHostToDevice, c->stream));
+  const int W = pick_waves(K);
+  hipLaunchKernelGGL(k_lowner, dim3((unsigned)rbs.size()), dim3(64 * W), 0, c->stream, dm, drb, d, z, gam, mu, uh);
+  if (v)
+    hipLaunchKernelGGL(k_vnorm, dim3((unsigned)rbs.size()), dim3(64 * W), 0, c->stream, dm, drb, d, gam, mu, uh, v);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_cauchy_gemm(adc_ctx c, int64_t P, int64_t K, const double* d, const double* gam,
+                                      const double* mu, const double* uh, const double* v, const double* X,
+                                      int64_t ldx, double* Y, int64_t ldy) {
+  if (!c || P < 0 || K < 0 || K > 65536 || P > (int64_t)INT32_MAX) return ADC_ERR_ARG;
+  if (P == 0 || K == 0) return ADC_OK;
+  if (!d || !gam || !mu || !uh || !v || !X || !Y || ldx < P || ldy < P) return ADC_ERR_ARG;
+  DeviceGuard g(c->device);
+  double* qc;
+  ADC_TRY(c->buffer(SLOT_QC, (size_t)K * K * sizeof(double), (void**)&qc));
+  MergeDev md{};
+  md.n = (int32_t)K;
+  md.K = (int32_t)K;
+  md.zoff = 0;
+  LevelBufs B{};
+  B.dS = const_cast<double*>(d);
+  B.gam = const_cast<double*>(gam);
+  B.mu = const_cast<double*>(mu);
+  B.uh = const_cast<double*>(uh);
+  B.qc = qc;
+  const int ncols = 8;
+  std::vector<int32_t> tm, tc;
+  for (int64_t j0 = 0; j0 < K; j0 += ncols) {
+    tm.push_back(0);
+    tc.push_back((int32_t)j0);
+  }
+  GemmProb gp{};
+  gp.A = X;
+  gp.B = qc;
+  gp.C = Y;
+  gp.colmap = nullptr;
+  gp.vscale = v;
+  gp.lda = ldx;
+  gp.ldb = K;
+  gp.ldc = ldy;
+  gp.M = (int32_t)P;
+  gp.N = (int32_t)K;
+  gp.K = (int32_t)K;
+  gp.tile0 = 0;
+  gp.tiles_m = (int32_t)((P + 127) / 128);
+  const int tiles = gp.tiles_m * (int)((K + 127) / 128);
+  void* dev;
+  const size_t need = sizeof(MergeDev) + sizeof(GemmProb) + 2 * tm.size() * sizeof(int32_t) + 256;
+  ADC_TRY(c->buffer(SLOT_DESC, need, &dev));
+  char* p = (char*)dev;
+  MergeDev* dm = (MergeDev*)p;
+  p += sizeof(MergeDev);
+  GemmProb* dg = (GemmProb*)p;
+  p += sizeof(GemmProb);
+  int32_t* dtm = (int32_t*)p;
+  int32_t* dtc = dtm + tm.size();
+  HIP_OK(hipMemcpyAsync(dm, &md, sizeof(md), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipMemcpyAsync(dg, &gp, sizeof(gp), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipMemcpyAsync(dtm, tm.data(), tm.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipMemcpyAsync(dtc, tc.data(), tc.size() * 4, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_cauchy, dim3((unsigned)tm.size()), dim3(256), 0, c->stream, dm, dtm, dtc, B, ncols, 0);
+  hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, c->stream, dg, 1);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return ADC_OK;
+}

@@ -1,0 +1,50 @@
+// Shared device/host definitions of the gfx950 ADC library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "adc.h"
+
+#define ADC_EPS 2.220446049250313e-16
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- host side
+#define HIP_OK(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return ADC_ERR_HIP;         \
+  } while (0)
+
+#define ADC_TRY(expr)                                 \
+  do {                                                \
+    adc_status _s = (expr);                           \
+    if (_s != ADC_OK) return _s;                      \
+  } while (0)
+
+// ---------------------------------------------------------------- device side
+
+// d_i - lam_j by the accurate differences of Remark 1 (eq. d-lambda):
+//   (d_i - d_j) - gam_j       for i <= j
+//   (d_i - d_{j+1}) + mu_j    for i >  j
+// dj1 is d_{j+1} (unused when i <= j).
+__device__ __forceinline__ double d_minus_lam(int i, int j, double di, double dj, double dj1,
+                                              double gj, double mj) {
+  return (i <= j) ? ((di - dj) - gj) : ((di - dj1) + mj);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum_i(int x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}

@@ -1,0 +1,415 @@
+// The divide-and-conquer tree of Algorithm 1 on one GPU.
+//
+// Tree: balanced binary splits k = floor(n/2) down to leaves of size <=
+// dc_leaf.  All tears are applied to the diagonal at once (eq. T2: every
+// split at k removes |b_k| from a_k and a_{k+1}); the leaves are solved in
+// one launch; the merges of one tree depth form a "level" whose phases each
+// run as one launch over all merges of the level.  Results of depth t live in
+// buffer t mod 2 (depth 0 = the caller's Z), so that the children of a merge
+// are read from one buffer while the merged block is written to the other.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "adc_internal.hpp"
+#include "hss.hpp"
+
+__global__ void k_check_finite(const double* __restrict__ x, int64_t n, int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+// a_i = diag_i - |b_i| [i is a split] - |b_{i-1}| [i-1 is a split]
+__global__ void k_tear(const double* __restrict__ diag, const double* __restrict__ off,
+                       const int64_t* __restrict__ splits, int nsplit, double* __restrict__ a, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  auto has = [&](int64_t k) {
+    int lo = 0, hi = nsplit;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (splits[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo < nsplit && splits[lo] == k;
+  };
+  double x = diag[i];
+  if (has(i)) x -= fabs(off[i]);
+  if (i > 0 && has(i - 1)) x -= fabs(off[i - 1]);
+  a[i] = x;
+}
+
+namespace {
+
+struct Node {
+  int64_t s0;
+  int32_t n;
+};
+
+struct Plan {
+  int64_t N = 0;
+  int leaf = 32;
+  std::vector<std::vector<Node>> merge_levels;  // depth t -> merges (n > leaf)
+  std::vector<int64_t> leaf_s0;
+  std::vector<int32_t> leaf_m;
+  std::vector<int32_t> leaf_depth;
+  std::vector<int64_t> splits;
+};
+
+Plan make_plan(int64_t N, int leaf) {
+  Plan p;
+  p.N = N;
+  p.leaf = leaf;
+  std::vector<Node> cur{{0, (int32_t)N}};
+  int depth = 0;
+  while (!cur.empty()) {
+    std::vector<Node> nxt, merges;
+    for (const Node& nd : cur) {
+      if (nd.n > leaf) {
+        merges.push_back(nd);
+        const int32_t h = nd.n / 2;
+        p.splits.push_back(nd.s0 + h - 1);
+        nxt.push_back({nd.s0, h});
+        nxt.push_back({nd.s0 + h, nd.n - h});
+      } else {
+        p.leaf_s0.push_back(nd.s0);
+        p.leaf_m.push_back(nd.n);
+        p.leaf_depth.push_back(depth);
+      }
+    }
+    if (!merges.empty()) p.merge_levels.push_back(merges);
+    cur.swap(nxt);
+    ++depth;
+  }
+  std::sort(p.splits.begin(), p.splits.end());
+  return p;
+}
+
+struct WsLayout {
+  double *a, *win, *Zb;
+  double *dsort, *zsort, *dS, *zS, *lam, *gam, *mu, *uh, *v, *rot_c, *rot_s;
+  int32_t *src, *supp, *surv, *defl, *gorder, *rot_i, *rot_j, *rot_f, *posR, *posD, *colmerge;
+  double *pk, *qc;
+  int* noconv;
+  size_t bytes;
+};
+
+WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
+  Arena ar{base, 0, 0};
+  WsLayout L{};
+  L.a = ar.take<double>(N);
+  L.win = ar.take<double>(N);
+  L.dsort = ar.take<double>(N);
+  L.zsort = ar.take<double>(N);
+  L.dS = ar.take<double>(N);
+  L.zS = ar.take<double>(N);
+  L.lam = ar.take<double>(N);
+  L.gam = ar.take<double>(N);
+  L.mu = ar.take<double>(N);
+  L.uh = ar.take<double>(N);
+  L.v = ar.take<double>(N);
+  L.rot_c = ar.take<double>(N);
+  L.rot_s = ar.take<double>(N);
+  L.src = ar.take<int32_t>(N);
+  L.supp = ar.take<int32_t>(N);
+  L.surv = ar.take<int32_t>(N);
+  L.defl = ar.take<int32_t>(N);
+  L.gorder = ar.take<int32_t>(N);
+  L.rot_i = ar.take<int32_t>(N);
+  L.rot_j = ar.take<int32_t>(N);
+  L.rot_f = ar.take<int32_t>(N);
+  L.posR = ar.take<int32_t>(N);
+  L.posD = ar.take<int32_t>(N);
+  L.colmerge = ar.take<int32_t>(N);
+  L.noconv = ar.take<int>(64);
+  L.Zb = need_zb ? ar.take<double>((size_t)N * N) : nullptr;
+  L.pk = ar.take<double>((size_t)N * N);
+  L.qc = ar.take<double>((size_t)N * N);
+  L.bytes = ar.off + 256;
+  return L;
+}
+
+}  // namespace
+
+extern "C" adc_status adc_workspace_query(adc_ctx c, int64_t n, const adc_opts* opts, size_t* bytes) {
+  if (!c || n < 0 || !bytes) return ADC_ERR_ARG;
+  (void)opts;
+  *bytes = layout_ws(nullptr, std::max<int64_t>(n, 1), true).bytes;
+  return ADC_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const double* offdiag, double* w,
+                                double* Z, int64_t ldz, void* ws, size_t ws_bytes, const adc_opts* opts_in,
+                                adc_report* rep) {
+  if (!c || n < 0) return ADC_ERR_ARG;
+  if (n == 0) return ADC_OK;
+  if (!diag || !w || !Z || ldz < n || (n > 1 && !offdiag)) return ADC_ERR_ARG;
+  if (n > 1000000) return ADC_ERR_UNSUPPORTED;
+  adc_opts o;
+  if (opts_in) o = *opts_in;
+  else adc_opts_default(&o);
+  ADC_TRY(validate_opts_ext(o));
+  DeviceGuard g(c->device);
+  const auto t_start = std::chrono::steady_clock::now();
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->info_index = -1;
+  }
+  bool ok = true;
+  ADC_TRY(check_finite(c, diag, n, &ok));
+  if (!ok) return ADC_ERR_ARG;
+  if (n > 1) {
+    ADC_TRY(check_finite(c, offdiag, n - 1, &ok));
+    if (!ok) return ADC_ERR_ARG;
+  }
+
+  const Plan plan = make_plan(n, o.dc_leaf);
+  const int nlev = (int)plan.merge_levels.size();
+  const bool need_zb = nlev > 0;
+  const size_t need = layout_ws(nullptr, n, need_zb).bytes;
+  char* base;
+  if (ws) {
+    if (ws_bytes < need) return ADC_ERR_ARG;
+    base = (char*)ws;
+  } else {
+    ADC_TRY(c->buffer(SLOT_WS, need, (void**)&base));
+  }
+  WsLayout L = layout_ws(base, n, need_zb);
+  hipStream_t st = c->stream;
+
+  // --- host staging for descriptors
+  const int64_t nleaf = (int64_t)plan.leaf_s0.size();
+  size_t max_merges = 1;
+  for (auto& lv : plan.merge_levels) max_merges = std::max(max_merges, lv.size());
+  const size_t blocks64 = (size_t)(n / 64 + 2 * max_merges + 8);
+  const size_t desc_bytes = 4096 + nleaf * 16 + plan.splits.size() * 8 + max_merges * sizeof(MergeDev) +
+                            3 * blocks64 * sizeof(RootBlock) + 2 * max_merges * sizeof(GemmProb) +
+                            (size_t)n * 8 + 2 * ((size_t)n / 8 + max_merges + 8) * 4 + 32 * 256;
+  char* hs;
+  ADC_TRY(c->stage(desc_bytes * 2, (void**)&hs));
+  char* dd;
+  ADC_TRY(c->buffer(SLOT_DESC, desc_bytes, (void**)&dd));
+
+  // --- tear all splits and solve the leaves
+  {
+    Arena ha{hs, 0, 0}, da{dd, 0, 0};
+    int64_t* h_sp = ha.take<int64_t>(plan.splits.size() + 1);
+    int64_t* d_sp = da.take<int64_t>(plan.splits.size() + 1);
+    int64_t* h_ls = ha.take<int64_t>(nleaf);
+    int64_t* d_ls = da.take<int64_t>(nleaf);
+    int32_t* h_lm = ha.take<int32_t>(nleaf);
+    int32_t* d_lm = da.take<int32_t>(nleaf);
+    if (!plan.splits.empty()) std::memcpy(h_sp, plan.splits.data(), plan.splits.size() * 8);
+    // leaves grouped by the buffer they go to (depth parity)
+    std::vector<int64_t> ls[2];
+    std::vector<int32_t> lm[2];
+    for (int64_t i = 0; i < nleaf; ++i) {
+      const int par = plan.leaf_depth[i] & 1;
+      ls[par].push_back(plan.leaf_s0[i]);
+      lm[par].push_back(plan.leaf_m[i]);
+    }
+    const size_t n0 = ls[0].size();
+    std::memcpy(h_ls, ls[0].data(), n0 * 8);
+    std::memcpy(h_ls + n0, ls[1].data(), ls[1].size() * 8);
+    std::memcpy(h_lm, lm[0].data(), n0 * 4);
+    std::memcpy(h_lm + n0, lm[1].data(), lm[1].size() * 4);
+    HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_tear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag, offdiag, d_sp,
+                       (int)plan.splits.size(), L.a, n);
+    if (n0)
+      hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)n0), dim3(256), 0, st, L.a, offdiag, d_ls, d_lm, w, Z, ldz,
+                         40);
+    if (ls[1].size())
+      hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)ls[1].size()), dim3(256), 0, st, L.a, offdiag, d_ls + n0,
+                         d_lm + n0, w, L.Zb, (int64_t)n, 40);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, L.noconv, INT32_MAX);
+    HIP_OK(hipStreamSynchronize(st));  // staging buffer is reused below
+  }
+
+  if (rep) rep->levels = nlev;
+  double flops = 0.0, bytes = 0.0;
+
+  // --- merge levels, deepest first
+  for (int t = nlev - 1; t >= 0; --t) {
+    const std::vector<Node>& lev = plan.merge_levels[t];
+    const int nm = (int)lev.size();
+    LevelBufs B{};
+    B.w_in = L.win;
+    B.w_out = w;
+    B.off = offdiag;
+    const bool out_user = (t % 2) == 0;
+    B.Znew = out_user ? Z : L.Zb;
+    B.ldn = out_user ? ldz : n;
+    B.Zold = out_user ? L.Zb : Z;
+    B.ldo = out_user ? n : ldz;
+    B.dsort = L.dsort;
+    B.zsort = L.zsort;
+    B.src = L.src;
+    B.supp = L.supp;
+    B.surv = L.surv;
+    B.defl = L.defl;
+    B.gorder = L.gorder;
+    B.rot_i = L.rot_i;
+    B.rot_j = L.rot_j;
+    B.rot_f = L.rot_f;
+    B.rot_c = L.rot_c;
+    B.rot_s = L.rot_s;
+    B.dS = L.dS;
+    B.zS = L.zS;
+    B.lam = L.lam;
+    B.gam = L.gam;
+    B.mu = L.mu;
+    B.uh = L.uh;
+    B.v = L.v;
+    B.posR = L.posR;
+    B.posD = L.posD;
+    B.pk = L.pk;
+    B.qc = L.qc;
+
+    Arena ha{hs, 0, 0}, da{dd, 0, 0};
+    MergeDev* h_m = ha.take<MergeDev>(nm);
+    MergeDev* d_m = da.take<MergeDev>(nm);
+    int32_t nmax = 0;
+    for (int g2 = 0; g2 < nm; ++g2) {
+      MergeDev& M = h_m[g2];
+      std::memset(&M, 0, sizeof(M));
+      M.s0 = lev[g2].s0;
+      M.gbase = lev[g2].s0;
+      M.n = lev[g2].n;
+      M.n1 = lev[g2].n / 2;
+      nmax = std::max(nmax, M.n);
+    }
+    HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(d_m, h_m, nm * sizeof(MergeDev), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(h_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+
+    // --- host decisions and launch lists
+    int64_t Kmax = 0, Ksum = 0, nsum = 0;
+    int hss_here = 0;
+    for (int g2 = 0; g2 < nm; ++g2) {
+      MergeDev& M = h_m[g2];
+      M.zoff = M.s0 * (int64_t)nmax;
+      const bool level_ok = (o.hss_levels < 0) || (t < o.hss_levels);
+      M.mode = (!o.force_dense && level_ok && M.K >= o.hss_min_k) ? 1 : 0;
+      hss_here += M.mode == 1;
+      Kmax = std::max<int64_t>(Kmax, M.K);
+      Ksum += M.K;
+      nsum += M.n;
+    }
+    RootBlock* h_rb = ha.take<RootBlock>(blocks64);
+    RootBlock* d_rb = da.take<RootBlock>(blocks64);
+    int nrb = 0;
+    for (int g2 = 0; g2 < nm; ++g2)
+      for (int i0 = 0; i0 < h_m[g2].K; i0 += 64) h_rb[nrb++] = RootBlock{g2, i0};
+    RootBlock* h_ob = ha.take<RootBlock>(blocks64);
+    RootBlock* d_ob = da.take<RootBlock>(blocks64);
+    int nob = 0;
+    for (int g2 = 0; g2 < nm; ++g2)
+      for (int i0 = 0; i0 < h_m[g2].n; i0 += 256) h_ob[nob++] = RootBlock{g2, i0};
+    int32_t* h_cm = ha.take<int32_t>(n);
+    int32_t* d_cm = da.take<int32_t>(n);
+    int32_t* h_cc = ha.take<int32_t>(n);
+    int32_t* d_cc = da.take<int32_t>(n);
+    int njob = 0;
+    for (int g2 = 0; g2 < nm; ++g2)
+      for (int c2 = 0; c2 < h_m[g2].n; ++c2) {
+        h_cm[njob] = g2;
+        h_cc[njob] = c2;
+        ++njob;
+      }
+    const int ncols = 8;
+    const size_t maxtiles = (size_t)n / 8 + max_merges + 8;
+    int32_t* h_tm = ha.take<int32_t>(maxtiles);
+    int32_t* d_tm = da.take<int32_t>(maxtiles);
+    int32_t* h_tc = ha.take<int32_t>(maxtiles);
+    int32_t* d_tc = da.take<int32_t>(maxtiles);
+    int ntile = 0;
+    GemmProb* h_gp = ha.take<GemmProb>(2 * nm);
+    GemmProb* d_gp = da.take<GemmProb>(2 * nm);
+    int ngp = 0, gtiles = 0;
+    for (int g2 = 0; g2 < nm; ++g2) {
+      const MergeDev& M = h_m[g2];
+      if (M.K == 0 || M.mode != 0) continue;
+      for (int j0 = 0; j0 < M.K; j0 += ncols) {
+        h_tm[ntile] = g2;
+        h_tc[ntile] = j0;
+        ++ntile;
+      }
+      const int n2 = M.n - M.n1;
+      for (int half = 0; half < 2; ++half) {
+        GemmProb& P = h_gp[ngp];
+        std::memset(&P, 0, sizeof(P));
+        P.M = half ? n2 : M.n1;
+        P.N = M.K;
+        P.K = half ? (M.k2 + M.k3) : (M.k1 + M.k2);
+        P.A = L.pk + M.zoff + (half ? (M.n1 + (int64_t)M.k1 * M.n) : 0);
+        P.lda = M.n;
+        P.B = L.qc + M.zoff + (half ? M.k1 : 0);
+        P.ldb = M.K;
+        P.C = B.Znew + (M.s0 + (half ? M.n1 : 0)) + M.s0 * B.ldn;
+        P.ldc = B.ldn;
+        P.colmap = L.posR + M.s0;
+        P.vscale = L.v + M.s0;
+        P.tiles_m = (P.M + 127) / 128;
+        P.tile0 = gtiles;
+        gtiles += P.tiles_m * ((P.N + 127) / 128);
+        ++ngp;
+        flops += 2.0 * P.M * (double)P.N * P.K;
+        bytes += 8.0 * ((double)P.M * P.K + (double)P.K * P.N + (double)P.M * P.N);
+      }
+    }
+    HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
+
+    // --- secular, Loewner, v
+    const int W = pick_waves(Kmax);
+    if (nrb) {
+      hipLaunchKernelGGL(k_secular, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.lam, L.gam, L.mu,
+                         o.max_iter, L.noconv);
+      hipLaunchKernelGGL(k_lowner, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.gam, L.mu, L.uh);
+      hipLaunchKernelGGL(k_vnorm, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.gam, L.mu, L.uh, L.v);
+    }
+    hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
+    hipLaunchKernelGGL(k_rotate, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B, 0);
+    HIP_OK(hipGetLastError());
+    if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, ncols, 1);
+    if (gtiles) hipLaunchKernelGGL(k_gemm_f64, dim3(gtiles), dim3(256), 0, st, d_gp, ngp);
+    HIP_OK(hipGetLastError());
+    if (hss_here) {
+      ADC_TRY(hss_level_update(c, o, h_m, d_m, nm, B, t, rep, &flops, &bytes));
+    }
+    HIP_OK(hipStreamSynchronize(st));  // staging buffer reused by the next level
+
+    if (rep && t < 64) {
+      rep->n_per_level[t] = nsum;
+      rep->K_per_level[t] = Ksum;
+      rep->hss_per_level[t] = hss_here;
+      rep->merges += nm;
+      rep->hss_merges += hss_here;
+    }
+  }
+
+  int nc = INT32_MAX;
+  HIP_OK(hipMemcpyAsync(&nc, L.noconv, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (rep) {
+    rep->flops_model += flops;
+    rep->bytes_model += bytes;
+    rep->t_phase[10] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (nc != INT32_MAX) {
+    if (rep) rep->info_index = nc;
+    return ADC_ERR_NOCONV;
+  }
+  return ADC_OK;
+}

@@ -1,0 +1,108 @@
+// Device-side descriptors and kernel declarations of the ADC library.
+#pragma once
+#include "common.hpp"
+
+// One merge of the DC tree (Algorithm 1).  Every per-merge vector lives at
+// offset s0 of an N-long array, because the merges of one level partition
+// [0, N).  Fields below "prep" are written by k_merge_prep.
+struct MergeDev {
+  int64_t s0;      // first row/column of the merge block (global)
+  int64_t gbase;   // global index base used in error reports
+  int64_t zoff;    // element offset of this merge's packed / Cauchy buffers
+  int32_t n, n1;   // merge size and size of the first child
+  double beta;     // off-diagonal entry b_k at the tear (eq. T2)
+  // prep
+  int32_t K;       // survivors of deflation (secular size)
+  int32_t nrot;    // Givens rotations of type-2 deflation
+  int32_t k1, k2, k3;  // survivors whose column lives in rows: top only, both, bottom only
+  int32_t mode;    // 0 dense update, 1 HSS update (host decision)
+  double rho;      // rho after normalising z
+  double tol;      // deflation tolerance
+};
+
+// 64 consecutive roots (columns) of one merge.
+struct RootBlock {
+  int32_t merge;
+  int32_t i0;
+};
+
+// One product C(:, colmap[j]) = v_j * (A * B)(:, j) of the dense update.
+struct GemmProb {
+  const double* A;
+  const double* B;
+  double* C;
+  const int32_t* colmap;  // may be null (identity)
+  const double* vscale;   // may be null (1)
+  int64_t lda, ldb, ldc;
+  int32_t M, N, K;
+  int32_t tile0;          // first flat tile index of this problem
+  int32_t tiles_m;        // tiles along M
+};
+
+// Per-level scratch pointers shared by the merge kernels.
+struct LevelBufs {
+  const double* w_in;   // children's eigenvalues (copy of w)
+  double* w_out;        // merged eigenvalues
+  const double* off;    // off-diagonal of T (b_k of every tear)
+  double* Zold;         // eigenvectors of the children (block diagonal)
+  double* Znew;         // merged eigenvectors
+  int64_t ldo, ldn;     // leading dimensions of Zold and Znew
+  double* dsort;        // d after merging the two runs (and rotation updates)
+  double* zsort;        // z likewise
+  int32_t* src;         // sorted position -> block-local source column
+  int32_t* supp;        // sorted position -> row support (1 top, 2 bottom, 3 both)
+  int32_t* surv;        // survivor r -> sorted position
+  int32_t* defl;        // deflated q -> sorted position
+  int32_t* gorder;      // grouped order (dense GEMM) -> survivor r
+  int32_t* rot_i;       // rotation t -> sorted positions (i, j)
+  int32_t* rot_j;
+  int32_t* rot_f;       // supports of i and j before the rotation: fi | fj << 2
+  double* rot_c;
+  double* rot_s;
+  double* dS;           // survivor poles d'
+  double* zS;           // survivor weights z'
+  double* lam;          // roots
+  double* gam;          // lam_i - d_i
+  double* mu;           // d_{i+1} - lam_i
+  double* uh;           // Loewner vector
+  double* v;            // column scales
+  int32_t* posR;        // survivor r -> final position in the block
+  int32_t* posD;        // deflated q -> final position in the block
+  double* pk;           // packed survivor columns of U
+  double* qc;           // materialised Cauchy matrix (dense update)
+};
+
+// ---- kernels
+__global__ void k_leaf_jacobi(const double* __restrict__ a, const double* __restrict__ b,
+                              const int64_t* __restrict__ leaf_s0, const int32_t* __restrict__ leaf_m,
+                              double* __restrict__ w, double* __restrict__ Z, int64_t ldz, int max_sweeps);
+
+__global__ void k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B);
+
+__global__ void k_secular(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,
+                          const double* __restrict__ dS, const double* __restrict__ zS,
+                          double* __restrict__ lamS, double* __restrict__ gamS, double* __restrict__ muS,
+                          int max_iter, int* __restrict__ noconv);
+
+__global__ void k_lowner(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,
+                         const double* __restrict__ dS, const double* __restrict__ zS,
+                         const double* __restrict__ gamS, const double* __restrict__ muS,
+                         double* __restrict__ uhS);
+
+__global__ void k_vnorm(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,
+                        const double* __restrict__ dS, const double* __restrict__ gamS,
+                        const double* __restrict__ muS, const double* __restrict__ uhS,
+                        double* __restrict__ vS);
+
+__global__ void k_final_order(const MergeDev* __restrict__ merges, LevelBufs B,
+                              const RootBlock* __restrict__ blocks);
+
+__global__ void k_rotate(const MergeDev* __restrict__ merges, LevelBufs B, const RootBlock* __restrict__ blocks);
+
+__global__ void k_pack(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
+                       const int32_t* __restrict__ col_idx, LevelBufs B, int sorted_pack);
+
+__global__ void k_cauchy(const MergeDev* __restrict__ merges, const int32_t* __restrict__ tile_merge,
+                         const int32_t* __restrict__ tile_col0, LevelBufs B, int ncols, int grouped);
+
+__global__ void k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs);

@@ -1,0 +1,333 @@
+// Merge-step kernels around the secular solve (Algorithm 1, "form M = D +
+// b_k u u^T", deflation, and the assembly of the merged eigenpairs).
+//
+// k_merge_prep   eq. (T3): z = [last row of Q1; first row of Q2] (second half
+//                negated when b_k < 0), rho = |b_k| ||z||^2, z normalised;
+//                stable merge of the two sorted child spectra; deflation with
+//                tol = 8 eps max(max|d|, rho max|z|): type 1 when |rho z_j| <=
+//                tol, type 2 (a Givens rotation of two columns) when the
+//                coupling |(d_j - d_i) c s| <= tol.  The scan is sequential
+//                in the pole order and runs on one lane per merge.
+// k_final_order  merged eigenvalues in ascending order (roots before
+//                deflated values on ties, deflated values in scan order).
+// k_rotate       applies the type-2 rotations to the eigenvector columns in
+//                place; the rows outside a column's support are implicit
+//                zeros of the block-diagonal diag(Q1, Q2).
+// k_pack         survivor columns into a dense n x K operand; deflated
+//                columns straight to their final place.
+// k_cauchy       the Cauchy-like matrix uh_i/(d_i - lam_j) (eq. Ev-Q without
+//                the column scale v, which the GEMM applies), differences by
+//                eq. (d-lambda).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+__device__ __forceinline__ int lower_bound_d(const double* __restrict__ x, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int upper_bound_d(const double* __restrict__ x, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, typename Op>
+__device__ T block_reduce(T x, T* sh, Op op) {
+  const int tid = threadIdx.x;
+  sh[tid] = x;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (tid < st) sh[tid] = op(sh[tid], sh[tid + st]);
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+struct OpAdd {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMax {
+  __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B) {
+  __shared__ double sh[1024];
+  MergeDev& M = merges[blockIdx.x];
+  const int64_t s0 = M.s0;
+  const int n = M.n, n1 = M.n1, n2 = n - n1;
+  const double beta = B.off[s0 + n1 - 1];
+  const double sg = (beta >= 0.0) ? 1.0 : -1.0;
+  const int tid = threadIdx.x;
+  const double* __restrict__ win = B.w_in + s0;
+  const double* __restrict__ d1 = win;
+  const double* __restrict__ d2 = win + n1;
+  const int64_t ldz = B.ldo;
+
+  // ||u||^2 with u = [last row of Q1; +-first row of Q2]
+  double ss = 0.0;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double u = (j < n1) ? B.Zold[(s0 + n1 - 1) + (s0 + j) * ldz] : sg * B.Zold[(s0 + n1) + (s0 + j) * ldz];
+    ss += u * u;
+  }
+  const double nu2 = block_reduce(ss, sh, OpAdd());
+  const double rho = fabs(beta) * nu2;
+  const double inv = (nu2 > 0.0) ? 1.0 / sqrt(nu2) : 0.0;
+
+  double md = 0.0, mz = 0.0;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const double u = (j < n1) ? B.Zold[(s0 + n1 - 1) + (s0 + j) * ldz] : sg * B.Zold[(s0 + n1) + (s0 + j) * ldz];
+    const double dj = win[j];
+    int pos;
+    if (j < n1) pos = j + lower_bound_d(d2, n2, dj);
+    else pos = (j - n1) + upper_bound_d(d1, n1, dj);
+    const double zj = u * inv;
+    B.dsort[s0 + pos] = dj;
+    B.zsort[s0 + pos] = zj;
+    B.src[s0 + pos] = j;
+    B.supp[s0 + pos] = (j < n1) ? 1 : 2;
+    md = fmax(md, fabs(dj));
+    mz = fmax(mz, fabs(zj));
+  }
+  md = block_reduce(md, sh, OpMax());
+  mz = block_reduce(mz, sh, OpMax());
+  const double tol = 8.0 * ADC_EPS * fmax(md, rho * mz);
+  __syncthreads();
+
+  if (tid == 0) {
+    double* __restrict__ ds = B.dsort + s0;
+    double* __restrict__ zs = B.zsort + s0;
+    int32_t* __restrict__ sp = B.supp + s0;
+    int32_t* __restrict__ surv = B.surv + s0;
+    int32_t* __restrict__ defl = B.defl + s0;
+    double* __restrict__ dS = B.dS + s0;
+    double* __restrict__ zS = B.zS + s0;
+    int K = 0, nd = 0, nrot = 0, prev = -1;
+    double pd = 0.0, pz = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double zj = zs[j];
+      const double dj = ds[j];
+      if (rho * fabs(zj) <= tol) {
+        defl[nd++] = j;
+        continue;
+      }
+      if (prev < 0) {
+        prev = j;
+        pd = dj;
+        pz = zj;
+        continue;
+      }
+      const double r = hypot(pz, zj);
+      const double c = zj / r;
+      const double s = -pz / r;
+      if (fabs((dj - pd) * c * s) <= tol) {
+        const int fi = sp[prev], fj = sp[j];
+        B.rot_i[s0 + nrot] = prev;
+        B.rot_j[s0 + nrot] = j;
+        B.rot_c[s0 + nrot] = c;
+        B.rot_s[s0 + nrot] = s;
+        B.rot_f[s0 + nrot] = fi | (fj << 2);
+        ++nrot;
+        sp[prev] = sp[j] = fi | fj;
+        ds[prev] = c * c * pd + s * s * dj;
+        zs[prev] = 0.0;
+        defl[nd++] = prev;
+        pd = s * s * pd + c * c * dj;
+        pz = r;
+        prev = j;
+      } else {
+        surv[K] = prev;
+        dS[K] = pd;
+        zS[K] = pz;
+        ds[prev] = pd;
+        zs[prev] = pz;
+        ++K;
+        prev = j;
+        pd = dj;
+        pz = zj;
+      }
+    }
+    if (prev >= 0) {
+      surv[K] = prev;
+      dS[K] = pd;
+      zS[K] = pz;
+      ds[prev] = pd;
+      zs[prev] = pz;
+      ++K;
+    }
+    // survivor groups by row support: top only (1), both (3), bottom only (2)
+    int k1 = 0, k2 = 0, k3 = 0;
+    for (int r = 0; r < K; ++r) {
+      const int f = sp[surv[r]];
+      k1 += (f == 1);
+      k2 += (f == 3);
+      k3 += (f == 2);
+    }
+    int c1 = 0, c2 = k1, c3 = k1 + k2;
+    int32_t* __restrict__ go = B.gorder + s0;
+    for (int r = 0; r < K; ++r) {
+      const int f = sp[surv[r]];
+      if (f == 1) go[c1++] = r;
+      else if (f == 3) go[c2++] = r;
+      else go[c3++] = r;
+    }
+    M.K = K;
+    M.nrot = nrot;
+    M.k1 = k1;
+    M.k2 = k2;
+    M.k3 = k3;
+    M.rho = rho;
+    M.tol = tol;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// blocks: RootBlock(merge, i0) with 256 items each, items [0, K) are roots,
+// [K, n) deflated values.
+__global__ void __launch_bounds__(256) k_final_order(const MergeDev* __restrict__ merges, LevelBufs B,
+                                                     const RootBlock* __restrict__ blocks) {
+  __shared__ double tile[256];
+  const RootBlock rb = blocks[blockIdx.x];
+  const MergeDev& M = merges[rb.merge];
+  const int64_t s0 = M.s0;
+  const int n = M.n, K = M.K, D = n - K;
+  const int item = rb.i0 + threadIdx.x;
+  if (rb.i0 >= n) return;
+  const bool valid = item < n;
+  const bool isroot = item < K;
+  const int q = item - K;
+  double x = 0.0;
+  if (valid) x = isroot ? B.lam[s0 + item] : B.dsort[s0 + B.defl[s0 + q]];
+  int cnt = 0;
+  for (int t0 = 0; t0 < D; t0 += 256) {
+    const int tq = t0 + threadIdx.x;
+    tile[threadIdx.x] = (tq < D) ? B.dsort[s0 + B.defl[s0 + tq]] : 0.0;
+    __syncthreads();
+    const int lim = min(256, D - t0);
+    if (valid) {
+      if (isroot) {
+        for (int u = 0; u < lim; ++u) cnt += tile[u] < x;
+      } else {
+        for (int u = 0; u < lim; ++u) {
+          const double y = tile[u];
+          cnt += (y < x) || (y == x && (t0 + u) < q);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  int pos;
+  if (isroot) {
+    pos = item + cnt;
+    B.posR[s0 + item] = pos;
+  } else {
+    pos = upper_bound_d(B.lam + s0, K, x) + cnt;
+    B.posD[s0 + q] = pos;
+  }
+  B.w_out[s0 + pos] = x;
+}
+
+// ---------------------------------------------------------------------------
+// blocks: RootBlock(merge, row0), one thread per row of the merge block.
+__global__ void __launch_bounds__(256) k_rotate(const MergeDev* __restrict__ merges, LevelBufs B,
+                                                const RootBlock* __restrict__ blocks) {
+  const RootBlock rb = blocks[blockIdx.x];
+  const MergeDev& M = merges[rb.merge];
+  const int nrot = M.nrot;
+  if (nrot == 0 || rb.i0 >= M.n) return;
+  const int r = rb.i0 + threadIdx.x;
+  const bool valid = r < M.n;
+  const int64_t s0 = M.s0;
+  const int bit = (r < M.n1) ? 1 : 2;
+  double* __restrict__ row = B.Zold + (s0 + r);
+  const int64_t ldz = B.ldo;
+  for (int t = 0; t < nrot; ++t) {
+    const int i = B.rot_i[s0 + t], j = B.rot_j[s0 + t];
+    const int f = B.rot_f[s0 + t];
+    const int fi = f & 3, fj = f >> 2;
+    if (!valid || !((fi | fj) & bit)) continue;
+    const double c = B.rot_c[s0 + t], s = B.rot_s[s0 + t];
+    const int64_t ci = (s0 + B.src[s0 + i]) * ldz;
+    const int64_t cj = (s0 + B.src[s0 + j]) * ldz;
+    const double xi = (fi & bit) ? row[ci] : 0.0;
+    const double xj = (fj & bit) ? row[cj] : 0.0;
+    row[ci] = c * xi + s * xj;
+    row[cj] = -s * xi + c * xj;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one block per column job: job -> (merge col_merge[job], local column col_idx[job]).
+__global__ void __launch_bounds__(256) k_pack(const MergeDev* __restrict__ merges,
+                                              const int32_t* __restrict__ col_merge,
+                                              const int32_t* __restrict__ col_idx, LevelBufs B, int sorted_pack) {
+  const MergeDev& M = merges[col_merge[blockIdx.x]];
+  const int64_t s0 = M.s0;
+  const int n = M.n, n1 = M.n1, K = M.K;
+  const int c = col_idx[blockIdx.x];
+  int sp;
+  double* __restrict__ dst;
+  if (c < K) {
+    const int r = (sorted_pack || M.mode == 1) ? c : B.gorder[s0 + c];
+    sp = B.surv[s0 + r];
+    dst = B.pk + M.zoff + (int64_t)c * n;
+  } else {
+    const int q = c - K;
+    sp = B.defl[s0 + q];
+    dst = B.Znew + s0 + (s0 + B.posD[s0 + q]) * B.ldn;
+  }
+  const int f = B.supp[s0 + sp];
+  const double* __restrict__ srcc = B.Zold + s0 + (s0 + B.src[s0 + sp]) * B.ldo;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const int bit = (r < n1) ? 1 : 2;
+    dst[r] = (f & bit) ? srcc[r] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cauchy matrix qc(r', j) = uh_i / (d_i - lam_j), i = gorder[r'] (grouped) or
+// r'; column-major with leading dimension K.  One block per (merge, column
+// tile of ncols columns); tile lists built by the host.
+__global__ void __launch_bounds__(256) k_cauchy(const MergeDev* __restrict__ merges,
+                                                const int32_t* __restrict__ tile_merge,
+                                                const int32_t* __restrict__ tile_col0, LevelBufs B, int ncols,
+                                                int grouped) {
+  const MergeDev& M = merges[tile_merge[blockIdx.x]];
+  const int K = M.K;
+  const int j0 = tile_col0[blockIdx.x];
+  if (j0 >= K) return;
+  const int64_t s0 = M.s0;
+  const double* __restrict__ d = B.dS + s0;
+  const double* __restrict__ gam = B.gam + s0;
+  const double* __restrict__ mu = B.mu + s0;
+  const double* __restrict__ uh = B.uh + s0;
+  const int32_t* __restrict__ go = B.gorder + s0;
+  double* __restrict__ qc = B.qc + M.zoff;
+  const int j1 = min(K, j0 + ncols);
+  for (int rr = threadIdx.x; rr < K; rr += blockDim.x) {
+    const int i = grouped ? go[rr] : rr;
+    const double di = d[i];
+    const double ui = uh[i];
+    for (int j = j0; j < j1; ++j) {
+      const double dj = d[j];
+      const double dj1 = (j + 1 < K) ? d[j + 1] : 0.0;
+      const double dl = d_minus_lam(i, j, di, dj, dj1, gam[j], mu[j]);
+      qc[rr + (int64_t)j * K] = ui / dl;
+    }
+  }
+}

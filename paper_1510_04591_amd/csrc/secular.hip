@@ -1,0 +1,235 @@
+// Secular equation of D + rho z z^T (Theorem 1) on gfx950.
+//
+// One root per lane; a workgroup owns 64 consecutive roots of one merge and
+// splits the pole sum over its W waves (W = blockDim/64), so that large
+// secular sizes still put many waves on every SIMD.  The poles d_j and
+// weights z_j are read as wave-uniform (scalar) loads, one j per step.
+//
+// Iteration (written from the rational-interpolation literature: Bunch,
+// Nielsen & Sorensen 1978; Li 1993): with origin d_o the nearer pole and
+// tau = lam - d_o, the function
+//     g(tau) = 1/rho + psi(tau) + phi(tau),
+//     psi = sum_{j<=sp} z_j^2/(delta_j - tau),  phi = sum_{j>sp} z_j^2/(delta_j - tau)
+// (delta_j = d_j - d_o, sp = i for interior roots, K-2 for the last) is
+// modelled near tau by  C + q/(D1 - eta) + Q/(D2 - eta)  with the poles
+// D1 = delta_sp - tau, D2 = delta_{sp+1} - tau, q = D1^2 psi', Q = D2^2 phi'
+// and C fixed by g(tau); the model root of the quadratic is the next step.
+// A bracket from the signs of g guards every step; a step leaving it is
+// replaced by a bisection over the representable doubles.  Convergence: |g|
+// below its rounding-error bound, or an exhausted bracket.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr int MAXW = 16;
+
+__device__ __forceinline__ double bits_mid(double lo, double hi) {
+  // midpoint over the ordered set of doubles of one sign (|lo| < |hi| or the
+  // reverse); both have the sign of hi or are zero.
+  unsigned long long a = (unsigned long long)__double_as_longlong(fabs(lo));
+  unsigned long long b = (unsigned long long)__double_as_longlong(fabs(hi));
+  unsigned long long m = a + (b - a) / 2ull;
+  if (b < a) m = b + (a - b) / 2ull;
+  double r = __longlong_as_double((long long)m);
+  return (hi < 0.0 || lo < 0.0) ? -r : r;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ merges,
+                                                  const RootBlock* __restrict__ blocks,
+                                                  const double* __restrict__ dS,
+                                                  const double* __restrict__ zS, double* __restrict__ lamS,
+                                                  double* __restrict__ gamS, double* __restrict__ muS,
+                                                  int max_iter, int* __restrict__ noconv) {
+  __shared__ double s_part[5][MAXW][64];
+  __shared__ double s_tau[64];
+  __shared__ int s_org[64];
+  __shared__ int s_done[64];
+  __shared__ int s_any;
+
+  const RootBlock rb = blocks[blockIdx.x];
+  const MergeDev& M = merges[rb.merge];
+  const int K = M.K;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int W = blockDim.x >> 6;
+  if (rb.i0 >= K) return;  // block-uniform
+  const int64_t base = M.s0;
+  const double* __restrict__ d = dS + base;
+  const double* __restrict__ z = zS + base;
+  const double rho = M.rho;
+  const double rhoinv = 1.0 / rho;
+  const int i = rb.i0 + lane;
+  const bool valid = i < K;
+  const bool last = (i == K - 1);
+
+  // j range of this wave
+  const int chunk = (K + W - 1) / W;
+  const int j0 = wv * chunk;
+  const int j1 = min(K, j0 + chunk);
+
+  // wave-0 lane state
+  double lo = 0.0, hi = 0.0, gap = 0.0, tau = 0.0;
+  int org = 0, it = 0;
+  bool done = !valid;
+
+  if (K == 1) {
+    if (threadIdx.x == 0) {
+      const double g = rho * z[0] * z[0];
+      gamS[base] = g;
+      muS[base] = INFINITY;
+      if (lamS) lamS[base] = d[0] + g;
+    }
+    return;
+  }
+
+  if (wv == 0) {
+    if (valid) {
+      gap = last ? INFINITY : (d[i + 1] - d[i]);
+      tau = last ? rho : 0.5 * gap;  // phase 0 point, frame d_i
+      org = i;
+    }
+    s_tau[lane] = tau;
+    s_org[lane] = valid ? i : 0;
+    s_done[lane] = done ? 1 : 0;
+  }
+  __syncthreads();
+
+  for (int iter = 0;; ++iter) {
+    // ---- partial sums over this wave's poles
+    const double t_l = s_tau[lane];
+    const int o_l = s_org[lane];
+    const bool act = !s_done[lane];
+    const int sp = last ? K - 2 : i;
+    const double dorg = valid ? d[o_l] : 0.0;
+    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
+    if (act) {
+      for (int j = j0; j < j1; ++j) {
+        const double dj = d[j];
+        const double zj = z[j];
+        const double del = (dj - dorg) - t_l;
+        const double t = zj / del;
+        const double term = zj * t;
+        if (j <= sp) {
+          psi += term;
+          dpsi += t * t;
+        } else {
+          phi += term;
+          dphi += t * t;
+        }
+        eabs += fabs(term);
+      }
+    }
+    s_part[0][wv][lane] = psi;
+    s_part[1][wv][lane] = dpsi;
+    s_part[2][wv][lane] = phi;
+    s_part[3][wv][lane] = dphi;
+    s_part[4][wv][lane] = eabs;
+    __syncthreads();
+
+    if (wv == 0) {
+      if (!done) {
+        psi = dpsi = phi = dphi = eabs = 0.0;
+        for (int w2 = 0; w2 < W; ++w2) {
+          psi += s_part[0][w2][lane];
+          dpsi += s_part[1][w2][lane];
+          phi += s_part[2][w2][lane];
+          dphi += s_part[3][w2][lane];
+          eabs += s_part[4][w2][lane];
+        }
+        const double g = rhoinv + psi + phi;
+        if (iter == 0) {
+          // origin choice (frame d_i): root left of the midpoint iff g >= 0
+          if (last) {
+            lo = 0.0;
+            hi = rho;
+          } else if (g >= 0.0) {
+            org = i;
+            lo = 0.0;
+            hi = 0.5 * gap;
+          } else {
+            org = i + 1;
+            tau = -0.5 * gap;  // same point seen from d_{i+1}
+            lo = 0.0;
+            hi = -0.5 * gap;
+          }
+        }
+        // error bound of the computed g (rounding of every term, of 1/rho
+        // and of tau itself)
+        const double ebound = ADC_EPS * (8.0 * eabs + 2.0 * rhoinv + 3.0 * fabs(tau) * (dpsi + dphi));
+        bool conv = (iter > 0) && (fabs(g) <= ebound);
+        if (g == 0.0) conv = true;
+        if (!conv) {
+          // bracket update from the sign of g (g increases with tau)
+          if (iter > 0 || last) {
+            if (org == i) {  // tau > 0
+              if (g < 0.0) lo = tau; else hi = tau;
+            } else {         // tau < 0, |tau| small means near d_{i+1}: g > 0 there
+              if (g < 0.0) hi = tau; else lo = tau;
+            }
+          }
+          // model step
+          const double dsp = d[sp] - d[org];
+          const double dsp1 = d[sp + 1] - d[org];
+          const double D1 = dsp - tau;
+          const double D2 = dsp1 - tau;
+          const double q = D1 * D1 * dpsi;
+          const double Q = D2 * D2 * dphi;
+          const double C = g - D1 * dpsi - D2 * dphi;
+          const double a = C * (D1 + D2) + q + Q;
+          const double b = D1 * D2 * g;
+          const double disc = sqrt(fabs(a * a - 4.0 * b * C));
+          double eta;
+          if (!last) {
+            eta = (a <= 0.0) ? (a - disc) / (2.0 * C) : (2.0 * b) / (a + disc);
+          } else {
+            eta = (a >= 0.0) ? (a + disc) / (2.0 * C) : (2.0 * b) / (a - disc);
+          }
+          double tn = tau + eta;
+          // the bracket is (lo, hi) for org == i (0 <= lo < hi) and
+          // (hi, lo) for org == i+1 (hi < lo <= 0)
+          const double bl = fmin(lo, hi), bh = fmax(lo, hi);
+          if (!(tn > bl && tn < bh) || !isfinite(tn)) tn = bits_mid(lo, hi);
+          if (tn == tau || tn == lo || tn == hi) conv = true;
+          else tau = tn;
+          ++it;
+          if (it >= max_iter && !conv) {
+            conv = true;
+            atomicMin(noconv, (int)(M.gbase + i));
+          }
+        }
+        done = conv;
+      }
+      s_tau[lane] = tau;
+      s_org[lane] = org;
+      s_done[lane] = done ? 1 : 0;
+    }
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    if (wv == 0) {
+      const int nd = __any(!done) ? 1 : 0;
+      if (lane == 0) s_any = nd;
+    }
+    __syncthreads();
+    if (!s_any) break;
+  }
+
+  if (wv == 0 && valid) {
+    double gm, mu;
+    if (last) {
+      gm = tau;
+      mu = INFINITY;
+    } else if (org == i) {
+      gm = tau;
+      mu = gap - tau;
+    } else {
+      mu = -tau;
+      gm = gap + tau;
+    }
+    gamS[base + i] = gm;
+    muS[base + i] = mu;
+    if (lamS) lamS[base + i] = d[org] + tau;
+  }
+}

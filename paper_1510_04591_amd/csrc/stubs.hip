@@ -1,0 +1,41 @@
+// Entry points whose GPU implementation is not built yet: they report
+// ADC_ERR_UNSUPPORTED so that callers fail loudly.
+#include "adc_internal.hpp"
+#include "hss.hpp"
+
+adc_status hss_level_update(adc_ctx, const adc_opts&, MergeDev*, MergeDev*, int, const LevelBufs&, int,
+                            adc_report*, double*, double*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+void mlp_release(adc_ctx) {}
+extern "C" {
+adc_status adc_stedc_batched(adc_ctx, int32_t, const int64_t*, const double* const*, const double* const*,
+                             double* const*, double* const*, const int64_t*, const adc_opts*, adc_report*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_hss_build(adc_ctx, int64_t, const double*, const double*, const double*, const double*,
+                         const double*, const double*, int32_t, const adc_opts*, adc_hss*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_hss_apply(adc_ctx, adc_hss, int64_t, const double*, int64_t, double*, int64_t) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_hss_info(adc_hss, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, double*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_hss_free(adc_hss) { return ADC_ERR_UNSUPPORTED; }
+adc_status adc_mlp_features(adc_ctx, int64_t, const double*, const double*, const double*, const int64_t*,
+                            int32_t, float*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_mlp_init(adc_ctx, uint64_t) { return ADC_ERR_UNSUPPORTED; }
+adc_status adc_mlp_train(adc_ctx, int32_t, const float*, const float*, int32_t, int32_t, float, float*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_mlp_infer(adc_ctx, int32_t, const float*, float*) { return ADC_ERR_UNSUPPORTED; }
+adc_status adc_mlp_grad(adc_ctx, int32_t, const float*, const float*, float*, float*) {
+  return ADC_ERR_UNSUPPORTED;
+}
+adc_status adc_mlp_get(adc_ctx, float*) { return ADC_ERR_UNSUPPORTED; }
+adc_status adc_mlp_set(adc_ctx, const float*) { return ADC_ERR_UNSUPPORTED; }
+}

@@ -1,0 +1,45 @@
+"""Full eigendecomposition on the GPU vs the oracle and closed forms."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dc as odc, sturm
+from paper_1510_04591_amd import adc, workloads
+from conftest import cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def solve(ctx, a, b, **kw):
+    w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b) if len(a) > 1 else None, **kw)
+    torch.cuda.synchronize()
+    return w.cpu().numpy(), Z.cpu().numpy(), rep
+
+
+def check_result(a, b, w, Z, w_ref, res_tol=1e-13, orth_tol=1e-12):
+    tn = odc.tnorm1(a, b) if len(a) > 1 else abs(a[0])
+    assert np.max(np.abs(w - w_ref)) <= 1e-13 * max(tn, 1e-300)
+    assert np.all(np.diff(w) >= 0)
+    assert odc.residual(a, b, w, Z) <= res_tol
+    assert odc.orthogonality(Z) <= orth_tol
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 32, 33, 64, 65, 100, 1024])
+def test_toeplitz_dense(ctx, N):
+    print(f"toeplitz N={N}", flush=True)
+    a, b = workloads.toeplitz(N)
+    w, Z, rep = solve(ctx, a, b, force_dense=1)
+    k = np.arange(1, N + 1)
+    exact = np.sort(2 + 2 * np.cos(k * np.pi / (N + 1)))
+    check_result(a, b, w, Z, exact)
+
+
+@pytest.mark.parametrize("N,seed", [(64, 1), (200, 2), (1000, 3), (2048, 2)])
+def test_random_dense_vs_oracle(ctx, N, seed):
+    print(f"random N={N} seed={seed}", flush=True)
+    a, b = workloads.random_uniform(N, seed)
+    w, Z, rep = solve(ctx, a, b, force_dense=1)
+    w_o, Z_o = odc.stedc(a, b, leaf=32)
+    check_result(a, b, w, Z, w_o)
+    ks = np.array([0, N // 3, N - 1])
+    assert np.max(np.abs(w[ks] - sturm.eigenvalues_by_index(a, b, ks))) <= 1e-13 * odc.tnorm1(a, b)
