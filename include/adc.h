@@ -93,14 +93,19 @@ typedef struct adc_report {
   int32_t hss_per_level[64]; /* HSS merges per level                            */
   int32_t max_rank;          /* largest HSS node rank seen                      */
   int32_t samples;           /* largest sample count s used                     */
-  double  t_phase[12];       /* seconds: 0 leaves, 1 deflation, 2 secular,
-                                3 loewner+v, 4 dense Cauchy+GEMM, 5 HSS sampling,
-                                6 HSS compression, 7 HSS check, 8 HSS multiply,
-                                9 permute/copy, 10 total, 11 host overhead
-                                (filled only when timing is requested by
-                                a non-null report with t_phase[0] = -1)       */
-  double  flops_model;       /* algorithmic flops of the chosen updates        */
-  double  bytes_model;       /* algorithmic HBM bytes of the chosen updates    */
+  double  t_phase[12];       /* seconds, from HIP events on the context stream:
+                                0 tear+leaves, 1 merge prep and deflation,
+                                2 secular, 3 Loewner+v, 4 dense update GEMM,
+                                5 HSS rank estimate+sampling, 6 HSS compression,
+                                7 HSS check, 8 HSS multiply, 9 ordering,
+                                rotations, packing and the Cauchy matrix,
+                                10 total wall time (host clock), 11 wall time
+                                not covered by phases 0-9                      */
+  double  phase_flops[12];   /* algorithmic flops per phase (same indices)     */
+  double  phase_bytes[12];   /* algorithmic HBM bytes per phase                */
+  int32_t phase_launches[12];/* kernel launches of the phase's main kernel     */
+  double  flops_model;       /* algorithmic flops of the eigenvector updates   */
+  double  bytes_model;       /* algorithmic HBM bytes of the updates           */
   double  check_err_max;     /* largest HSS check error accepted               */
 } adc_report;
 
@@ -191,6 +196,12 @@ adc_status adc_hss_apply(adc_ctx ctx, adc_hss h, int64_t P, const double* X, int
  * samples used, retries, check error (any pointer may be NULL). */
 adc_status adc_hss_info(adc_hss h, int32_t* levels, int32_t* leaves, int32_t* max_rank,
                         int32_t* samples, int32_t* retries, double* check_err);
+/* Per-node ranks in heap order (root 0, children of p at 2p+1, 2p+2): kr =
+ * row-ID rank (columns of U_i), kc = column-ID rank (columns of V_i), lo/hi =
+ * index range t_i.  Host arrays of nmax entries; writes min(nmax, nodes) and
+ * returns the node count in *count. */
+adc_status adc_hss_nodes(adc_hss h, int32_t nmax, int32_t* lo, int32_t* hi, int32_t* kr, int32_t* kc,
+                         int32_t* count);
 adc_status adc_hss_free(adc_hss h);
 
 /* -------------------------------------------- learned rank predictor (MLP) */

@@ -201,13 +201,27 @@ def cauchy_block(gen, rows, cols):
     return np.asarray(uh)[np.asarray(rows)][:, None] * np.asarray(v)[np.asarray(cols)][None, :] / dl
 
 
-def rshss(gen, Omega, bounds, tol):
-    """Algorithm 2 with a given Omega (K x s).  Returns (root, postorder, info)."""
+def rshss(gen, Omega, bounds, tol, sample="paper"):
+    """Algorithm 2 with a given Omega (K x s).  Returns (root, postorder, info).
+
+    sample="paper": Phi_i = Y_i - D_i Omega_i and Theta_i = Z_i - D_i^T Omega_i
+    as printed.  sample="offdiag": the same quantities by their definition,
+    the HSS block row A(t_i, I \\ t_i) times Omega(I \\ t_i) (and the column
+    likewise), which avoids the cancellation of the subtraction."""
     d = gen[0]
     K = len(d)
     A = cauchy_block(gen, np.arange(K), np.arange(K))
-    Y = A @ Omega
-    Z = A.T @ Omega
+    if sample == "offdiag":
+        Aoff = A.copy()
+        for lo, hi in zip(bounds[:-1], bounds[1:]):
+            Aoff[lo:hi, lo:hi] = 0.0
+        Y = Aoff @ Omega
+        Z = Aoff.T @ Omega
+        A_for_D = np.zeros_like(A)
+    else:
+        Y = A @ Omega
+        Z = A.T @ Omega
+        A_for_D = A
     root, post = build_tree(bounds)
     L = max(n.level for n in post)
     Phi, Theta, Yh, Zh = {}, {}, {}, {}
@@ -216,7 +230,7 @@ def rshss(gen, Omega, bounds, tol):
         for nd in [n for n in post if n.level == lev]:
             if nd.leaf:
                 t = np.arange(nd.lo, nd.hi)
-                D = A[np.ix_(t, t)]
+                D = A_for_D[np.ix_(t, t)]
                 phi = Y[t] - D @ Omega[t]
                 theta = Z[t] - D.T @ Omega[t]
                 rows_r, rows_c = t, t

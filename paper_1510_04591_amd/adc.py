@@ -44,7 +44,8 @@ class adc_report(C.Structure):
         ("retries", C.c_int32), ("hss_fallbacks", C.c_int32), ("info_index", C.c_int32),
         ("n_per_level", C.c_int64 * 64), ("K_per_level", C.c_int64 * 64),
         ("hss_per_level", C.c_int32 * 64), ("max_rank", C.c_int32), ("samples", C.c_int32),
-        ("t_phase", C.c_double * 12), ("flops_model", C.c_double), ("bytes_model", C.c_double),
+        ("t_phase", C.c_double * 12), ("phase_flops", C.c_double * 12), ("phase_bytes", C.c_double * 12),
+        ("phase_launches", C.c_int32 * 12), ("flops_model", C.c_double), ("bytes_model", C.c_double),
         ("check_err_max", C.c_double),
     ]
 
@@ -54,7 +55,9 @@ class adc_report(C.Structure):
                     hss_fallbacks=self.hss_fallbacks, info_index=self.info_index,
                     n_per_level=list(self.n_per_level[:L]), K_per_level=list(self.K_per_level[:L]),
                     hss_per_level=list(self.hss_per_level[:L]), max_rank=self.max_rank,
-                    samples=self.samples, t_phase=list(self.t_phase), flops_model=self.flops_model,
+                    samples=self.samples, t_phase=list(self.t_phase), phase_flops=list(self.phase_flops),
+                    phase_bytes=list(self.phase_bytes), phase_launches=list(self.phase_launches),
+                    flops_model=self.flops_model,
                     bytes_model=self.bytes_model, check_err_max=self.check_err_max)
 
 
@@ -87,6 +90,8 @@ _SIGS = {
     "adc_hss_info": (_P, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                      C.POINTER(_I32), C.POINTER(_D)),
     "adc_hss_free": (_P,),
+    "adc_hss_nodes": (_P, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
+                      C.POINTER(_I32)),
     "adc_mlp_features": (_P, _I64, _P, _P, _P, C.POINTER(_I64), _I32, _P),
     "adc_mlp_init": (_P, C.c_uint64),
     "adc_mlp_train": (_P, _I32, _P, _P, _I32, _I32, C.c_float, C.POINTER(C.c_float)),
@@ -209,6 +214,14 @@ def adc_hss_info(h):
 
 def adc_hss_free(h):
     return lib().adc_hss_free(h)
+
+
+def adc_hss_nodes(h, nmax=1 << 16):
+    arrs = [(_I32 * nmax)() for _ in range(4)]
+    cnt = _I32()
+    _check(lib().adc_hss_nodes(h, nmax, *arrs, C.byref(cnt)), "adc_hss_nodes")
+    n = min(cnt.value, nmax)
+    return [dict(lo=arrs[0][i], hi=arrs[1][i], kr=arrs[2][i], kc=arrs[3][i]) for i in range(n)]
 
 
 def adc_mlp_features(ctx, K, d, gam, mu, bounds, feat):

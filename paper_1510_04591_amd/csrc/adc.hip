@@ -90,6 +90,7 @@ void adc_ctx_s::release() {
   if (host_stage) hipHostFree(host_stage);
   host_stage = nullptr;
   host_stage_bytes = 0;
+  timer.destroy();
   mlp_release(this);
 }
 

@@ -14,10 +14,58 @@ enum Slot {
   SLOT_BATCH,      // batched solver workspace
   SLOT_BATCH_DESC, // batched solver descriptors
   SLOT_MLP,        // MLP scratch
+  SLOT_HSS_JOBS,   // HSS launch lists
+  SLOT_HSS_CHECK,  // HSS accuracy-check probes
+  SLOT_GEMM_A,     // grouped GEMM descriptors (narrow tiles)
+  SLOT_GEMM_B,     // grouped GEMM descriptors (wide tiles)
+  SLOT_FB,         // dense-fallback descriptors
   NSLOT
 };
 
 struct MlpState;
+
+// Phase timing with HIP events on the context stream: start() opens an
+// interval, mark(p) closes it as phase p and opens the next; collect() (after
+// a stream synchronisation) adds the closed intervals to the report.
+struct PhaseTimer {
+  static constexpr int NEV = 24;
+  hipEvent_t ev[NEV] = {};
+  int phase[NEV] = {};
+  int n = 0;
+  bool ready = false;
+  bool on = false;
+  void start(hipStream_t s, bool enable) {
+    on = enable;
+    n = 0;
+    if (!on) return;
+    if (!ready) {
+      for (int i = 0; i < NEV; ++i) hipEventCreate(&ev[i]);
+      ready = true;
+    }
+    hipEventRecord(ev[0], s);
+    n = 1;
+  }
+  void mark(hipStream_t s, int p) {
+    if (!on || n >= NEV) return;
+    hipEventRecord(ev[n], s);
+    phase[n] = p;
+    ++n;
+  }
+  void collect(adc_report* rep) {
+    if (!on || !rep) return;
+    for (int i = 1; i < n; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) == hipSuccess && phase[i] >= 0)
+        rep->t_phase[phase[i]] += 1e-3 * ms;
+    }
+    n = 0;
+  }
+  void destroy() {
+    if (ready)
+      for (int i = 0; i < NEV; ++i) hipEventDestroy(ev[i]);
+    ready = false;
+  }
+};
 
 struct adc_ctx_s {
   struct Buf {
@@ -31,6 +79,7 @@ struct adc_ctx_s {
   size_t host_stage_bytes = 0;
   MlpState* mlp = nullptr;
   void* batch_cache = nullptr;  // graph cache of the batched solver
+  PhaseTimer timer;
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);
   void release();
@@ -71,3 +120,14 @@ __global__ void k_set_int(int* p, int v);
 __global__ void k_tear(const double* __restrict__ diag, const double* __restrict__ off,
                        const int64_t* __restrict__ splits, int nsplit, double* __restrict__ a, int64_t n);
 adc_status validate_opts_ext(const adc_opts& o);
+
+// Dense Cauchy update of merge g whose survivor columns were packed in pole
+// order (the fallback of a failed HSS check).
+adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const MergeDev& M, const LevelBufs& B,
+                               double* flops);
+// HSS sample rank from the learned predictor (r_bound when no model is loaded).
+int mlp_rank(adc_ctx c, const double* d, const double* gam, const double* mu, int K, const std::vector<int>& bounds,
+             const adc_opts& o, int r_bound);
+// Rank estimate of eq. (bounds) over leaf boundaries (may move boundaries).
+int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
+                      const adc_opts& o);

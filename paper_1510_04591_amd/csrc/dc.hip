@@ -136,6 +136,48 @@ WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
 
 }  // namespace
 
+adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const MergeDev& M, const LevelBufs& B,
+                               double* flops) {
+  if (M.K == 0) return ADC_OK;
+  hipStream_t st = c->stream;
+  const int ncols = 8;
+  std::vector<int32_t> tm, tc;
+  for (int j0 = 0; j0 < M.K; j0 += ncols) {
+    tm.push_back(g);
+    tc.push_back(j0);
+  }
+  GemmProb P{};
+  P.M = M.n;
+  P.N = M.K;
+  P.K = M.K;
+  P.A = B.pk + M.zoff;
+  P.lda = M.n;
+  P.B = B.qc + M.zoff;
+  P.ldb = M.K;
+  P.C = B.Znew + M.s0 + M.s0 * B.ldn;
+  P.ldc = B.ldn;
+  P.colmap = B.posR + M.s0;
+  P.vscale = B.v + M.s0;
+  P.tiles_m = (P.M + 127) / 128;
+  P.tile0 = 0;
+  const int tiles = P.tiles_m * ((P.N + 127) / 128);
+  const size_t nt = tm.size();
+  void* dp;
+  ADC_TRY(c->buffer(SLOT_FB, sizeof(GemmProb) + 2 * nt * 4 + 1024, &dp));
+  GemmProb* dg = (GemmProb*)dp;
+  int32_t* dtm = (int32_t*)((char*)dp + 256);
+  int32_t* dtc = dtm + nt;
+  HIP_OK(hipMemcpyAsync(dg, &P, sizeof(P), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(dtm, tm.data(), nt * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(dtc, tc.data(), nt * 4, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_cauchy, dim3((unsigned)nt), dim3(256), 0, st, d_m, dtm, dtc, B, ncols, 0);
+  hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, st, dg, 1);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(st));
+  if (flops) *flops += 2.0 * P.M * (double)P.N * P.K;
+  return ADC_OK;
+}
+
 extern "C" adc_status adc_workspace_query(adc_ctx c, int64_t n, const adc_opts* opts, size_t* bytes) {
   if (!c || n < 0 || !bytes) return ADC_ERR_ARG;
   (void)opts;
@@ -220,6 +262,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     std::memcpy(h_lm, lm[0].data(), n0 * 4);
     std::memcpy(h_lm + n0, lm[1].data(), lm[1].size() * 4);
     HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
+    c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_tear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag, offdiag, d_sp,
                        (int)plan.splits.size(), L.a, n);
     if (n0)
@@ -229,8 +272,10 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)ls[1].size()), dim3(256), 0, st, L.a, offdiag, d_ls + n0,
                          d_lm + n0, w, L.Zb, (int64_t)n, 40);
     HIP_OK(hipGetLastError());
+    c->timer.mark(st, 0);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, L.noconv, INT32_MAX);
     HIP_OK(hipStreamSynchronize(st));  // staging buffer is reused below
+    c->timer.collect(rep);
   }
 
   if (rep) rep->levels = nlev;
@@ -288,10 +333,13 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     }
     HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(d_m, h_m, nm * sizeof(MergeDev), hipMemcpyHostToDevice, st));
+    c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
     HIP_OK(hipGetLastError());
+    c->timer.mark(st, 1);
     HIP_OK(hipMemcpyAsync(h_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    c->timer.collect(rep);
 
     // --- host decisions and launch lists
     int64_t Kmax = 0, Ksum = 0, nsum = 0;
@@ -364,31 +412,44 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
         P.tile0 = gtiles;
         gtiles += P.tiles_m * ((P.N + 127) / 128);
         ++ngp;
-        flops += 2.0 * P.M * (double)P.N * P.K;
-        bytes += 8.0 * ((double)P.M * P.K + (double)P.K * P.N + (double)P.M * P.N);
+        const double f = 2.0 * P.M * (double)P.N * P.K;
+        const double by = 8.0 * ((double)P.M * P.K + (double)P.K * P.N + (double)P.M * P.N);
+        flops += f;
+        bytes += by;
+        if (rep) {
+          rep->phase_flops[4] += f;
+          rep->phase_bytes[4] += by;
+        }
       }
     }
+    if (rep && gtiles) rep->phase_launches[4] += 1;
     HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
 
     // --- secular, Loewner, v
     const int W = pick_waves(Kmax);
+    c->timer.start(st, rep != nullptr);
     if (nrb) {
       hipLaunchKernelGGL(k_secular, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.lam, L.gam, L.mu,
                          o.max_iter, L.noconv);
+      c->timer.mark(st, 2);
       hipLaunchKernelGGL(k_lowner, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.gam, L.mu, L.uh);
       hipLaunchKernelGGL(k_vnorm, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.gam, L.mu, L.uh, L.v);
+      c->timer.mark(st, 3);
     }
     hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
     hipLaunchKernelGGL(k_rotate, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
     hipLaunchKernelGGL(k_pack, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B, 0);
     HIP_OK(hipGetLastError());
     if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, ncols, 1);
+    c->timer.mark(st, 9);
     if (gtiles) hipLaunchKernelGGL(k_gemm_f64, dim3(gtiles), dim3(256), 0, st, d_gp, ngp);
+    c->timer.mark(st, 4);
     HIP_OK(hipGetLastError());
     if (hss_here) {
       ADC_TRY(hss_level_update(c, o, h_m, d_m, nm, B, t, rep, &flops, &bytes));
     }
     HIP_OK(hipStreamSynchronize(st));  // staging buffer reused by the next level
+    c->timer.collect(rep);
 
     if (rep && t < 64) {
       rep->n_per_level[t] = nsum;
@@ -406,6 +467,9 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     rep->flops_model += flops;
     rep->bytes_model += bytes;
     rep->t_phase[10] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    double covered = 0.0;
+    for (int p = 0; p < 10; ++p) covered += rep->t_phase[p];
+    rep->t_phase[11] = rep->t_phase[10] - covered;
   }
   if (nc != INT32_MAX) {
     if (rep) rep->info_index = nc;

@@ -1,0 +1,857 @@
+// Host orchestration of the HSS update (Algorithm 2 and Algorithm 3), the
+// rank estimate of eq. (bounds) with the neighbouring-segment rules of
+// Section 4.1, the adaptive accuracy check, and the adc_hss_* entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hss.hpp"
+
+namespace {
+
+constexpr int SP_PROBE = 32;  // padded probe count of the accuracy check
+constexpr int S_MAX = 512;
+
+int ceil_log2_ratio(int K, int m) {
+  int L = 0;
+  while (((int64_t)m << L) < K) ++L;
+  return L;
+}
+
+std::vector<int> balanced_bounds(int K, int L) {
+  std::vector<std::pair<int, int>> r{{0, K}};
+  for (int l = 0; l < L; ++l) {
+    std::vector<std::pair<int, int>> nx;
+    for (auto& p : r) {
+      const int h = (p.second - p.first) / 2;
+      nx.push_back({p.first, p.first + h});
+      nx.push_back({p.first + h, p.second});
+    }
+    r.swap(nx);
+  }
+  std::vector<int> b;
+  for (auto& p : r) b.push_back(p.first);
+  b.push_back(K);
+  return b;
+}
+
+// smallest integer r >= log(16/eps) log(8R) / pi^2  (eq. bounds)
+int rank_bound(double R, double eps) {
+  return (int)std::ceil(std::log(16.0 / eps) * std::log(8.0 * R) / (M_PI * M_PI));
+}
+
+// distance of the segments split before index b: min(lam_b - d_{b-1}, d_b - lam_{b-1})
+double boundary_dist(const double* d, const double* gam, const double* mu, int K, int b) {
+  const double x = (b < K) ? (d[b] - d[b - 1]) + gam[b] : INFINITY;
+  const double y = mu[b - 1];
+  return std::min(std::fabs(x), std::fabs(y));
+}
+
+}  // namespace
+
+// Rank estimate over the leaf boundaries (Section 4.1): every boundary closer
+// than shift_thresh is moved by up to shift_max indices to the largest
+// distance; r = min(r_cap, max_b rank_bound((lam_K - d_1)/dist_b)).
+int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
+                      const adc_opts& o) {
+  const double span = (d[K - 1] + gam[K - 1]) - d[0];
+  int r = 0;
+  for (size_t t = 1; t + 1 < bounds.size(); ++t) {
+    int b = bounds[t];
+    double dist = boundary_dist(d, gam, mu, K, b);
+    if (dist < o.shift_thresh) {
+      int best = b;
+      double bd = dist;
+      const int lo = std::max(bounds[t - 1] + 1, b - o.shift_max);
+      const int hi = std::min(bounds[t + 1] - 1, b + o.shift_max);
+      for (int bb = lo; bb <= hi; ++bb) {
+        const double dd = boundary_dist(d, gam, mu, K, bb);
+        if (dd > bd) {
+          best = bb;
+          bd = dd;
+        }
+      }
+      bounds[t] = best;
+      dist = bd;
+    }
+    const double R = (dist > 0.0) ? span / dist : INFINITY;
+    const int rb = std::isfinite(R) ? std::min(o.r_cap, rank_bound(std::max(R, 1.0), o.rank_eps)) : o.r_cap;
+    r = std::max(r, rb);
+  }
+  return std::min(r, o.r_cap);
+}
+
+// ---------------------------------------------------------------------------
+// A set of HSS merges built together (one DC level, or one adc_hss_build).
+struct HssBatch {
+  struct One {
+    int K = 0, L = 0, s = 0, sp = 0, r = 0;
+    uint32_t stream = 0;
+    std::vector<int> bounds;
+    std::vector<HssNode> nodes;  // host copy
+    HssMerge dev{};
+    int64_t node_off = 0, arena_off = 0, iarena_off = 0, vec_off = 0;
+    int64_t arena_n = 0, iarena_n = 0;
+    bool pass = false;
+    double err = 0.0;
+    int retries = 0;
+    int max_rank = 0;
+  };
+  std::vector<One> ms;
+  char* mem = nullptr;
+  HssMerge* d_ms = nullptr;
+};
+
+namespace {
+
+// Lay out the nodes and storage of one merge for s samples; fills o.nodes and
+// sizes (in doubles / ints).  Offsets are relative to the merge's arenas.
+void layout_merge(HssBatch::One& m) {
+  const int L = m.L;
+  const int nn = (1 << (L + 1)) - 1;
+  m.nodes.assign(nn, HssNode{});
+  const int sp = m.sp, s = m.s;
+  int64_t a = 0, ia = 0;
+  for (int l = 0; l <= L; ++l) {
+    const int first = (1 << l) - 1;
+    const int cnt = 1 << l;
+    const int span = 1 << (L - l);
+    for (int q = 0; q < cnt; ++q) {
+      HssNode& nd = m.nodes[first + q];
+      nd.lo = m.bounds[q * span];
+      nd.hi = m.bounds[(q + 1) * span];
+      nd.leaf = (l == L);
+      const int kmax = std::min(s, nd.hi - nd.lo);
+      const int cand = nd.leaf ? (nd.hi - nd.lo) : std::min(2 * s, nd.hi - nd.lo);
+      nd.offU = a;
+      a += (int64_t)cand * kmax;
+      nd.offV = a;
+      a += (int64_t)cand * kmax;
+      nd.offB = a;
+      a += (int64_t)kmax * s;
+      nd.offPs = a;
+      a += (int64_t)kmax * sp;
+      nd.offTs = a;
+      a += (int64_t)kmax * sp;
+      nd.offYh = a;
+      a += (int64_t)kmax * sp;
+      nd.offZh = a;
+      a += (int64_t)kmax * sp;
+      nd.offWork = a;
+      a += (l == 0) ? 0 : 2 * (int64_t)cand * sp;
+      nd.offSr = ia;
+      ia += kmax;
+      nd.offSc = ia;
+      ia += kmax;
+      a = (a + 31) & ~(int64_t)31;
+    }
+  }
+  m.arena_n = a;
+  m.iarena_n = ia;
+}
+
+}  // namespace
+
+// Allocate and upload a batch (all merges' sizes and bounds already set).
+static adc_status batch_alloc(adc_ctx c, HssBatch& hb, int slot) {
+  int64_t bytes = 0;
+  auto take = [&](int64_t n) {
+    bytes = (bytes + 255) & ~(int64_t)255;
+    const int64_t o = bytes;
+    bytes += n;
+    return o;
+  };
+  const int nm = (int)hb.ms.size();
+  const int64_t off_ms = take(nm * sizeof(HssMerge));
+  for (auto& m : hb.ms) {
+    layout_merge(m);
+    m.vec_off = take((int64_t)3 * m.K * m.sp * 8 + (int64_t)m.K * 4 + ((int64_t)m.bounds.size()) * 4 + 64);
+    m.node_off = take((int64_t)m.nodes.size() * sizeof(HssNode));
+    m.arena_off = take(m.arena_n * 8);
+    m.iarena_off = take(m.iarena_n * 4);
+  }
+  void* p;
+  ADC_TRY(c->buffer(slot, (size_t)bytes + 256, &p));
+  hb.mem = (char*)p;
+  hb.d_ms = (HssMerge*)(hb.mem + off_ms);
+  for (auto& m : hb.ms) {
+    char* v = hb.mem + m.vec_off;
+    m.dev.omega = (double*)v;
+    m.dev.phi = m.dev.omega + (int64_t)m.K * m.sp;
+    m.dev.theta = m.dev.phi + (int64_t)m.K * m.sp;
+    int32_t* lo = (int32_t*)(m.dev.theta + (int64_t)m.K * m.sp);
+    m.dev.leafof = lo;
+    m.dev.bounds = lo + m.K;
+    m.dev.nodes = (HssNode*)(hb.mem + m.node_off);
+    m.dev.arena = (double*)(hb.mem + m.arena_off);
+    m.dev.iarena = (int32_t*)(hb.mem + m.iarena_off);
+    m.dev.K = m.K;
+    m.dev.s = m.s;
+    m.dev.sp = m.sp;
+    m.dev.L = m.L;
+  }
+  return ADC_OK;
+}
+
+static adc_status batch_upload(adc_ctx c, HssBatch& hb) {
+  hipStream_t st = c->stream;
+  for (auto& m : hb.ms) {
+    std::vector<int32_t> lo(m.K);
+    for (size_t t = 0; t + 1 < m.bounds.size(); ++t)
+      for (int i = m.bounds[t]; i < m.bounds[t + 1]; ++i) lo[i] = (int32_t)t;
+    HIP_OK(hipMemcpyAsync((void*)m.dev.leafof, lo.data(), m.K * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync((void*)m.dev.bounds, m.bounds.data(), m.bounds.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(m.dev.nodes, m.nodes.data(), m.nodes.size() * sizeof(HssNode), hipMemcpyHostToDevice, st));
+  }
+  std::vector<HssMerge> hm;
+  for (auto& m : hb.ms) hm.push_back(m.dev);
+  HIP_OK(hipMemcpyAsync(hb.d_ms, hm.data(), hm.size() * sizeof(HssMerge), hipMemcpyHostToDevice, st));
+  // the host vectors above are released on return: make the copies complete
+  HIP_OK(hipStreamSynchronize(st));
+  return ADC_OK;
+}
+
+// Sampling and compression of every merge in the batch (omega already drawn).
+static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
+  hipStream_t st = c->stream;
+  const int nm = (int)hb.ms.size();
+  // sampling jobs
+  std::vector<SampleJob> sj;
+  for (int g = 0; g < nm; ++g) {
+    const auto& m = hb.ms[g];
+    for (int r0 = 0; r0 < m.K; r0 += 64)
+      for (int c0 = 0; c0 < m.sp; c0 += 32) sj.push_back(SampleJob{g, r0, c0});
+  }
+  // compression jobs per level
+  int Lmax = 0;
+  for (auto& m : hb.ms) Lmax = std::max(Lmax, m.L);
+  std::vector<std::vector<NodeJob>> lj(Lmax + 1);
+  int ncand_max = 0, sp_max = 0;
+  for (int g = 0; g < nm; ++g) {
+    const auto& m = hb.ms[g];
+    sp_max = std::max(sp_max, m.sp);
+    for (int l = 0; l <= m.L; ++l) {
+      const int first = (1 << l) - 1;
+      for (int q = 0; q < (1 << l); ++q) {
+        const HssNode& nd = m.nodes[first + q];
+        lj[l].push_back(NodeJob{g, first + q, l == 0 ? 1 : 0});
+        const int cand = nd.leaf ? nd.hi - nd.lo : std::min(2 * m.s, nd.hi - nd.lo);
+        if (l > 0) ncand_max = std::max(ncand_max, cand);
+      }
+    }
+  }
+  size_t njobs = sj.size();
+  for (auto& v : lj) njobs += v.size();
+  void* dp;
+  ADC_TRY(c->buffer(SLOT_HSS_JOBS, njobs * 16 + 4096, &dp));
+  char* dj = (char*)dp;
+  std::vector<char> hj(njobs * 16 + 4096);
+  size_t off = 0;
+  auto put = [&](const void* src, size_t n) {
+    const size_t o = off;
+    std::memcpy(hj.data() + off, src, n);
+    off = (off + n + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_sj = put(sj.data(), sj.size() * sizeof(SampleJob));
+  std::vector<size_t> o_lj(Lmax + 1);
+  for (int l = 0; l <= Lmax; ++l) o_lj[l] = put(lj[l].data(), lj[l].size() * sizeof(NodeJob));
+  HIP_OK(hipMemcpyAsync(dj, hj.data(), off, hipMemcpyHostToDevice, st));
+
+  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms,
+                     (const SampleJob*)(dj + o_sj), 0, 1, (const double*)nullptr, (double*)nullptr, 0);
+  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms,
+                     (const SampleJob*)(dj + o_sj), 1, 1, (const double*)nullptr, (double*)nullptr, 0);
+  HIP_OK(hipGetLastError());
+  c->timer.mark(st, 5);
+  int lds = ncand_max * sp_max;
+  if (lds > 15360) lds = 0;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_hss_compress, hipFuncAttributeMaxDynamicSharedMemorySize, 15360 * 8);
+    attr_set = true;
+  }
+  for (int l = Lmax; l >= 0; --l) {
+    if (lj[l].empty()) continue;
+    hipLaunchKernelGGL(k_hss_compress, dim3((unsigned)lj[l].size()), dim3(256), (size_t)lds * 8, st, hb.d_ms,
+                       (const NodeJob*)(dj + o_lj[l]), lds);
+    HIP_OK(hipGetLastError());
+  }
+  c->timer.mark(st, 6);
+  // ranks back to the host
+  for (auto& m : hb.ms)
+    HIP_OK(hipMemcpyAsync(m.nodes.data(), m.dev.nodes, m.nodes.size() * sizeof(HssNode), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  (void)rep;
+  for (auto& m : hb.ms) {
+    m.max_rank = 0;
+    for (size_t i = 1; i < m.nodes.size(); ++i) m.max_rank = std::max({m.max_rank, m.nodes[i].kr, m.nodes[i].kc});
+  }
+  return ADC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 3 for a list of (merge, X, P, output) products.
+struct ApplyJob {
+  int g;              // merge in the batch
+  const double* X;    // P x K, column-major, ld ldx
+  int64_t ldx;
+  int P;
+  double* C;          // output columns: C + colmap[j] * ldc (colmap may be null)
+  int64_t ldc;
+  const int32_t* colmap;
+};
+
+static void push_prob(std::vector<GemmProb>& v, const GemmProb& p) { v.push_back(p); }
+
+static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops) {
+  if (probs.empty()) return ADC_OK;
+  std::vector<GemmProb> narrow, wide;
+  for (auto& p : probs) {
+    if (p.M <= 0 || p.N <= 0) continue;
+    if (flops) *flops += 2.0 * p.M * (double)p.N * (p.K + p.K2);
+    (p.N <= 64 ? narrow : wide).push_back(p);
+  }
+  hipStream_t st = c->stream;
+  for (int pass = 0; pass < 2; ++pass) {
+    auto& L = pass ? wide : narrow;
+    if (L.empty()) continue;
+    const int bn = pass ? 128 : 64;
+    int tiles = 0;
+    for (auto& p : L) {
+      p.tiles_m = (p.M + 127) / 128;
+      p.tile0 = tiles;
+      tiles += p.tiles_m * ((p.N + bn - 1) / bn);
+    }
+    void* dp;
+    ADC_TRY(c->buffer(pass ? SLOT_GEMM_B : SLOT_GEMM_A, L.size() * sizeof(GemmProb) + 256, &dp));
+    HIP_OK(hipMemcpyAsync(dp, L.data(), L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
+    if (pass)
+      hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, st, (const GemmProb*)dp, (int)L.size());
+    else
+      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(256), 0, st, (const GemmProb*)dp, (int)L.size());
+    HIP_OK(hipGetLastError());
+    // the descriptor arrays are host vectors: wait before they are reused
+    HIP_OK(hipStreamSynchronize(st));
+  }
+  return ADC_OK;
+}
+
+static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJob>& jobs, double* flops) {
+  hipStream_t st = c->stream;
+  // storage: per job and level, G (P x sum kr) and F (P x sum kc); leaf D blocks
+  struct Lay {
+    std::vector<int64_t> goff, foff;  // per node: column offset inside its level block
+    std::vector<int64_t> lev_g, lev_f;  // per level: element offset of the level block
+  };
+  std::vector<Lay> lays(jobs.size());
+  int64_t total = 0;
+  std::vector<int2> leafjobs;
+  std::vector<int64_t> doff;
+  std::vector<int64_t> leaf_base(jobs.size());
+  int64_t dtotal = 0;
+  for (size_t t = 0; t < jobs.size(); ++t) {
+    const auto& m = hb.ms[jobs[t].g];
+    Lay& ly = lays[t];
+    const int nn = (int)m.nodes.size();
+    ly.goff.assign(nn, 0);
+    ly.foff.assign(nn, 0);
+    ly.lev_g.assign(m.L + 1, 0);
+    ly.lev_f.assign(m.L + 1, 0);
+    for (int l = 1; l <= m.L; ++l) {
+      int64_t sg = 0, sf = 0;
+      for (int q = (1 << l) - 1; q < (1 << (l + 1)) - 1; ++q) {
+        ly.goff[q] = sg;
+        ly.foff[q] = sf;
+        sg += m.nodes[q].kr;
+        sf += m.nodes[q].kc;
+      }
+      ly.lev_g[l] = total;
+      total += sg * jobs[t].P;
+      ly.lev_f[l] = total;
+      total += sf * jobs[t].P;
+    }
+    leaf_base[t] = (int64_t)leafjobs.size();
+    for (int q = (1 << m.L) - 1; q < (1 << (m.L + 1)) - 1; ++q) {
+      const int mm = m.nodes[q].hi - m.nodes[q].lo;
+      leafjobs.push_back(int2{jobs[t].g, q});
+      doff.push_back(dtotal);
+      dtotal += (int64_t)mm * mm;
+    }
+  }
+  void* wp;
+  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal) * 8 + leafjobs.size() * 16 + 1024, &wp));
+  double* work = (double*)wp;
+  double* dmat = work + total;
+  char* tail = (char*)(dmat + dtotal);
+  int2* d_lj = (int2*)tail;
+  int64_t* d_doff = (int64_t*)(tail + ((leafjobs.size() * sizeof(int2) + 255) & ~(size_t)255));
+  HIP_OK(hipMemcpyAsync(d_lj, leafjobs.data(), leafjobs.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(d_doff, doff.data(), doff.size() * 8, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_hss_dmat, dim3((unsigned)leafjobs.size()), dim3(256), 0, st, hb.d_ms, d_lj, dmat, d_doff);
+  HIP_OK(hipGetLastError());
+
+  int Lmax = 0;
+  for (auto& j : jobs) Lmax = std::max(Lmax, hb.ms[j.g].L);
+  std::vector<GemmProb> probs;
+  auto G = [&](size_t t, int node) {
+    const auto& m = hb.ms[jobs[t].g];
+    int l = 0;
+    while ((1 << (l + 1)) - 1 <= node) ++l;
+    (void)m;
+    return work + lays[t].lev_g[l] + lays[t].goff[node] * jobs[t].P;
+  };
+  auto F = [&](size_t t, int node) {
+    int l = 0;
+    while ((1 << (l + 1)) - 1 <= node) ++l;
+    return work + lays[t].lev_f[l] + lays[t].foff[node] * jobs[t].P;
+  };
+  // upsweep
+  for (int l = Lmax; l >= 1; --l) {
+    probs.clear();
+    for (size_t t = 0; t < jobs.size(); ++t) {
+      const auto& m = hb.ms[jobs[t].g];
+      if (l > m.L) continue;
+      const ApplyJob& J = jobs[t];
+      for (int q = (1 << l) - 1; q < (1 << (l + 1)) - 1; ++q) {
+        const HssNode& nd = m.nodes[q];
+        GemmProb p{};
+        p.M = J.P;
+        p.N = nd.kr;
+        p.C = G(t, q);
+        p.ldc = J.P;
+        p.B = m.dev.arena + nd.offU;
+        p.ldb = nd.nr;
+        if (nd.leaf) {
+          p.A = J.X + (int64_t)nd.lo * J.ldx;
+          p.lda = J.ldx;
+          p.K = nd.hi - nd.lo;
+        } else {
+          p.A = G(t, 2 * q + 1);  // [G_i1 G_i2] are adjacent
+          p.lda = J.P;
+          p.K = m.nodes[2 * q + 1].kr + m.nodes[2 * q + 2].kr;
+        }
+        push_prob(probs, p);
+      }
+    }
+    ADC_TRY(launch_probs(c, probs, flops));
+  }
+  // downsweep: H_i = G_j B_j (+ F_i); then [F_i1 F_i2] = H_i V_i^T
+  for (int l = 1; l <= Lmax; ++l) {
+    probs.clear();
+    for (size_t t = 0; t < jobs.size(); ++t) {
+      const auto& m = hb.ms[jobs[t].g];
+      if (l > m.L) continue;
+      const ApplyJob& J = jobs[t];
+      for (int q = (1 << l) - 1; q < (1 << (l + 1)) - 1; ++q) {
+        const HssNode& nd = m.nodes[q];
+        const int sib = (q & 1) ? q + 1 : q - 1;
+        const HssNode& sj = m.nodes[sib];
+        GemmProb p{};
+        p.M = J.P;
+        p.N = nd.kc;
+        p.K = sj.kr;
+        p.A = G(t, sib);
+        p.lda = J.P;
+        p.B = m.dev.arena + sj.offB;  // kr(sib) x kc(i)
+        p.ldb = std::max(sj.kr, 1);
+        p.C = F(t, q);
+        p.ldc = J.P;
+        p.beta = (l > 1) ? 1.0 : 0.0;
+        push_prob(probs, p);
+      }
+    }
+    ADC_TRY(launch_probs(c, probs, flops));
+    probs.clear();
+    for (size_t t = 0; t < jobs.size(); ++t) {
+      const auto& m = hb.ms[jobs[t].g];
+      if (l >= m.L) continue;
+      const ApplyJob& J = jobs[t];
+      for (int q = (1 << l) - 1; q < (1 << (l + 1)) - 1; ++q) {
+        const HssNode& nd = m.nodes[q];
+        GemmProb p{};
+        p.M = J.P;
+        p.N = nd.nc;  // kc(i1) + kc(i2)
+        p.K = nd.kc;
+        p.A = F(t, q);
+        p.lda = J.P;
+        p.B = m.dev.arena + nd.offV;  // nc x kc, read transposed
+        p.ldb = std::max(nd.nc, 1);
+        p.transB = 1;
+        p.C = F(t, 2 * q + 1);
+        p.ldc = J.P;
+        push_prob(probs, p);
+      }
+    }
+    ADC_TRY(launch_probs(c, probs, flops));
+  }
+  // leaves: out(:, t_i) = X(:, t_i) D_i + H_i V_i^T
+  probs.clear();
+  for (size_t t = 0; t < jobs.size(); ++t) {
+    const auto& m = hb.ms[jobs[t].g];
+    const ApplyJob& J = jobs[t];
+    int li = 0;
+    for (int q = (1 << m.L) - 1; q < (1 << (m.L + 1)) - 1; ++q, ++li) {
+      const HssNode& nd = m.nodes[q];
+      const int mm = nd.hi - nd.lo;
+      GemmProb p{};
+      p.M = J.P;
+      p.N = mm;
+      p.K = mm;
+      p.A = J.X + (int64_t)nd.lo * J.ldx;
+      p.lda = J.ldx;
+      p.B = dmat + doff[leaf_base[t] + li];
+      p.ldb = mm;
+      if (m.L > 0) {
+        p.K2 = nd.kc;
+        p.A2 = F(t, q);
+        p.lda2 = J.P;
+        p.B2 = m.dev.arena + nd.offV;  // mm x kc, read transposed
+        p.ldb2 = mm;
+        p.transB2 = 1;
+      }
+      if (J.colmap) {
+        p.C = J.C;
+        p.colmap = J.colmap + nd.lo;
+      } else {
+        p.C = J.C + (int64_t)nd.lo * J.ldc;
+      }
+      p.ldc = J.ldc;
+      push_prob(probs, p);
+    }
+  }
+  ADC_TRY(launch_probs(c, probs, flops));
+  return ADC_OK;
+}
+
+// Draw Omega for merge g of the batch (stream id of the merge, 2*id).
+static void draw_omega(adc_ctx c, const HssBatch::One& m, uint64_t seed) {
+  const int64_t n = (int64_t)m.K * m.sp;
+  hipLaunchKernelGGL(k_philox_normal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, m.dev.omega,
+                     (int64_t)m.K, m.s, m.sp, seed, 2u * m.stream);
+}
+
+// Accuracy check of every merge: err = ||W^T (Q' - H)||_F / ||W^T Q'||_F for
+// nprobe Gaussian probes (stream 2*id + 1).
+static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double* flops) {
+  hipStream_t st = c->stream;
+  const int nm = (int)hb.ms.size();
+  int64_t tot = 0;
+  std::vector<int64_t> base(nm);
+  for (int g = 0; g < nm; ++g) {
+    base[g] = tot;
+    tot += 3 * (int64_t)hb.ms[g].K * SP_PROBE;
+  }
+  void* p;
+  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)tot * 8 + nm * 16 + 1024, &p));
+  double* buf = (double*)p;
+  double* norms = buf + tot;
+  std::vector<SampleJob> sj;
+  std::vector<ApplyJob> aj;
+  for (int g = 0; g < nm; ++g) {
+    auto& m = hb.ms[g];
+    double* W = buf + base[g];
+    double* WQ = W + (int64_t)m.K * SP_PROBE;
+    double* WH = WQ + (int64_t)m.K * SP_PROBE;
+    const int64_t n = (int64_t)m.K * SP_PROBE;
+    hipLaunchKernelGGL(k_philox_normal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, (int64_t)m.K,
+                       o.nprobe, SP_PROBE, o.seed, 2u * m.stream + 1u);
+    aj.push_back(ApplyJob{g, W, SP_PROBE, SP_PROBE, WH, SP_PROBE, nullptr});
+  }
+  // W^T Q' per merge (sampling kernel, transposed, no exclusion)
+  for (int g = 0; g < nm; ++g) {
+    auto& m = hb.ms[g];
+    sj.clear();
+    for (int r0 = 0; r0 < m.K; r0 += 64) sj.push_back(SampleJob{g, r0, 0});
+    void* dp;
+    ADC_TRY(c->buffer(SLOT_HSS_JOBS, sj.size() * sizeof(SampleJob) + 256, &dp));
+    HIP_OK(hipMemcpyAsync(dp, sj.data(), sj.size() * sizeof(SampleJob), hipMemcpyHostToDevice, st));
+    double* W = buf + base[g];
+    double* WQ = W + (int64_t)m.K * SP_PROBE;
+    hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms, (const SampleJob*)dp, 1, 0,
+                       (const double*)W, WQ, SP_PROBE);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+  }
+  ADC_TRY(batch_apply(c, hb, aj, flops));
+  for (int g = 0; g < nm; ++g) {
+    double* W = buf + base[g];
+    double* WQ = W + (int64_t)hb.ms[g].K * SP_PROBE;
+    double* WH = WQ + (int64_t)hb.ms[g].K * SP_PROBE;
+    hipLaunchKernelGGL(k_diff_norms, dim3(1), dim3(1024), 0, st, WH, WQ, (int64_t)hb.ms[g].K * SP_PROBE,
+                       norms + 2 * g);
+  }
+  std::vector<double> hn(2 * nm);
+  HIP_OK(hipMemcpyAsync(hn.data(), norms, 2 * nm * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int g = 0; g < nm; ++g) {
+    auto& m = hb.ms[g];
+    m.err = (hn[2 * g + 1] > 0.0) ? std::sqrt(hn[2 * g] / hn[2 * g + 1]) : 0.0;
+    const bool saturated = (m.max_rank >= m.s) && (m.s < m.K);
+    m.pass = std::isfinite(m.err) && m.err <= o.check_tol && !saturated;
+  }
+  return ADC_OK;
+}
+
+// Build (construct + check + retries) for a batch whose merges have K, L,
+// bounds, r and stream set.  gens[g] = device generators (d, gam, mu, uh, v).
+static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool check, adc_report* rep,
+                              double* flops, const std::vector<const double*>* omega_given) {
+  for (auto& m : hb.ms) {
+    m.s = std::min({m.K, m.r + o.oversample, S_MAX});
+    m.s = std::max(m.s, 1);
+    m.sp = (m.s + 31) / 32 * 32;
+    m.retries = 0;
+  }
+  for (int attempt = 0;; ++attempt) {
+    ADC_TRY(batch_alloc(c, hb, SLOT_HSS));
+    ADC_TRY(batch_upload(c, hb));
+    for (size_t g = 0; g < hb.ms.size(); ++g) {
+      auto& m = hb.ms[g];
+      if (omega_given && (*omega_given)[g]) {
+        // caller's K x s row-major Omega into the padded layout
+        HIP_OK(hipMemset2DAsync(m.dev.omega, m.sp * 8, 0, m.sp * 8, m.K, c->stream));
+        HIP_OK(hipMemcpy2DAsync(m.dev.omega, m.sp * 8, (*omega_given)[g], m.s * 8, m.s * 8, m.K,
+                                hipMemcpyDeviceToDevice, c->stream));
+      } else {
+        draw_omega(c, m, o.seed);
+      }
+    }
+    HIP_OK(hipGetLastError());
+    ADC_TRY(batch_construct(c, hb, rep));
+    if (!check) {
+      for (auto& m : hb.ms) m.pass = true;
+      return ADC_OK;
+    }
+    ADC_TRY(batch_check(c, hb, o, flops));
+    c->timer.mark(c->stream, 7);
+    bool all = true;
+    for (auto& m : hb.ms) all = all && m.pass;
+    if (all || attempt >= o.max_retries) return ADC_OK;
+    // double the samples of the failing merges and rebuild the batch
+    for (auto& m : hb.ms) {
+      if (!m.pass && m.s < std::min(m.K, S_MAX)) {
+        m.s = std::min({2 * m.s, m.K, S_MAX});
+        m.sp = (m.s + 31) / 32 * 32;
+        m.retries++;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
+                            const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes) {
+  (void)bytes;
+  hipStream_t st = c->stream;
+  HssBatch hb;
+  std::vector<int> which;
+  for (int g = 0; g < nm; ++g)
+    if (h_m[g].mode == 1) which.push_back(g);
+  if (which.empty()) return ADC_OK;
+  for (size_t t = 0; t < which.size(); ++t) {
+    const MergeDev& M = h_m[which[t]];
+    HssBatch::One m;
+    m.K = M.K;
+    m.L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
+    m.bounds = balanced_bounds(M.K, m.L);
+    m.stream = (uint32_t)((depth << 20) + which[t]);
+    std::vector<double> d(M.K), g2(M.K), mu(M.K);
+    HIP_OK(hipMemcpyAsync(d.data(), B.dS + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(g2.data(), B.gam + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(mu.data(), B.mu + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    m.r = hss_rank_estimate(d.data(), g2.data(), mu.data(), M.K, m.bounds, o);
+    if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
+    if (o.rank_mode == ADC_RANK_MLP) m.r = mlp_rank(c, d.data(), g2.data(), mu.data(), M.K, m.bounds, o, m.r);
+    m.dev.d = B.dS + M.s0;
+    m.dev.gam = B.gam + M.s0;
+    m.dev.mu = B.mu + M.s0;
+    m.dev.uh = B.uh + M.s0;
+    m.dev.v = B.v + M.s0;
+    m.dev.id_tol = o.id_tol;
+    hb.ms.push_back(m);
+  }
+  ADC_TRY(batch_build(c, hb, o, true, rep, flops, nullptr));
+  std::vector<ApplyJob> aj;
+  std::vector<int> dense_fb;
+  for (size_t t = 0; t < which.size(); ++t) {
+    const MergeDev& M = h_m[which[t]];
+    auto& m = hb.ms[t];
+    if (rep) {
+      rep->retries += m.retries;
+      rep->max_rank = std::max(rep->max_rank, m.max_rank);
+      rep->samples = std::max(rep->samples, m.s);
+      if (m.pass) rep->check_err_max = std::max(rep->check_err_max, m.err);
+    }
+    if (m.pass) {
+      aj.push_back(ApplyJob{(int)t, B.pk + M.zoff, (int64_t)M.n, M.n, B.Znew + M.s0 + M.s0 * B.ldn, B.ldn,
+                            B.posR + M.s0});
+    } else {
+      dense_fb.push_back(which[t]);
+      if (rep) rep->hss_fallbacks++;
+    }
+  }
+  if (!dense_fb.empty() && o.strict) return ADC_ERR_ACCURACY;
+  double fm = 0.0;
+  ADC_TRY(batch_apply(c, hb, aj, &fm));
+  c->timer.mark(st, 8);
+  if (flops) *flops += fm;
+  if (rep) {
+    rep->phase_flops[8] += fm;
+    rep->phase_launches[8] += 1;
+  }
+  // dense fallback: the packed columns are in pole order, so one product
+  // pk (n x K) * Cauchy (K x K) per merge
+  for (int g : dense_fb) ADC_TRY(dense_sorted_update(c, d_m, g, h_m[g], B, flops));
+  return ADC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: build / apply / info / free
+extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const double* gam, const double* mu,
+                                    const double* uh, const double* v, const double* omega, int32_t s,
+                                    const adc_opts* opts_in, adc_hss* out) {
+  if (!c || !out || K < 2 || K > (1 << 24) || !d || !gam || !mu || !uh || !v) return ADC_ERR_ARG;
+  *out = nullptr;
+  adc_opts o;
+  if (opts_in) o = *opts_in;
+  else adc_opts_default(&o);
+  ADC_TRY(validate_opts_ext(o));
+  if (omega && (s < 1 || s > S_MAX)) return ADC_ERR_ARG;
+  DeviceGuard gd(c->device);
+  hipStream_t st = c->stream;
+  adc_hss h = new (std::nothrow) adc_hss_s();
+  if (!h) return ADC_ERR_NOMEM;
+  h->ctx = c;
+  h->K = (int)K;
+  // own copies of the generators
+  if (hipMalloc(&h->gen, 5 * K * 8) != hipSuccess) {
+    delete h;
+    return ADC_ERR_NOMEM;
+  }
+  const double* src[5] = {d, gam, mu, uh, v};
+  for (int i = 0; i < 5; ++i)
+    HIP_OK(hipMemcpyAsync(h->gen + i * K, src[i], K * 8, hipMemcpyDeviceToDevice, st));
+  HssBatch hb;
+  HssBatch::One m;
+  m.K = (int)K;
+  m.L = std::max(1, ceil_log2_ratio((int)K, o.hss_leaf));
+  m.bounds = balanced_bounds((int)K, m.L);
+  std::vector<double> hd(K), hg(K), hm(K);
+  HIP_OK(hipMemcpyAsync(hd.data(), d, K * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hg.data(), gam, K * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hm.data(), mu, K * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  m.r = hss_rank_estimate(hd.data(), hg.data(), hm.data(), (int)K, m.bounds, o);
+  if (omega) m.r = std::max(0, s - o.oversample);
+  else if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
+  m.stream = 0;
+  m.dev.d = h->gen;
+  m.dev.gam = h->gen + K;
+  m.dev.mu = h->gen + 2 * K;
+  m.dev.uh = h->gen + 3 * K;
+  m.dev.v = h->gen + 4 * K;
+  m.dev.id_tol = o.id_tol;
+  hb.ms.push_back(m);
+  std::vector<const double*> om{omega};
+  adc_status sres = batch_build(c, hb, o, omega == nullptr, nullptr, nullptr, omega ? &om : nullptr);
+  if (sres != ADC_OK) {
+    hipFree(h->gen);
+    delete h;
+    return sres;
+  }
+  if (omega) {
+    // the caller chose s: use exactly that many samples
+  }
+  // move the batch memory into the handle (the context slot is reused later)
+  HssBatch::One& mm = hb.ms[0];
+  const size_t bytes = (size_t)((char*)(mm.dev.iarena + mm.iarena_n) - hb.mem) + 256;
+  if (hipMalloc(&h->mem, bytes) != hipSuccess) {
+    hipFree(h->gen);
+    delete h;
+    return ADC_ERR_NOMEM;
+  }
+  HIP_OK(hipMemcpyAsync(h->mem, hb.mem, bytes, hipMemcpyDeviceToDevice, st));
+  const ptrdiff_t shift = (char*)h->mem - hb.mem;
+  auto mv = [&](auto* p) { return (decltype(p))((char*)p + shift); };
+  h->dev = mm.dev;
+  h->dev.omega = mv(mm.dev.omega);
+  h->dev.phi = mv(mm.dev.phi);
+  h->dev.theta = mv(mm.dev.theta);
+  h->dev.leafof = mv(mm.dev.leafof);
+  h->dev.bounds = mv(mm.dev.bounds);
+  h->dev.nodes = mv(mm.dev.nodes);
+  h->dev.arena = mv(mm.dev.arena);
+  h->dev.iarena = mv(mm.dev.iarena);
+  h->d_merge = mv(hb.d_ms);
+  HIP_OK(hipMemcpyAsync(h->d_merge, &h->dev, sizeof(HssMerge), hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  h->nodes = mm.nodes;
+  h->L = mm.L;
+  h->s = mm.s;
+  h->retries = mm.retries;
+  h->max_rank = mm.max_rank;
+  h->check_err = mm.err;
+  h->dense_fallback = !mm.pass;
+  h->bounds = mm.bounds;
+  *out = h;
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_hss_apply(adc_ctx c, adc_hss h, int64_t P, const double* X, int64_t ldx, double* Y,
+                                    int64_t ldy) {
+  if (!c || !h || P < 0 || P > INT32_MAX || !X || !Y || ldx < P || ldy < P) return ADC_ERR_ARG;
+  if (P == 0) return ADC_OK;
+  DeviceGuard gd(c->device);
+  HssBatch hb;
+  HssBatch::One m;
+  m.K = h->K;
+  m.L = h->L;
+  m.s = h->s;
+  m.nodes = h->nodes;
+  m.dev = h->dev;
+  m.bounds = h->bounds;
+  hb.ms.push_back(m);
+  hb.d_ms = h->d_merge;
+  std::vector<ApplyJob> aj{ApplyJob{0, X, ldx, (int)P, Y, ldy, nullptr}};
+  ADC_TRY(batch_apply(c, hb, aj, nullptr));
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_hss_info(adc_hss h, int32_t* levels, int32_t* leaves, int32_t* max_rank, int32_t* samples,
+                                   int32_t* retries, double* check_err) {
+  if (!h) return ADC_ERR_ARG;
+  if (levels) *levels = h->L;
+  if (leaves) *leaves = 1 << h->L;
+  if (max_rank) *max_rank = h->max_rank;
+  if (samples) *samples = h->s;
+  if (retries) *retries = h->retries;
+  if (check_err) *check_err = h->check_err;
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_hss_nodes(adc_hss h, int32_t nmax, int32_t* lo, int32_t* hi, int32_t* kr, int32_t* kc,
+                                    int32_t* count) {
+  if (!h || nmax < 0) return ADC_ERR_ARG;
+  const int n = (int)h->nodes.size();
+  for (int i = 0; i < std::min(n, (int)nmax); ++i) {
+    if (lo) lo[i] = h->nodes[i].lo;
+    if (hi) hi[i] = h->nodes[i].hi;
+    if (kr) kr[i] = h->nodes[i].kr;
+    if (kc) kc[i] = h->nodes[i].kc;
+  }
+  if (count) *count = n;
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_hss_free(adc_hss h) {
+  if (!h) return ADC_ERR_ARG;
+  DeviceGuard gd(h->ctx->device);
+  hipStreamSynchronize(h->ctx->stream);
+  if (h->mem) hipFree(h->mem);
+  if (h->gen) hipFree(h->gen);
+  delete h;
+  return ADC_OK;
+}

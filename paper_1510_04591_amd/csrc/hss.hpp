@@ -1,10 +1,78 @@
-// HSS update of one DC level (Algorithms 2 and 3 on gfx950).
+// Randomized HSS approximation of the Cauchy-like eigenvector matrix
+// (Algorithm 2) and its product from the right (Algorithm 3) on gfx950.
 #pragma once
 #include "adc_internal.hpp"
 
-// Update every merge of the level whose mode is 1 (HSS): rank estimate,
-// Gaussian sampling, level-by-level interpolative compression, adaptive
-// check, and the HSS product U_K * H written to the merged block.  Merges
-// that fail the check fall back to the dense Cauchy update.
+// One HSS tree node (heap numbering inside its merge: root 0, children of p
+// at 2p+1 and 2p+2; level l holds nodes 2^l - 1 .. 2^(l+1) - 2).
+struct HssNode {
+  int32_t lo, hi;      // index range t_i in [0, K)
+  int32_t leaf;        // 1 for a leaf
+  int32_t kr, kc;      // row / column ranks (written by the compression)
+  int32_t nr, nc;      // candidate rows / columns of the IDs (written)
+  int64_t offU, offV;  // U_i (nr x kr) and V_i (nc x kc), column-major, in the arena
+  int64_t offB;        // B_i = A(skel_r(i), skel_c(sibling)), kr x kc(sib), column-major
+  int64_t offSr, offSc;  // skeleton index lists (int32) in the index arena
+  int64_t offPs, offTs;  // Phi_i|skel (kr x s) and Theta_i|skel (kc x s), row-major
+  int64_t offYh, offZh;  // Yhat_i (kc x s) and Zhat_i (kr x s), row-major
+  int64_t offWork;     // scratch: the node's Phi_i / Theta_i before the ID (cand x s)
+};
+
+// One HSS merge on the device.
+struct HssMerge {
+  int32_t K, s, sp;    // size, samples, padded sample count (multiple of 32)
+  int32_t L;           // levels below the root
+  const double* d;     // generators (length K)
+  const double* gam;
+  const double* mu;
+  const double* uh;
+  const double* v;
+  const int32_t* leafof;  // leaf number of every index
+  const int32_t* bounds;  // leaf boundaries (2^L + 1)
+  double* omega;       // K x sp Gaussian, row-major
+  double* phi;         // K x sp leaf row samples, row-major
+  double* theta;       // K x sp leaf column samples, row-major
+  HssNode* nodes;      // 2^(L+1) - 1 nodes
+  double* arena;       // generator and work storage
+  int32_t* iarena;     // skeleton index storage
+  double id_tol;
+};
+
+// Host-side view of a built HSS matrix (adc_hss handle).
+struct adc_hss_s {
+  adc_ctx ctx = nullptr;
+  int K = 0, L = 0, s = 0, retries = 0, max_rank = 0;
+  double check_err = 0.0;
+  bool dense_fallback = false;
+  std::vector<HssNode> nodes;       // host copy (ranks, offsets)
+  void* mem = nullptr;              // device allocation owning everything below
+  HssMerge dev{};                   // device pointers
+  HssMerge* d_merge = nullptr;      // device copy of dev
+  double* gen = nullptr;            // generator copies (d, gam, mu, uh, v)
+  std::vector<int> bounds;          // leaf boundaries
+};
+
+// kernels
+__global__ void k_philox_normal(double* __restrict__ out, int64_t K, int s, int sp, uint64_t seed,
+                                uint32_t stream);
+struct SampleJob {
+  int32_t merge;
+  int32_t r0;   // first output row
+  int32_t c0;   // first sample column (multiple of 32)
+};
+__global__ void k_hss_sample(const HssMerge* __restrict__ ms, const SampleJob* __restrict__ jobs, int trans,
+                             int exclude_diag, const double* __restrict__ omega_override,
+                             double* __restrict__ out_override, int sp_override);
+struct NodeJob {
+  int32_t merge;
+  int32_t node;  // heap index
+  int32_t root;  // 1: only generate the children's B blocks
+};
+__global__ void k_hss_compress(const HssMerge* __restrict__ ms, const NodeJob* __restrict__ jobs, int lds_doubles);
+__global__ void k_hss_dmat(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
+                           double* __restrict__ dmat, const int64_t* __restrict__ doff);
+__global__ void k_diff_norms(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                             double* __restrict__ out2);
+
 adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
                             const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes);

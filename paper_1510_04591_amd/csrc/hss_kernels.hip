@@ -1,0 +1,504 @@
+// Device kernels of the randomized HSS construction (Algorithm 2), of the
+// Gaussian sampling matrices and of the accuracy check.
+//
+// k_philox_normal  Omega, standard normal by Philox4x32-10 (Salmon et al.
+//                  2011) and the Box-Muller transform; element (i, c) is normal
+//                  number i*s + c of the stream.
+// k_hss_sample     Y = A Omega and Z = A^T Omega restricted to the HSS block
+//                  rows / columns of the leaves, i.e. Phi_i = Y_i - D_i Omega_i
+//                  and Theta_i = Z_i - D_i^T Omega_i of Algorithm 2 computed
+//                  without forming D_i Omega_i: the entries of the leaf's own
+//                  diagonal block are skipped.  A = Q' is never stored: every
+//                  16 x 4 operand fragment of v_mfma_f64_16x16x4f64 is generated
+//                  in registers from the generators (eq. Ev-Q, differences by
+//                  eq. d-lambda), Omega tiles are staged in LDS.
+// k_hss_compress   one workgroup per tree node and level: the compressed block
+//                  row Phi_i and column Theta_i (leaves from the samples,
+//                  parents from the children as in Algorithm 2), their
+//                  interpolative decompositions by column-pivoted Householder
+//                  QR truncated at |R_kk| <= tol |R_11|, the generators U_i,
+//                  V_i, B of the children, and Yhat_i, Zhat_i.
+// k_hss_dmat       the leaf diagonal blocks D_i = A(t_i, t_i) for Algorithm 3.
+#include "hss.hpp"
+
+namespace {
+
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Q'(i, j) = uh_i v_j / (d_i - lam_j)
+__device__ __forceinline__ double cauchy_entry(int i, int j, double di, double ui, double dj, double dj1, double gj,
+                                               double mj, double vj) {
+  return ui * vj / d_minus_lam(i, j, di, dj, dj1, gj, mj);
+}
+
+__device__ __forceinline__ double gen_entry(const HssMerge& M, int i, int j) {
+  const double dj1 = (j + 1 < M.K) ? M.d[j + 1] : 0.0;
+  return cauchy_entry(i, j, M.d[i], M.uh[i], M.d[j], dj1, M.gam[j], M.mu[j], M.v[j]);
+}
+
+}  // namespace
+
+__global__ void k_philox_normal(double* __restrict__ out, int64_t K, int s, int sp, uint64_t seed,
+                                uint32_t stream) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= K * sp) return;
+  const int64_t i = idx / sp;
+  const int c = (int)(idx % sp);
+  if (c >= s) {
+    out[idx] = 0.0;
+    return;
+  }
+  const uint64_t e = (uint64_t)i * (uint64_t)s + (uint64_t)c;
+  const uint64_t ctr = e >> 1;
+  uint32_t x[4] = {(uint32_t)ctr, (uint32_t)(ctr >> 32), stream, 0u};
+  philox10(x, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double u1 = ((double)(x[0] >> 5) * 67108864.0 + (double)(x[1] >> 6)) * 0x1.0p-53;
+  const double u2 = ((double)(x[2] >> 5) * 67108864.0 + (double)(x[3] >> 6)) * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(1.0 - u1));
+  const double th = 6.283185307179586 * u2;
+  out[idx] = (e & 1ull) ? r * sin(th) : r * cos(th);
+}
+
+// ---------------------------------------------------------------------------
+// sampling: rows r0..r0+63 (16 per wave) x columns c0..c0+31 of the output
+__global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__ ms,
+                                                    const SampleJob* __restrict__ jobs, int trans, int exclude_diag,
+                                                    const double* __restrict__ omega_override,
+                                                    double* __restrict__ out_override, int sp_override) {
+  constexpr int JT = 64;
+  __shared__ double s_om[JT][33];
+  __shared__ double s_g0[JT + 1], s_g1[JT], s_g2[JT], s_g3[JT];
+  const SampleJob jb = jobs[blockIdx.x];
+  const HssMerge& M = ms[jb.merge];
+  const int K = M.K;
+  const int sp = sp_override > 0 ? sp_override : M.sp;
+  const double* __restrict__ om = omega_override ? omega_override : M.omega;
+  double* __restrict__ out = out_override ? out_override : (trans ? M.theta : M.phi);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rr = jb.r0 + wv * 16 + li;  // this lane's output row
+  const bool rvalid = rr < K;
+  int lo_r = 0, hi_r = 0;
+  double rd = 0.0, rd1 = 0.0, rg = 0.0, rm = 0.0, ru = 0.0, rv = 0.0;
+  if (rvalid) {
+    if (exclude_diag) {
+      const int lf = M.leafof[rr];
+      lo_r = M.bounds[lf];
+      hi_r = M.bounds[lf + 1];
+    }
+    rd = M.d[rr];
+    if (trans) {  // the row of the output is a column j of Q'
+      rd1 = (rr + 1 < K) ? M.d[rr + 1] : 0.0;
+      rg = M.gam[rr];
+      rm = M.mu[rr];
+      rv = M.v[rr];
+    } else {
+      ru = M.uh[rr];
+    }
+  }
+  dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
+  for (int q0 = 0; q0 < K; q0 += JT) {
+    __syncthreads();
+    for (int e = tid; e < JT * 32; e += 256) {
+      const int qr = e >> 5, cc = e & 31;
+      const int q = q0 + qr, c = jb.c0 + cc;
+      s_om[qr][cc] = (q < K && c < sp) ? om[(int64_t)q * sp + c] : 0.0;
+    }
+    if (tid < JT) {
+      const int q = q0 + tid;
+      if (q < K) {
+        s_g0[tid] = M.d[q];
+        if (trans) {
+          s_g1[tid] = M.uh[q];
+        } else {
+          s_g1[tid] = M.gam[q];
+          s_g2[tid] = M.mu[q];
+          s_g3[tid] = M.v[q];
+        }
+      } else {
+        s_g0[tid] = 0.0;
+        s_g1[tid] = s_g2[tid] = s_g3[tid] = 0.0;
+      }
+    }
+    if (tid == 0) s_g0[JT] = (q0 + JT < K) ? M.d[q0 + JT] : 0.0;
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < JT / 4; ++kk) {
+      const int ql = kk * 4 + lk;
+      const int q = q0 + ql;
+      double a = 0.0;
+      if (rvalid && q < K && !(q >= lo_r && q < hi_r)) {
+        if (trans) {
+          // Q'(q, rr): i = q (inner), j = rr
+          a = cauchy_entry(q, rr, s_g0[ql], s_g1[ql], rd, rd1, rg, rm, rv);
+        } else {
+          // Q'(rr, q): i = rr, j = q
+          const double dq1 = (q + 1 < K) ? s_g0[ql + 1] : 0.0;
+          a = cauchy_entry(rr, q, rd, ru, s_g0[ql], dq1, s_g1[ql], s_g2[ql], s_g3[ql]);
+        }
+      }
+      const double b0 = s_om[ql][li];
+      const double b1 = s_om[ql][16 + li];
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[1], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = jb.c0 + 16 * t + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = jb.r0 + wv * 16 + lk + 4 * r;
+      if (row < K && col < sp) out[(int64_t)row * sp + col] = acc[t][r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column interpolative decomposition of A (m x n, column-major, ld lda) by
+// column-pivoted Householder QR (pivot: largest remaining norm, recomputed
+// every step; ties to the smaller index), stopped when that norm is <= tol
+// times the first one.  On return A[0:k, k:n] = R11^-1 R12 and perm lists the
+// chosen columns first.  All threads of the block take part.
+namespace {
+constexpr int CMAX = 1024;  // candidates
+constexpr int SMAX = 512;   // samples
+
+__device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
+                       double* redv, int* redi) {
+  const int tid = threadIdx.x;
+  __shared__ int s_stop;
+  __shared__ double s_r11, s_alpha, s_vn2;
+  for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
+  const int kmax = min(m, n);
+  int k = 0;
+  for (; k < kmax; ++k) {
+    // remaining column norms and the pivot
+    double best = -1.0;
+    int bi = n;
+    for (int c = k + tid; c < n; c += blockDim.x) {
+      double s2 = 0.0;
+      const double* col = A + (int64_t)c * lda;
+      for (int r = k; r < m; ++r) s2 += col[r] * col[r];
+      nrm[c] = s2;
+      if (s2 > best) {
+        best = s2;
+        bi = c;
+      }
+    }
+    redv[tid] = best;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double ov = redv[tid + st];
+        const int oi = redi[tid + st];
+        if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) {
+          redv[tid] = ov;
+          redi[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = redi[0];
+    const double pn = sqrt(fmax(redv[0], 0.0));
+    if (tid == 0) {
+      if (k == 0) s_r11 = pn;
+      s_stop = (p >= n) || (pn == 0.0) || (pn <= tol * s_r11);
+    }
+    __syncthreads();
+    if (s_stop) break;
+    if (p != k) {
+      for (int r = tid; r < m; r += blockDim.x) {
+        const double t = A[r + (int64_t)k * lda];
+        A[r + (int64_t)k * lda] = A[r + (int64_t)p * lda];
+        A[r + (int64_t)p * lda] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[k];
+        perm[k] = perm[p];
+        perm[p] = t;
+      }
+    }
+    __syncthreads();
+    // Householder vector v = x - alpha e_1, alpha = -sign(x_0) ||x||
+    if (tid == 0) {
+      const double x0 = A[k + (int64_t)k * lda];
+      s_alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int r = k + tid; r < m; r += blockDim.x) {
+      double x = A[r + (int64_t)k * lda];
+      if (r == k) x -= s_alpha;
+      vv[r] = x;
+      part += x * x;
+    }
+    redv[tid] = part;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (tid < st) redv[tid] += redv[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) s_vn2 = redv[0];
+    __syncthreads();
+    const double vn2 = s_vn2;
+    if (vn2 > 0.0) {
+      for (int c = k + 1 + tid; c < n; c += blockDim.x) {
+        double* col = A + (int64_t)c * lda;
+        double dot = 0.0;
+        for (int r = k; r < m; ++r) dot += vv[r] * col[r];
+        const double f = 2.0 * dot / vn2;
+        for (int r = k; r < m; ++r) col[r] -= f * vv[r];
+      }
+    }
+    __syncthreads();
+    for (int r = k + tid; r < m; r += blockDim.x) A[r + (int64_t)k * lda] = (r == k) ? s_alpha : 0.0;
+    __syncthreads();
+  }
+  // T = R11^-1 R12 in place
+  for (int c = k + tid; c < n; c += blockDim.x) {
+    double* col = A + (int64_t)c * lda;
+    for (int r = k - 1; r >= 0; --r) {
+      double x = col[r];
+      for (int j = r + 1; j < k; ++j) x -= A[r + (int64_t)j * lda] * col[j];
+      col[r] = x / A[r + (int64_t)r * lda];
+    }
+  }
+  __syncthreads();
+  return k;
+}
+
+// Write U (n x k, column-major, ld n): rows perm[j] (j < k) are e_j, rows
+// perm[c] (c >= k) are T(:, c)^T.
+__device__ void write_interp(const double* A, int lda, int n, int k, const int* perm, int* inv, double* U) {
+  const int tid = threadIdx.x;
+  for (int c = tid; c < n; c += blockDim.x) inv[perm[c]] = c;
+  __syncthreads();
+  for (int e = tid; e < n * k; e += blockDim.x) {
+    const int row = e % n, j = e / n;
+    const int pos = inv[row];
+    double x;
+    if (pos < k) x = (pos == j) ? 1.0 : 0.0;
+    else x = A[j + (int64_t)pos * lda];
+    U[row + (int64_t)j * n] = x;
+  }
+  __syncthreads();
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict__ ms,
+                                                      const NodeJob* __restrict__ jobs, int lds_doubles) {
+  extern __shared__ double dyn[];
+  __shared__ double s_nrm[CMAX];
+  __shared__ int s_perm[CMAX];
+  __shared__ int s_inv[CMAX];
+  __shared__ int s_cand[CMAX];
+  __shared__ double s_vv[SMAX];
+  __shared__ double s_redv[256];
+  __shared__ int s_redi[256];
+
+  const NodeJob jb = jobs[blockIdx.x];
+  const HssMerge& M = ms[jb.merge];
+  HssNode* nodes = M.nodes;
+  HssNode& nd = nodes[jb.node];
+  const int tid = threadIdx.x;
+  const int s = M.s, sp = M.sp;
+  double* ar = M.arena;
+  int* ia = M.iarena;
+
+  // B blocks of the children: B_{i1} = A(skel_r(i1), skel_c(i2)), B_{i2} likewise
+  if (!nd.leaf) {
+    HssNode& a = nodes[2 * jb.node + 1];
+    HssNode& b = nodes[2 * jb.node + 2];
+    const int* sra = ia + a.offSr;
+    const int* sca = ia + a.offSc;
+    const int* srb = ia + b.offSr;
+    const int* scb = ia + b.offSc;
+    double* Ba = ar + a.offB;
+    double* Bb = ar + b.offB;
+    for (int e = tid; e < a.kr * b.kc; e += blockDim.x) {
+      const int r = e % a.kr, q = e / a.kr;
+      Ba[e] = gen_entry(M, sra[r], scb[q]);
+    }
+    for (int e = tid; e < b.kr * a.kc; e += blockDim.x) {
+      const int r = e % b.kr, q = e / b.kr;
+      Bb[e] = gen_entry(M, srb[r], sca[q]);
+    }
+    __syncthreads();
+  }
+  if (jb.root) return;
+
+  for (int side = 0; side < 2; ++side) {  // 0: rows (Phi, U), 1: columns (Theta, V)
+    // candidates and the compressed block (cand x sp, row-major) in the work area
+    double* W0 = ar + nd.offWork;
+    int nc;
+    if (nd.leaf) {
+      nc = nd.hi - nd.lo;
+      const double* src = side ? M.theta : M.phi;
+      for (int e = tid; e < nc * sp; e += blockDim.x) W0[e] = src[(int64_t)nd.lo * sp + e];
+      for (int c = tid; c < nc; c += blockDim.x) s_cand[c] = nd.lo + c;
+    } else {
+      const HssNode& a = nodes[2 * jb.node + 1];
+      const HssNode& b = nodes[2 * jb.node + 2];
+      const int ka = side ? a.kc : a.kr, kb = side ? b.kc : b.kr;
+      nc = ka + kb;
+      const int* la = ia + (side ? a.offSc : a.offSr);
+      const int* lb = ia + (side ? b.offSc : b.offSr);
+      for (int c = tid; c < nc; c += blockDim.x) s_cand[c] = (c < ka) ? la[c] : lb[c - ka];
+      // side 0: [Phi_a|sk - B_a Yhat_b ; Phi_b|sk - B_b Yhat_a]
+      // side 1: [Theta_a|sk - B_b^T Zhat_b ; Theta_b|sk - B_a^T Zhat_a]
+      for (int e = tid; e < nc * sp; e += blockDim.x) {
+        const int r = e / sp, col = e % sp;
+        double x = 0.0;
+        if (col < s) {
+          if (side == 0) {
+            if (r < ka) {
+              x = ar[a.offPs + (int64_t)r * sp + col];
+              const double* Ba = ar + a.offB;  // ka x b.kc
+              for (int q = 0; q < b.kc; ++q) x -= Ba[r + (int64_t)q * ka] * ar[b.offYh + (int64_t)q * sp + col];
+            } else {
+              const int r2 = r - ka;
+              x = ar[b.offPs + (int64_t)r2 * sp + col];
+              const double* Bb = ar + b.offB;  // kb x a.kc
+              for (int q = 0; q < a.kc; ++q) x -= Bb[r2 + (int64_t)q * kb] * ar[a.offYh + (int64_t)q * sp + col];
+            }
+          } else {
+            if (r < ka) {
+              x = ar[a.offTs + (int64_t)r * sp + col];
+              const double* Bb = ar + b.offB;  // b.kr x a.kc ; B_b^T(r, q) = Bb(q, r)
+              for (int q = 0; q < b.kr; ++q) x -= Bb[q + (int64_t)r * b.kr] * ar[b.offZh + (int64_t)q * sp + col];
+            } else {
+              const int r2 = r - ka;
+              const double* Ba = ar + a.offB;  // a.kr x b.kc ; B_a^T(r2, q) = Ba(q, r2)
+              x = ar[b.offTs + (int64_t)r2 * sp + col];
+              for (int q = 0; q < a.kr; ++q) x -= Ba[q + (int64_t)r2 * a.kr] * ar[a.offZh + (int64_t)q * sp + col];
+            }
+          }
+        }
+        W0[e] = x;
+      }
+    }
+    __syncthreads();
+    // working copy: columns = candidates, rows = samples (ld sp)
+    double* Aw = (lds_doubles >= nc * sp) ? dyn : (W0 + (int64_t)nc * sp);
+    for (int e = tid; e < nc * sp; e += blockDim.x) Aw[e] = W0[e];
+    __syncthreads();
+    const int k = cpqr_id(Aw, sp, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+    double* U = ar + (side ? nd.offV : nd.offU);
+    write_interp(Aw, sp, nc, k, s_perm, s_inv, U);
+    int* skel = ia + (side ? nd.offSc : nd.offSr);
+    double* sk = ar + (side ? nd.offTs : nd.offPs);
+    for (int j = tid; j < k; j += blockDim.x) skel[j] = s_cand[s_perm[j]];
+    for (int e = tid; e < k * sp; e += blockDim.x) {
+      const int j = e / sp, col = e % sp;
+      sk[e] = W0[(int64_t)s_perm[j] * sp + col];
+    }
+    if (tid == 0) {
+      if (side) {
+        nd.kc = k;
+        nd.nc = nc;
+      } else {
+        nd.kr = k;
+        nd.nr = nc;
+      }
+    }
+    __syncthreads();
+  }
+
+  // Yhat_i = V_i^T Om_c and Zhat_i = U_i^T Om_r with Om = Omega(t_i) for a
+  // leaf, the children's stacked Yhat / Zhat for a parent.
+  const int kr = nd.kr, kc = nd.kc, nr = nd.nr, ncc = nd.nc;
+  const double* U = ar + nd.offU;
+  const double* V = ar + nd.offV;
+  for (int e = tid; e < kc * sp; e += blockDim.x) {
+    const int j = e / sp, col = e % sp;
+    double x = 0.0;
+    if (col < s) {
+      for (int c = 0; c < ncc; ++c) {
+        double o;
+        if (nd.leaf) o = M.omega[(int64_t)(nd.lo + c) * sp + col];
+        else {
+          const HssNode& a = nodes[2 * jb.node + 1];
+          const HssNode& b = nodes[2 * jb.node + 2];
+          o = (c < a.kc) ? ar[a.offYh + (int64_t)c * sp + col] : ar[b.offYh + (int64_t)(c - a.kc) * sp + col];
+        }
+        x += V[c + (int64_t)j * ncc] * o;
+      }
+    }
+    ar[nd.offYh + e] = x;
+  }
+  for (int e = tid; e < kr * sp; e += blockDim.x) {
+    const int j = e / sp, col = e % sp;
+    double x = 0.0;
+    if (col < s) {
+      for (int c = 0; c < nr; ++c) {
+        double o;
+        if (nd.leaf) o = M.omega[(int64_t)(nd.lo + c) * sp + col];
+        else {
+          const HssNode& a = nodes[2 * jb.node + 1];
+          const HssNode& b = nodes[2 * jb.node + 2];
+          o = (c < a.kr) ? ar[a.offZh + (int64_t)c * sp + col] : ar[b.offZh + (int64_t)(c - a.kr) * sp + col];
+        }
+        x += U[c + (int64_t)j * nr] * o;
+      }
+    }
+    ar[nd.offZh + e] = x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_hss_dmat(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
+                                                  double* __restrict__ dmat, const int64_t* __restrict__ doff) {
+  const int2 jb = leafjobs[blockIdx.x];
+  const HssMerge& M = ms[jb.x];
+  const HssNode& nd = M.nodes[jb.y];
+  const int m = nd.hi - nd.lo;
+  double* D = dmat + doff[blockIdx.x];
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int r = e % m, c = e / m;
+    D[e] = gen_entry(M, nd.lo + r, nd.lo + c);
+  }
+}
+
+// out2[0] = sum (a - b)^2, out2[1] = sum b^2 (one block, deterministic order)
+__global__ void __launch_bounds__(1024) k_diff_norms(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int64_t n, double* __restrict__ out2) {
+  __shared__ double s0[1024], s1[1024];
+  double x0 = 0.0, x1 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double dd = a[i] - b[i];
+    x0 += dd * dd;
+    x1 += b[i] * b[i];
+  }
+  s0[threadIdx.x] = x0;
+  s1[threadIdx.x] = x1;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s0[threadIdx.x] += s0[threadIdx.x + st];
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out2[0] = s0[0];
+    out2[1] = s1[0];
+  }
+}

@@ -26,15 +26,21 @@ struct RootBlock {
   int32_t i0;
 };
 
-// One product C(:, colmap[j]) = v_j * (A * B)(:, j) of the dense update.
+// One product C(:, colmap[j]) = beta C(:, colmap[j]) + vscale[j] ([A A2] [B; B2])(:, j).
+// Column-major; the inner dimension is K (first segment) + K2 (second, may be 0);
+// a transposed B segment is read as B(k, n) = B[n + k ldb].
 struct GemmProb {
   const double* A;
   const double* B;
   double* C;
+  const double* A2;
+  const double* B2;
   const int32_t* colmap;  // may be null (identity)
   const double* vscale;   // may be null (1)
-  int64_t lda, ldb, ldc;
-  int32_t M, N, K;
+  int64_t lda, ldb, ldc, lda2, ldb2;
+  int32_t M, N, K, K2;
+  int32_t transB, transB2;
+  double beta;
   int32_t tile0;          // first flat tile index of this problem
   int32_t tiles_m;        // tiles along M
 };
@@ -106,3 +112,4 @@ __global__ void k_cauchy(const MergeDev* __restrict__ merges, const int32_t* __r
                          const int32_t* __restrict__ tile_col0, LevelBufs B, int ncols, int grouped);
 
 __global__ void k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs);
+__global__ void k_gemm_f64_n64(const GemmProb* __restrict__ probs, int nprobs);

@@ -1,11 +1,10 @@
 // Entry points whose GPU implementation is not built yet: they report
 // ADC_ERR_UNSUPPORTED so that callers fail loudly.
 #include "adc_internal.hpp"
-#include "hss.hpp"
 
-adc_status hss_level_update(adc_ctx, const adc_opts&, MergeDev*, MergeDev*, int, const LevelBufs&, int,
-                            adc_report*, double*, double*) {
-  return ADC_ERR_UNSUPPORTED;
+int mlp_rank(adc_ctx, const double*, const double*, const double*, int, const std::vector<int>&, const adc_opts&,
+             int r_bound) {
+  return r_bound;
 }
 void mlp_release(adc_ctx) {}
 extern "C" {
@@ -13,17 +12,6 @@ adc_status adc_stedc_batched(adc_ctx, int32_t, const int64_t*, const double* con
                              double* const*, double* const*, const int64_t*, const adc_opts*, adc_report*) {
   return ADC_ERR_UNSUPPORTED;
 }
-adc_status adc_hss_build(adc_ctx, int64_t, const double*, const double*, const double*, const double*,
-                         const double*, const double*, int32_t, const adc_opts*, adc_hss*) {
-  return ADC_ERR_UNSUPPORTED;
-}
-adc_status adc_hss_apply(adc_ctx, adc_hss, int64_t, const double*, int64_t, double*, int64_t) {
-  return ADC_ERR_UNSUPPORTED;
-}
-adc_status adc_hss_info(adc_hss, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, double*) {
-  return ADC_ERR_UNSUPPORTED;
-}
-adc_status adc_hss_free(adc_hss) { return ADC_ERR_UNSUPPORTED; }
 adc_status adc_mlp_features(adc_ctx, int64_t, const double*, const double*, const double*, const int64_t*,
                             int32_t, float*) {
   return ADC_ERR_UNSUPPORTED;
