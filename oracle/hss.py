@@ -370,11 +370,11 @@ def adc_hss_update(d, uh, gam, mu, opts, Omega=None):
         root, post, info = rshss(gen, Om, bounds, opts.get("id_tol", 1e-14))
         H = HSS(root, post, gen, info)
         err = np.linalg.norm(WQ - hss_matmul_right(W.T, H)) / np.linalg.norm(WQ)
-        # a node whose ID kept every sample column compressed nothing: the
-        # samples cannot show its rank
-        saturated = info["max_rank"] >= s and s < K
-        info.update(check_err=float(err), retries=retries, r_est=r)
-        if err <= opts.get("check_tol", 1e-12) and not saturated:
+        # the probe error alone decides; a node whose ID kept every sample
+        # column is only reported
+        info.update(check_err=float(err), retries=retries, r_est=r,
+                    saturated=bool(info["max_rank"] >= s and s < K))
+        if err <= opts.get("check_tol", 1e-12):
             return H, info
         if retries >= opts.get("max_retries", 2):
             info["fallback"] = True

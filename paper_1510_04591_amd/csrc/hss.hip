@@ -588,8 +588,7 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
     m.err = (hn[2 * g + 1] > 0.0) ? std::sqrt(hn[2 * g] / hn[2 * g + 1]) : 0.0;
-    const bool saturated = (m.max_rank >= m.s) && (m.s < m.K);
-    m.pass = std::isfinite(m.err) && m.err <= o.check_tol && !saturated;
+    m.pass = std::isfinite(m.err) && m.err <= o.check_tol;
   }
   return ADC_OK;
 }

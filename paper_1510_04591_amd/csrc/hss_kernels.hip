@@ -183,20 +183,27 @@ constexpr int SMAX = 512;   // samples
 __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
                        double* redv, int* redi) {
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   __shared__ int s_stop;
   __shared__ double s_r11, s_alpha, s_vn2;
   for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
   const int kmax = min(m, n);
   int k = 0;
   for (; k < kmax; ++k) {
-    // remaining column norms and the pivot
+    // remaining column norms (one wave per column, lanes over rows)
+    for (int c = k + wv; c < n; c += nw) {
+      const double* col = A + (int64_t)c * lda;
+      double s2 = 0.0;
+      for (int r = k + lane; r < m; r += 64) s2 += col[r] * col[r];
+      s2 = wave_sum(s2);
+      if (lane == 0) nrm[c] = s2;
+    }
+    __syncthreads();
+    // pivot: largest norm, ties to the smaller index
     double best = -1.0;
     int bi = n;
     for (int c = k + tid; c < n; c += blockDim.x) {
-      double s2 = 0.0;
-      const double* col = A + (int64_t)c * lda;
-      for (int r = k; r < m; ++r) s2 += col[r] * col[r];
-      nrm[c] = s2;
+      const double s2 = nrm[c];
       if (s2 > best) {
         best = s2;
         bi = c;
@@ -243,29 +250,28 @@ __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, 
       s_alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
     }
     __syncthreads();
-    double part = 0.0;
-    for (int r = k + tid; r < m; r += blockDim.x) {
-      double x = A[r + (int64_t)k * lda];
-      if (r == k) x -= s_alpha;
-      vv[r] = x;
-      part += x * x;
+    if (wv == 0) {
+      double part = 0.0;
+      for (int r = k + lane; r < m; r += 64) {
+        double x = A[r + (int64_t)k * lda];
+        if (r == k) x -= s_alpha;
+        vv[r] = x;
+        part += x * x;
+      }
+      part = wave_sum(part);
+      if (lane == 0) s_vn2 = part;
     }
-    redv[tid] = part;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (tid < st) redv[tid] += redv[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) s_vn2 = redv[0];
     __syncthreads();
     const double vn2 = s_vn2;
     if (vn2 > 0.0) {
-      for (int c = k + 1 + tid; c < n; c += blockDim.x) {
+      // A(k:m, c) -= (2 v^T A(k:m, c) / v^T v) v, one wave per column
+      for (int c = k + 1 + wv; c < n; c += nw) {
         double* col = A + (int64_t)c * lda;
         double dot = 0.0;
-        for (int r = k; r < m; ++r) dot += vv[r] * col[r];
+        for (int r = k + lane; r < m; r += 64) dot += vv[r] * col[r];
+        dot = wave_sum(dot);
         const double f = 2.0 * dot / vn2;
-        for (int r = k; r < m; ++r) col[r] -= f * vv[r];
+        for (int r = k + lane; r < m; r += 64) col[r] -= f * vv[r];
       }
     }
     __syncthreads();
