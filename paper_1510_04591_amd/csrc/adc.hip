@@ -49,7 +49,7 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
 
 adc_status validate_opts_ext(const adc_opts& o) {
   if (o.dc_leaf < 2 || o.dc_leaf > 64) return ADC_ERR_ARG;
-  if (o.hss_leaf < 16 || o.hss_leaf > 512) return ADC_ERR_ARG;
+  if (o.hss_leaf < 16 || o.hss_leaf > 256) return ADC_ERR_ARG;
   if (!(o.id_tol >= 0.0) || o.oversample < 0 || o.max_retries < 0 || o.max_iter < 1) return ADC_ERR_ARG;
   if (o.nprobe < 1 || o.nprobe > 64 || o.r_cap < 1 || !(o.rank_eps > 0.0)) return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;

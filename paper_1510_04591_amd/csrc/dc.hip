@@ -94,6 +94,7 @@ struct WsLayout {
   double *a, *win, *Zb;
   double *dsort, *zsort, *dS, *zS, *lam, *gam, *mu, *uh, *v, *rot_c, *rot_s;
   int32_t *src, *supp, *surv, *defl, *gorder, *rot_i, *rot_j, *rot_f, *posR, *posD, *colmerge;
+  int32_t *pidx, *ginv, *rot_i_of, *rot_j_of;
   double *pk, *qc;
   int* noconv;
   size_t bytes;
@@ -126,6 +127,10 @@ WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
   L.posR = ar.take<int32_t>(N);
   L.posD = ar.take<int32_t>(N);
   L.colmerge = ar.take<int32_t>(N);
+  L.pidx = ar.take<int32_t>(N);
+  L.ginv = ar.take<int32_t>(N);
+  L.rot_i_of = ar.take<int32_t>(N);
+  L.rot_j_of = ar.take<int32_t>(N);
   L.noconv = ar.take<int>(64);
   L.Zb = need_zb ? ar.take<double>((size_t)N * N) : nullptr;
   L.pk = ar.take<double>((size_t)N * N);
@@ -317,6 +322,10 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     B.posD = L.posD;
     B.pk = L.pk;
     B.qc = L.qc;
+    B.pidx = L.pidx;
+    B.ginv = L.ginv;
+    B.rot_i_of = L.rot_i_of;
+    B.rot_j_of = L.rot_j_of;
 
     Arena ha{hs, 0, 0}, da{dd, 0, 0};
     MergeDev* h_m = ha.take<MergeDev>(nm);
@@ -437,8 +446,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       c->timer.mark(st, 3);
     }
     hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
-    hipLaunchKernelGGL(k_rotate, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B, 0);
+    hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B);
     HIP_OK(hipGetLastError());
     if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, ncols, 1);
     c->timer.mark(st, 9);

@@ -11,7 +11,7 @@
 namespace {
 
 constexpr int SP_PROBE = 32;  // padded probe count of the accuracy check
-constexpr int S_MAX = 512;
+constexpr int S_MAX = 256;
 
 int ceil_log2_ratio(int K, int m) {
   int L = 0;

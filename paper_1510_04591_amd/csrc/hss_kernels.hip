@@ -177,60 +177,72 @@ __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__
 // times the first one.  On return A[0:k, k:n] = R11^-1 R12 and perm lists the
 // chosen columns first.  All threads of the block take part.
 namespace {
-constexpr int CMAX = 1024;  // candidates
-constexpr int SMAX = 512;   // samples
+constexpr int CMAX = 512;  // candidates
+constexpr int SMAX = 256;  // samples
+constexpr int NCH = 4;     // row chunks of the per-column reductions
+
+// (value, index) maximum with ties to the smaller index
+__device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int oi) {
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
 
 __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
-                       double* redv, int* redi) {
+                       double* part, double* redv, int* redi) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  __shared__ int s_stop;
-  __shared__ double s_r11, s_alpha, s_vn2;
+  __shared__ int s_stop, s_p;
+  __shared__ double s_r11, s_pn, s_alpha, s_vn2;
   for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
   const int kmax = min(m, n);
   int k = 0;
   for (; k < kmax; ++k) {
-    // remaining column norms (one wave per column, lanes over rows)
-    for (int c = k + wv; c < n; c += nw) {
+    const int rows = m - k;
+    const int clen = (rows + NCH - 1) / NCH;
+    // squared norms of the remaining columns: partial sums over row chunks
+    for (int t = tid; t < NCH * (n - k); t += blockDim.x) {
+      const int c = k + t / NCH, ch = t % NCH;
+      const int r0 = k + ch * clen, r1 = min(m, r0 + clen);
       const double* col = A + (int64_t)c * lda;
       double s2 = 0.0;
-      for (int r = k + lane; r < m; r += 64) s2 += col[r] * col[r];
-      s2 = wave_sum(s2);
-      if (lane == 0) nrm[c] = s2;
+      for (int r = r0; r < r1; ++r) s2 += col[r] * col[r];
+      part[ch * CMAX + c] = s2;
     }
     __syncthreads();
-    // pivot: largest norm, ties to the smaller index
     double best = -1.0;
     int bi = n;
     for (int c = k + tid; c < n; c += blockDim.x) {
-      const double s2 = nrm[c];
-      if (s2 > best) {
-        best = s2;
-        bi = c;
-      }
+      double s2 = 0.0;
+      for (int ch = 0; ch < NCH; ++ch) s2 += part[ch * CMAX + c];
+      nrm[c] = s2;
+      argmax_merge(best, bi, s2, c);
     }
-    redv[tid] = best;
-    redi[tid] = bi;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      argmax_merge(best, bi, ov, oi);
+    }
+    if (lane == 0) {
+      redv[wv] = best;
+      redi[wv] = bi;
+    }
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        const double ov = redv[tid + st];
-        const int oi = redi[tid + st];
-        if (ov > redv[tid] || (ov == redv[tid] && oi < redi[tid])) {
-          redv[tid] = ov;
-          redi[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int p = redi[0];
-    const double pn = sqrt(fmax(redv[0], 0.0));
     if (tid == 0) {
+      double v = redv[0];
+      int i = redi[0];
+      for (int w2 = 1; w2 < nw; ++w2) argmax_merge(v, i, redv[w2], redi[w2]);
+      const double pn = sqrt(fmax(v, 0.0));
       if (k == 0) s_r11 = pn;
-      s_stop = (p >= n) || (pn == 0.0) || (pn <= tol * s_r11);
+      s_p = i;
+      s_pn = pn;
+      s_stop = (i >= n) || (pn == 0.0) || (pn <= tol * s_r11);
     }
     __syncthreads();
     if (s_stop) break;
+    const int p = s_p;
+    const double pn = s_pn;
     if (p != k) {
       for (int r = tid; r < m; r += blockDim.x) {
         const double t = A[r + (int64_t)k * lda];
@@ -242,40 +254,51 @@ __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, 
         perm[k] = perm[p];
         perm[p] = t;
       }
+      __syncthreads();
     }
-    __syncthreads();
     // Householder vector v = x - alpha e_1, alpha = -sign(x_0) ||x||
-    if (tid == 0) {
-      const double x0 = A[k + (int64_t)k * lda];
-      s_alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
-    }
-    __syncthreads();
     if (wv == 0) {
-      double part = 0.0;
+      const double x0 = A[k + (int64_t)k * lda];
+      const double alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
+      double sq = 0.0;
       for (int r = k + lane; r < m; r += 64) {
         double x = A[r + (int64_t)k * lda];
-        if (r == k) x -= s_alpha;
+        if (r == k) x -= alpha;
         vv[r] = x;
-        part += x * x;
+        sq += x * x;
       }
-      part = wave_sum(part);
-      if (lane == 0) s_vn2 = part;
+      sq = wave_sum(sq);
+      if (lane == 0) {
+        s_vn2 = sq;
+        s_alpha = alpha;
+      }
     }
     __syncthreads();
     const double vn2 = s_vn2;
-    if (vn2 > 0.0) {
-      // A(k:m, c) -= (2 v^T A(k:m, c) / v^T v) v, one wave per column
-      for (int c = k + 1 + wv; c < n; c += nw) {
-        double* col = A + (int64_t)c * lda;
-        double dot = 0.0;
-        for (int r = k + lane; r < m; r += 64) dot += vv[r] * col[r];
-        dot = wave_sum(dot);
-        const double f = 2.0 * dot / vn2;
-        for (int r = k + lane; r < m; r += 64) col[r] -= f * vv[r];
-      }
+    // partial dots v^T A(:, c) over row chunks
+    for (int t = tid; t < NCH * (n - k - 1); t += blockDim.x) {
+      const int c = k + 1 + t / NCH, ch = t % NCH;
+      const int r0 = k + ch * clen, r1 = min(m, r0 + clen);
+      const double* col = A + (int64_t)c * lda;
+      double dt = 0.0;
+      for (int r = r0; r < r1; ++r) dt += vv[r] * col[r];
+      part[ch * CMAX + c] = dt;
     }
     __syncthreads();
-    for (int r = k + tid; r < m; r += blockDim.x) A[r + (int64_t)k * lda] = (r == k) ? s_alpha : 0.0;
+    for (int c = k + 1 + tid; c < n; c += blockDim.x) {
+      double dt = 0.0;
+      for (int ch = 0; ch < NCH; ++ch) dt += part[ch * CMAX + c];
+      nrm[c] = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;  // reflection coefficient of column c
+    }
+    __syncthreads();
+    // A(k:m, c) -= f_c v for c > k; column k becomes (alpha, 0, ..., 0)
+    const int ncol = n - k;
+    for (int e = tid; e < rows * ncol; e += blockDim.x) {
+      const int r = k + e % rows, c = k + e / rows;
+      double* a = A + r + (int64_t)c * lda;
+      if (c == k) *a = (r == k) ? s_alpha : 0.0;
+      else *a -= nrm[c] * vv[r];
+    }
     __syncthreads();
   }
   // T = R11^-1 R12 in place
@@ -313,6 +336,7 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
                                                       const NodeJob* __restrict__ jobs, int lds_doubles) {
   extern __shared__ double dyn[];
   __shared__ double s_nrm[CMAX];
+  __shared__ double s_part[NCH * CMAX];
   __shared__ int s_perm[CMAX];
   __shared__ int s_inv[CMAX];
   __shared__ int s_cand[CMAX];
@@ -378,22 +402,26 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
             if (r < ka) {
               x = ar[a.offPs + (int64_t)r * sp + col];
               const double* Ba = ar + a.offB;  // ka x b.kc
+#pragma unroll 4
               for (int q = 0; q < b.kc; ++q) x -= Ba[r + (int64_t)q * ka] * ar[b.offYh + (int64_t)q * sp + col];
             } else {
               const int r2 = r - ka;
               x = ar[b.offPs + (int64_t)r2 * sp + col];
               const double* Bb = ar + b.offB;  // kb x a.kc
+#pragma unroll 4
               for (int q = 0; q < a.kc; ++q) x -= Bb[r2 + (int64_t)q * kb] * ar[a.offYh + (int64_t)q * sp + col];
             }
           } else {
             if (r < ka) {
               x = ar[a.offTs + (int64_t)r * sp + col];
               const double* Bb = ar + b.offB;  // b.kr x a.kc ; B_b^T(r, q) = Bb(q, r)
+#pragma unroll 4
               for (int q = 0; q < b.kr; ++q) x -= Bb[q + (int64_t)r * b.kr] * ar[b.offZh + (int64_t)q * sp + col];
             } else {
               const int r2 = r - ka;
               const double* Ba = ar + a.offB;  // a.kr x b.kc ; B_a^T(r2, q) = Ba(q, r2)
               x = ar[b.offTs + (int64_t)r2 * sp + col];
+#pragma unroll 4
               for (int q = 0; q < a.kr; ++q) x -= Ba[q + (int64_t)r2 * a.kr] * ar[a.offZh + (int64_t)q * sp + col];
             }
           }
@@ -406,7 +434,7 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
     double* Aw = (lds_doubles >= nc * sp) ? dyn : (W0 + (int64_t)nc * sp);
     for (int e = tid; e < nc * sp; e += blockDim.x) Aw[e] = W0[e];
     __syncthreads();
-    const int k = cpqr_id(Aw, sp, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+    const int k = cpqr_id(Aw, sp, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_part, s_redv, s_redi);
     double* U = ar + (side ? nd.offV : nd.offU);
     write_interp(Aw, sp, nc, k, s_perm, s_inv, U);
     int* skel = ia + (side ? nd.offSc : nd.offSr);
@@ -437,6 +465,7 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
     const int j = e / sp, col = e % sp;
     double x = 0.0;
     if (col < s) {
+#pragma unroll 4
       for (int c = 0; c < ncc; ++c) {
         double o;
         if (nd.leaf) o = M.omega[(int64_t)(nd.lo + c) * sp + col];
@@ -454,6 +483,7 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
     const int j = e / sp, col = e % sp;
     double x = 0.0;
     if (col < s) {
+#pragma unroll 4
       for (int c = 0; c < nr; ++c) {
         double o;
         if (nd.leaf) o = M.omega[(int64_t)(nd.lo + c) * sp + col];

@@ -76,6 +76,10 @@ struct LevelBufs {
   int32_t* posD;        // deflated q -> final position in the block
   double* pk;           // packed survivor columns of U
   double* qc;           // materialised Cauchy matrix (dense update)
+  int32_t* pidx;        // sorted position -> survivor r (>= 0) or -1 - deflated q
+  int32_t* ginv;        // survivor r -> position in the grouped order
+  int32_t* rot_i_of;    // sorted position -> rotation t with rot_i[t] = position, else -1
+  int32_t* rot_j_of;    // sorted position -> rotation t with rot_j[t] = position, else -1
 };
 
 // ---- kernels
@@ -107,6 +111,8 @@ __global__ void k_rotate(const MergeDev* __restrict__ merges, LevelBufs B, const
 
 __global__ void k_pack(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
                        const int32_t* __restrict__ col_idx, LevelBufs B, int sorted_pack);
+__global__ void k_pack_rot(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
+                           const int32_t* __restrict__ col_idx, LevelBufs B);
 
 __global__ void k_cauchy(const MergeDev* __restrict__ merges, const int32_t* __restrict__ tile_merge,
                          const int32_t* __restrict__ tile_col0, LevelBufs B, int ncols, int grouped);

@@ -62,11 +62,30 @@ struct OpMax {
   __device__ double operator()(double a, double b) const { return fmax(a, b); }
 };
 
+// Exclusive prefix sum of one int per thread over the block; sh needs
+// blockDim.x + 1 ints and holds the total at sh[blockDim.x] on return.
+__device__ int block_exclusive_scan(int x, int* sh) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  sh[tid] = x;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int y = (tid >= off) ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += y;
+    __syncthreads();
+  }
+  const int incl = sh[tid];
+  if (tid == blockDim.x - 1) sh[blockDim.x] = incl;
+  __syncthreads();
+  return incl - x;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B) {
-  __shared__ double sh[1024];
+  __shared__ double sh[1025];
   MergeDev& M = merges[blockIdx.x];
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1, n2 = n - n1;
@@ -108,83 +127,209 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
   const double tol = 8.0 * ADC_EPS * fmax(md, rho * mz);
   __syncthreads();
 
+  // --- type-1 flags and the candidate list (positions that are not type 1),
+  // each candidate's rotation test against its predecessor candidate taken
+  // with the original values; scratch: posD = candidate list, posR = flags,
+  // gam / lam / mu = r, c, s of that test.
+  int32_t* __restrict__ cand = B.posD + s0;
+  int32_t* __restrict__ flg = B.posR + s0;
+  double* __restrict__ tr_r = B.gam + s0;
+  double* __restrict__ tr_c = B.lam + s0;
+  double* __restrict__ tr_s = B.mu + s0;
+  const double* __restrict__ ds0 = B.dsort + s0;
+  const double* __restrict__ zs0 = B.zsort + s0;
+  int* shi = reinterpret_cast<int*>(sh);
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int j0 = tid * per, j1 = min(n, j0 + per);
+  int cnt = 0;
+  for (int j = j0; j < j1; ++j) cnt += !(rho * fabs(zs0[j]) <= tol);
+  const int base = block_exclusive_scan(cnt, shi);
+  for (int j = j0, q = base; j < j1; ++j)
+    if (!(rho * fabs(zs0[j]) <= tol)) cand[q++] = j;
+  __syncthreads();
+  const int ncand = shi[blockDim.x];  // total written by the scan
+  __syncthreads();
+  for (int q = tid; q < n; q += blockDim.x) flg[q] = 1;  // type 1 unless listed below
+  __syncthreads();
+  for (int q = tid; q < ncand; q += blockDim.x) {
+    const int j = cand[q];
+    int f = 0;
+    if (q > 0) {
+      const int i = cand[q - 1];
+      const double zi = zs0[i], zj = zs0[j];
+      const double r = hypot(zi, zj);
+      const double c = zj / r, s = -zi / r;
+      tr_r[j] = r;
+      tr_c[j] = c;
+      tr_s[j] = s;
+      f = (fabs((ds0[j] - ds0[i]) * c * s) <= tol) ? 2 : 0;
+    }
+    flg[j] = f;
+  }
+  __syncthreads();
+
+  // --- the scan in pole order, one lane, over LDS-staged chunks; the test of
+  // a candidate is recomputed only when its predecessor was just rotated.
+  constexpr int CH = 2048;
+  __shared__ double c_d[CH], c_z[CH], c_r[CH], c_c[CH], c_s[CH];
+  __shared__ int c_f[CH], c_p[CH];
+  __shared__ int st_K, st_nd, st_nrot, st_prev, st_psupp, st_pmod;
+  __shared__ double st_pd, st_pz;
   if (tid == 0) {
-    double* __restrict__ ds = B.dsort + s0;
-    double* __restrict__ zs = B.zsort + s0;
-    int32_t* __restrict__ sp = B.supp + s0;
-    int32_t* __restrict__ surv = B.surv + s0;
-    int32_t* __restrict__ defl = B.defl + s0;
-    double* __restrict__ dS = B.dS + s0;
-    double* __restrict__ zS = B.zS + s0;
-    int K = 0, nd = 0, nrot = 0, prev = -1;
-    double pd = 0.0, pz = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double zj = zs[j];
-      const double dj = ds[j];
-      if (rho * fabs(zj) <= tol) {
-        defl[nd++] = j;
-        continue;
+    st_K = st_nd = st_nrot = 0;
+    st_prev = -1;
+    st_psupp = 0;
+    st_pmod = 0;
+    st_pd = st_pz = 0.0;
+  }
+  int32_t* __restrict__ sp = B.supp + s0;
+  double* __restrict__ ds = B.dsort + s0;
+  double* __restrict__ zs = B.zsort + s0;
+  for (int c0 = 0; c0 < n; c0 += CH) {
+    const int cl = min(CH, n - c0);
+    __syncthreads();
+    for (int t = tid; t < cl; t += blockDim.x) {
+      const int j = c0 + t;
+      c_d[t] = ds0[j];
+      c_z[t] = zs0[j];
+      c_f[t] = flg[j];
+      c_p[t] = sp[j];
+      c_r[t] = tr_r[j];
+      c_c[t] = tr_c[j];
+      c_s[t] = tr_s[j];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int K = st_K, nd = st_nd, nrot = st_nrot, prev = st_prev, psupp = st_psupp, pmod = st_pmod;
+      double pd = st_pd, pz = st_pz;
+      int32_t* __restrict__ surv = B.surv + s0;
+      int32_t* __restrict__ defl = B.defl + s0;
+      double* __restrict__ dS = B.dS + s0;
+      double* __restrict__ zS = B.zS + s0;
+      for (int t = 0; t < cl; ++t) {
+        const int j = c0 + t;
+        const int f = c_f[t];
+        if (f == 1) {
+          defl[nd++] = j;
+          continue;
+        }
+        const double dj = c_d[t], zj = c_z[t];
+        if (prev < 0) {
+          prev = j;
+          pd = dj;
+          pz = zj;
+          psupp = c_p[t];
+          pmod = 0;
+          continue;
+        }
+        double r, c, s;
+        bool rot;
+        if (!pmod) {
+          r = c_r[t];
+          c = c_c[t];
+          s = c_s[t];
+          rot = (f == 2);
+        } else {
+          r = hypot(pz, zj);
+          c = zj / r;
+          s = -pz / r;
+          rot = fabs((dj - pd) * c * s) <= tol;
+        }
+        if (rot) {
+          const int fj = c_p[t];
+          B.rot_i[s0 + nrot] = prev;
+          B.rot_j[s0 + nrot] = j;
+          B.rot_c[s0 + nrot] = c;
+          B.rot_s[s0 + nrot] = s;
+          B.rot_f[s0 + nrot] = psupp | (fj << 2);
+          ++nrot;
+          psupp |= fj;
+          sp[prev] = psupp;
+          sp[j] = psupp;
+          ds[prev] = c * c * pd + s * s * dj;
+          zs[prev] = 0.0;
+          defl[nd++] = prev;
+          pd = s * s * pd + c * c * dj;
+          pz = r;
+          prev = j;
+          pmod = 1;
+        } else {
+          surv[K] = prev;
+          dS[K] = pd;
+          zS[K] = pz;
+          ++K;
+          prev = j;
+          pd = dj;
+          pz = zj;
+          psupp = c_p[t];
+          pmod = 0;
+        }
       }
-      if (prev < 0) {
-        prev = j;
-        pd = dj;
-        pz = zj;
-        continue;
-      }
-      const double r = hypot(pz, zj);
-      const double c = zj / r;
-      const double s = -pz / r;
-      if (fabs((dj - pd) * c * s) <= tol) {
-        const int fi = sp[prev], fj = sp[j];
-        B.rot_i[s0 + nrot] = prev;
-        B.rot_j[s0 + nrot] = j;
-        B.rot_c[s0 + nrot] = c;
-        B.rot_s[s0 + nrot] = s;
-        B.rot_f[s0 + nrot] = fi | (fj << 2);
-        ++nrot;
-        sp[prev] = sp[j] = fi | fj;
-        ds[prev] = c * c * pd + s * s * dj;
-        zs[prev] = 0.0;
-        defl[nd++] = prev;
-        pd = s * s * pd + c * c * dj;
-        pz = r;
-        prev = j;
-      } else {
-        surv[K] = prev;
-        dS[K] = pd;
-        zS[K] = pz;
-        ds[prev] = pd;
-        zs[prev] = pz;
-        ++K;
-        prev = j;
-        pd = dj;
-        pz = zj;
-      }
+      st_K = K;
+      st_nd = nd;
+      st_nrot = nrot;
+      st_prev = prev;
+      st_psupp = psupp;
+      st_pmod = pmod;
+      st_pd = pd;
+      st_pz = pz;
     }
-    if (prev >= 0) {
-      surv[K] = prev;
-      dS[K] = pd;
-      zS[K] = pz;
-      ds[prev] = pd;
-      zs[prev] = pz;
-      ++K;
-    }
-    // survivor groups by row support: top only (1), both (3), bottom only (2)
-    int k1 = 0, k2 = 0, k3 = 0;
-    for (int r = 0; r < K; ++r) {
-      const int f = sp[surv[r]];
-      k1 += (f == 1);
-      k2 += (f == 3);
-      k3 += (f == 2);
-    }
-    int c1 = 0, c2 = k1, c3 = k1 + k2;
-    int32_t* __restrict__ go = B.gorder + s0;
-    for (int r = 0; r < K; ++r) {
-      const int f = sp[surv[r]];
-      if (f == 1) go[c1++] = r;
-      else if (f == 3) go[c2++] = r;
-      else go[c3++] = r;
-    }
+  }
+  __syncthreads();
+  if (tid == 0 && st_prev >= 0) {
+    B.surv[s0 + st_K] = st_prev;
+    B.dS[s0 + st_K] = st_pd;
+    B.zS[s0 + st_K] = st_pz;
+    ++st_K;
+  }
+  __syncthreads();
+  const int K = st_K;
+
+  // --- survivor groups by row support: top only (1), both (3), bottom only
+  // (2), and the grouped order (stable inside every group)
+  const int perK = (K + blockDim.x - 1) / blockDim.x;
+  const int r0 = tid * perK, r1 = min(K, r0 + perK);
+  int c1 = 0, c2 = 0, c3 = 0;
+  for (int r = r0; r < r1; ++r) {
+    const int f = sp[B.surv[s0 + r]];
+    c1 += (f == 1);
+    c2 += (f == 3);
+    c3 += (f == 2);
+  }
+  const int b1 = block_exclusive_scan(c1, shi);
+  const int k1 = shi[blockDim.x];
+  __syncthreads();
+  const int b2 = block_exclusive_scan(c2, shi);
+  const int k2 = shi[blockDim.x];
+  __syncthreads();
+  const int b3 = block_exclusive_scan(c3, shi);
+  const int k3 = shi[blockDim.x];
+  __syncthreads();
+  int32_t* __restrict__ go = B.gorder + s0;
+  for (int r = r0, p1 = b1, p2 = k1 + b2, p3 = k1 + k2 + b3; r < r1; ++r) {
+    const int f = sp[B.surv[s0 + r]];
+    if (f == 1) go[p1++] = r;
+    else if (f == 3) go[p2++] = r;
+    else go[p3++] = r;
+  }
+  // --- maps used by the packing: role of every position, grouped position of
+  // every survivor, rotation of every position
+  const int nrot = st_nrot;
+  for (int p = tid; p < n; p += blockDim.x) {
+    B.rot_i_of[s0 + p] = -1;
+    B.rot_j_of[s0 + p] = -1;
+  }
+  __syncthreads();
+  for (int r = tid; r < K; r += blockDim.x) {
+    B.pidx[s0 + B.surv[s0 + r]] = r;
+    B.ginv[s0 + go[r]] = r;
+  }
+  for (int q = tid; q < n - K; q += blockDim.x) B.pidx[s0 + B.defl[s0 + q]] = -1 - q;
+  for (int t = tid; t < nrot; t += blockDim.x) {
+    B.rot_i_of[s0 + B.rot_i[s0 + t]] = t;
+    B.rot_j_of[s0 + B.rot_j[s0 + t]] = t;
+  }
+  if (tid == 0) {
     M.K = K;
     M.nrot = nrot;
     M.k1 = k1;
@@ -192,6 +337,65 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
     M.k3 = k3;
     M.rho = rho;
     M.tol = tol;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packing with the type-2 rotations applied on the fly.  One block per sorted
+// position of the level (job -> merge col_merge[job], position col_idx[job]).
+// A position untouched by rotations copies its column; the first position of
+// a rotation chain (rot_i[t+1] == rot_j[t]) carries the chain's columns
+// through its rotations, writing every deflated column to its final place in
+// the merged block and the last (surviving) column into the packed operand;
+// the other chain members do nothing.  Rows outside a column's original
+// support are the zeros of diag(Q1, Q2).
+__global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
+                                                  const int32_t* __restrict__ col_merge,
+                                                  const int32_t* __restrict__ col_idx, LevelBufs B) {
+  const MergeDev& M = merges[col_merge[blockIdx.x]];
+  const int64_t s0 = M.s0;
+  const int n = M.n, n1 = M.n1;
+  const int p = col_idx[blockIdx.x];
+  if (B.rot_j_of[s0 + p] >= 0) return;  // inside a chain: done by its head
+  auto dst_of = [&](int pos) -> double* {
+    const int role = B.pidx[s0 + pos];
+    if (role >= 0) {
+      const int pk = (M.mode == 1) ? role : B.ginv[s0 + role];
+      return B.pk + M.zoff + (int64_t)pk * n;
+    }
+    const int q = -1 - role;
+    return B.Znew + s0 + (s0 + B.posD[s0 + q]) * B.ldn;
+  };
+  auto src_of = [&](int pos) -> const double* { return B.Zold + s0 + (s0 + B.src[s0 + pos]) * B.ldo; };
+  auto supp_of = [&](int pos) { return (B.src[s0 + pos] < n1) ? 1 : 2; };
+  const int t0 = B.rot_i_of[s0 + p];
+  if (t0 < 0) {
+    const double* sc = src_of(p);
+    double* dc = dst_of(p);
+    const int f = supp_of(p);
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      const int bit = (r < n1) ? 1 : 2;
+      dc[r] = (f & bit) ? sc[r] : 0.0;
+    }
+    return;
+  }
+  // chain t0, t0+1, ... while rot_i[t+1] == rot_j[t]
+  const int nrot = M.nrot;
+  int t1 = t0;
+  while (t1 + 1 < nrot && B.rot_i[s0 + t1 + 1] == B.rot_j[s0 + t1]) ++t1;
+  const int fa = supp_of(p);
+  const double* sa = src_of(p);
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const int bit = (r < n1) ? 1 : 2;
+    double a = (fa & bit) ? sa[r] : 0.0;
+    for (int t = t0; t <= t1; ++t) {
+      const int pj = B.rot_j[s0 + t];
+      const double c = B.rot_c[s0 + t], s = B.rot_s[s0 + t];
+      const double b = (supp_of(pj) & bit) ? src_of(pj)[r] : 0.0;
+      dst_of(B.rot_i[s0 + t])[r] = c * a + s * b;
+      a = -s * a + c * b;
+    }
+    dst_of(B.rot_j[s0 + t1])[r] = a;
   }
 }
 
