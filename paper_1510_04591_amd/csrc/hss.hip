@@ -274,7 +274,7 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   }
   for (int l = Lmax; l >= 0; --l) {
     if (lj[l].empty()) continue;
-    hipLaunchKernelGGL(k_hss_compress, dim3((unsigned)lj[l].size()), dim3(256), (size_t)lds * 8, st, hb.d_ms,
+    hipLaunchKernelGGL(k_hss_compress, dim3((unsigned)lj[l].size()), dim3(1024), (size_t)lds * 8, st, hb.d_ms,
                        (const NodeJob*)(dj + o_lj[l]), lds);
     HIP_OK(hipGetLastError());
   }

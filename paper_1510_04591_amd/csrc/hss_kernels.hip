@@ -291,27 +291,83 @@ __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, 
       nrm[c] = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;  // reflection coefficient of column c
     }
     __syncthreads();
-    // A(k:m, c) -= f_c v for c > k; column k becomes (alpha, 0, ..., 0)
-    const int ncol = n - k;
-    for (int e = tid; e < rows * ncol; e += blockDim.x) {
-      const int r = k + e % rows, c = k + e / rows;
-      double* a = A + r + (int64_t)c * lda;
-      if (c == k) *a = (r == k) ? s_alpha : 0.0;
-      else *a -= nrm[c] * vv[r];
+    // A(k:m, c) -= f_c v for c > k (a wave per column, lanes over rows);
+    // column k becomes (alpha, 0, ..., 0)
+    for (int c = k + wv; c < n; c += nw) {
+      double* col = A + (int64_t)c * lda;
+      if (c == k) {
+        for (int r = k + lane; r < m; r += 64) col[r] = (r == k) ? s_alpha : 0.0;
+      } else {
+        const double f = nrm[c];
+        for (int r = k + lane; r < m; r += 64) col[r] -= f * vv[r];
+      }
     }
     __syncthreads();
   }
-  // T = R11^-1 R12 in place
-  for (int c = k + tid; c < n; c += blockDim.x) {
+  // T = R11^-1 R12 in place: back substitution, a wave per column (the
+  // update of the remaining rows is spread over the lanes)
+  for (int c = k + wv; c < n; c += nw) {
     double* col = A + (int64_t)c * lda;
-    for (int r = k - 1; r >= 0; --r) {
-      double x = col[r];
-      for (int j = r + 1; j < k; ++j) x -= A[r + (int64_t)j * lda] * col[j];
-      col[r] = x / A[r + (int64_t)r * lda];
+    for (int j = k - 1; j >= 0; --j) {
+      const double xj = col[j] / A[j + (int64_t)j * lda];
+      for (int r = lane; r < j; r += 64) col[r] -= xj * A[r + (int64_t)j * lda];
+      if (lane == 0) col[j] = xj;
     }
   }
   __syncthreads();
   return k;
+}
+
+// C[r ldc + col] = (Cinit ? Cinit[r ldi + col] : 0) + sgn sum_q A(r, q) Y[q ldy + col]
+// for r < R, col < ncol, with A(r, q) = A[r ars + q acs]; both operands are
+// staged through `lds` (cap doubles) in chunks of q.  Every output element
+// is owned by one thread, so Cinit may alias C.
+__device__ void block_small_gemm(double* C, int ldc, const double* Cinit, int ldi, double sgn, const double* A,
+                                 int ars, int acs, const double* Y, int ldy, int R, int Q, int ncol, double* lds,
+                                 int cap) {
+  const int tid = threadIdx.x;
+  int qc = (cap > 0) ? cap / (R + ncol) : 0;
+  if (R <= 0 || ncol <= 0) return;
+  if (qc <= 0) {
+    for (int e = tid; e < R * ncol; e += blockDim.x) {
+      const int r = e / ncol, col = e % ncol;
+      double x = 0.0;
+      for (int q = 0; q < Q; ++q) x += A[(int64_t)r * ars + (int64_t)q * acs] * Y[(int64_t)q * ldy + col];
+      C[(int64_t)r * ldc + col] = (Cinit ? Cinit[(int64_t)r * ldi + col] : 0.0) + sgn * x;
+    }
+    __syncthreads();
+    return;
+  }
+  qc = min(qc, max(Q, 1));
+  double* As = lds;                // R x qc
+  double* Ys = lds + R * qc;       // qc x ncol
+  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int q0 = 0; q0 == 0 || q0 < Q; q0 += qc) {
+    const int qn = max(0, min(qc, Q - q0));
+    __syncthreads();
+    for (int r = wv; r < R; r += nw)
+      for (int qq = lane; qq < qn; qq += 64) As[r * qc + qq] = A[(int64_t)r * ars + (int64_t)(q0 + qq) * acs];
+    for (int qq = wv; qq < qn; qq += nw)
+      for (int col = lane; col < ncol; col += 64) Ys[qq * ncol + col] = Y[(int64_t)(q0 + qq) * ldy + col];
+    __syncthreads();
+    for (int r = wv; r < R; r += nw) {
+      const double* ar = As + r * qc;
+      for (int col = lane; col < ncol; col += 64) {
+        double x0 = 0.0, x1 = 0.0;
+        int qq = 0;
+        for (; qq + 1 < qn; qq += 2) {
+          x0 += ar[qq] * Ys[qq * ncol + col];
+          x1 += ar[qq + 1] * Ys[(qq + 1) * ncol + col];
+        }
+        if (qq < qn) x0 += ar[qq] * Ys[qq * ncol + col];
+        double* cp = C + (int64_t)r * ldc + col;
+        const double base = (q0 == 0) ? (Cinit ? Cinit[(int64_t)r * ldi + col] : 0.0) : *cp;
+        *cp = base + sgn * (x0 + x1);
+      }
+    }
+    if (Q <= 0) break;
+  }
+  __syncthreads();
 }
 
 // Write U (n x k, column-major, ld n): rows perm[j] (j < k) are e_j, rows
@@ -320,19 +376,20 @@ __device__ void write_interp(const double* A, int lda, int n, int k, const int* 
   const int tid = threadIdx.x;
   for (int c = tid; c < n; c += blockDim.x) inv[perm[c]] = c;
   __syncthreads();
-  for (int e = tid; e < n * k; e += blockDim.x) {
-    const int row = e % n, j = e / n;
-    const int pos = inv[row];
-    double x;
-    if (pos < k) x = (pos == j) ? 1.0 : 0.0;
-    else x = A[j + (int64_t)pos * lda];
-    U[row + (int64_t)j * n] = x;
-  }
+  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = wv; j < k; j += nw)
+    for (int row = lane; row < n; row += 64) {
+      const int pos = inv[row];
+      double x;
+      if (pos < k) x = (pos == j) ? 1.0 : 0.0;
+      else x = A[j + (int64_t)pos * lda];
+      U[row + (int64_t)j * n] = x;
+    }
   __syncthreads();
 }
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict__ ms,
+__global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restrict__ ms,
                                                       const NodeJob* __restrict__ jobs, int lds_doubles) {
   extern __shared__ double dyn[];
   __shared__ double s_nrm[CMAX];
@@ -341,8 +398,8 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
   __shared__ int s_inv[CMAX];
   __shared__ int s_cand[CMAX];
   __shared__ double s_vv[SMAX];
-  __shared__ double s_redv[256];
-  __shared__ int s_redi[256];
+  __shared__ double s_redv[16];
+  __shared__ int s_redi[16];
 
   const NodeJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
@@ -392,41 +449,20 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
       const int* la = ia + (side ? a.offSc : a.offSr);
       const int* lb = ia + (side ? b.offSc : b.offSr);
       for (int c = tid; c < nc; c += blockDim.x) s_cand[c] = (c < ka) ? la[c] : lb[c - ka];
-      // side 0: [Phi_a|sk - B_a Yhat_b ; Phi_b|sk - B_b Yhat_a]
-      // side 1: [Theta_a|sk - B_b^T Zhat_b ; Theta_b|sk - B_a^T Zhat_a]
-      for (int e = tid; e < nc * sp; e += blockDim.x) {
-        const int r = e / sp, col = e % sp;
-        double x = 0.0;
-        if (col < s) {
-          if (side == 0) {
-            if (r < ka) {
-              x = ar[a.offPs + (int64_t)r * sp + col];
-              const double* Ba = ar + a.offB;  // ka x b.kc
-#pragma unroll 4
-              for (int q = 0; q < b.kc; ++q) x -= Ba[r + (int64_t)q * ka] * ar[b.offYh + (int64_t)q * sp + col];
-            } else {
-              const int r2 = r - ka;
-              x = ar[b.offPs + (int64_t)r2 * sp + col];
-              const double* Bb = ar + b.offB;  // kb x a.kc
-#pragma unroll 4
-              for (int q = 0; q < a.kc; ++q) x -= Bb[r2 + (int64_t)q * kb] * ar[a.offYh + (int64_t)q * sp + col];
-            }
-          } else {
-            if (r < ka) {
-              x = ar[a.offTs + (int64_t)r * sp + col];
-              const double* Bb = ar + b.offB;  // b.kr x a.kc ; B_b^T(r, q) = Bb(q, r)
-#pragma unroll 4
-              for (int q = 0; q < b.kr; ++q) x -= Bb[q + (int64_t)r * b.kr] * ar[b.offZh + (int64_t)q * sp + col];
-            } else {
-              const int r2 = r - ka;
-              const double* Ba = ar + a.offB;  // a.kr x b.kc ; B_a^T(r2, q) = Ba(q, r2)
-              x = ar[b.offTs + (int64_t)r2 * sp + col];
-#pragma unroll 4
-              for (int q = 0; q < a.kr; ++q) x -= Ba[q + (int64_t)r2 * a.kr] * ar[a.offZh + (int64_t)q * sp + col];
-            }
-          }
-        }
-        W0[e] = x;
+      const double* Ba = ar + a.offB;  // a.kr x b.kc
+      const double* Bb = ar + b.offB;  // b.kr x a.kc
+      if (side == 0) {
+        // [Phi_a|sk - B_a Yhat_b ; Phi_b|sk - B_b Yhat_a]
+        block_small_gemm(W0, sp, ar + a.offPs, sp, -1.0, Ba, 1, ka, ar + b.offYh, sp, ka, b.kc, s, dyn,
+                         lds_doubles);
+        block_small_gemm(W0 + (int64_t)ka * sp, sp, ar + b.offPs, sp, -1.0, Bb, 1, kb, ar + a.offYh, sp, kb, a.kc,
+                         s, dyn, lds_doubles);
+      } else {
+        // [Theta_a|sk - B_b^T Zhat_b ; Theta_b|sk - B_a^T Zhat_a]
+        block_small_gemm(W0, sp, ar + a.offTs, sp, -1.0, Bb, b.kr, 1, ar + b.offZh, sp, ka, b.kr, s, dyn,
+                         lds_doubles);
+        block_small_gemm(W0 + (int64_t)ka * sp, sp, ar + b.offTs, sp, -1.0, Ba, a.kr, 1, ar + a.offZh, sp, kb,
+                         a.kr, s, dyn, lds_doubles);
       }
     }
     __syncthreads();
@@ -440,10 +476,8 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
     int* skel = ia + (side ? nd.offSc : nd.offSr);
     double* sk = ar + (side ? nd.offTs : nd.offPs);
     for (int j = tid; j < k; j += blockDim.x) skel[j] = s_cand[s_perm[j]];
-    for (int e = tid; e < k * sp; e += blockDim.x) {
-      const int j = e / sp, col = e % sp;
-      sk[e] = W0[(int64_t)s_perm[j] * sp + col];
-    }
+    for (int j = tid >> 6; j < k; j += blockDim.x >> 6)
+      for (int col = tid & 63; col < sp; col += 64) sk[(int64_t)j * sp + col] = W0[(int64_t)s_perm[j] * sp + col];
     if (tid == 0) {
       if (side) {
         nd.kc = k;
@@ -459,43 +493,22 @@ __global__ void __launch_bounds__(256) k_hss_compress(const HssMerge* __restrict
   // Yhat_i = V_i^T Om_c and Zhat_i = U_i^T Om_r with Om = Omega(t_i) for a
   // leaf, the children's stacked Yhat / Zhat for a parent.
   const int kr = nd.kr, kc = nd.kc, nr = nd.nr, ncc = nd.nc;
-  const double* U = ar + nd.offU;
-  const double* V = ar + nd.offV;
-  for (int e = tid; e < kc * sp; e += blockDim.x) {
-    const int j = e / sp, col = e % sp;
-    double x = 0.0;
-    if (col < s) {
-#pragma unroll 4
-      for (int c = 0; c < ncc; ++c) {
-        double o;
-        if (nd.leaf) o = M.omega[(int64_t)(nd.lo + c) * sp + col];
-        else {
-          const HssNode& a = nodes[2 * jb.node + 1];
-          const HssNode& b = nodes[2 * jb.node + 2];
-          o = (c < a.kc) ? ar[a.offYh + (int64_t)c * sp + col] : ar[b.offYh + (int64_t)(c - a.kc) * sp + col];
-        }
-        x += V[c + (int64_t)j * ncc] * o;
-      }
-    }
-    ar[nd.offYh + e] = x;
-  }
-  for (int e = tid; e < kr * sp; e += blockDim.x) {
-    const int j = e / sp, col = e % sp;
-    double x = 0.0;
-    if (col < s) {
-#pragma unroll 4
-      for (int c = 0; c < nr; ++c) {
-        double o;
-        if (nd.leaf) o = M.omega[(int64_t)(nd.lo + c) * sp + col];
-        else {
-          const HssNode& a = nodes[2 * jb.node + 1];
-          const HssNode& b = nodes[2 * jb.node + 2];
-          o = (c < a.kr) ? ar[a.offZh + (int64_t)c * sp + col] : ar[b.offZh + (int64_t)(c - a.kr) * sp + col];
-        }
-        x += U[c + (int64_t)j * nr] * o;
-      }
-    }
-    ar[nd.offZh + e] = x;
+  const double* U = ar + nd.offU;  // nr x kr
+  const double* V = ar + nd.offV;  // ncc x kc
+  double* Yh = ar + nd.offYh;
+  double* Zh = ar + nd.offZh;
+  // U^T(j, c) = U[c + j nr]: row stride nr, column stride 1
+  if (nd.leaf) {
+    const double* Om = M.omega + (int64_t)nd.lo * sp;
+    block_small_gemm(Yh, sp, nullptr, 0, 1.0, V, ncc, 1, Om, sp, kc, ncc, s, dyn, lds_doubles);
+    block_small_gemm(Zh, sp, nullptr, 0, 1.0, U, nr, 1, Om, sp, kr, nr, s, dyn, lds_doubles);
+  } else {
+    const HssNode& a = nodes[2 * jb.node + 1];
+    const HssNode& b = nodes[2 * jb.node + 2];
+    block_small_gemm(Yh, sp, nullptr, 0, 1.0, V, ncc, 1, ar + a.offYh, sp, kc, a.kc, s, dyn, lds_doubles);
+    block_small_gemm(Yh, sp, Yh, sp, 1.0, V + a.kc, ncc, 1, ar + b.offYh, sp, kc, b.kc, s, dyn, lds_doubles);
+    block_small_gemm(Zh, sp, nullptr, 0, 1.0, U, nr, 1, ar + a.offZh, sp, kr, a.kr, s, dyn, lds_doubles);
+    block_small_gemm(Zh, sp, Zh, sp, 1.0, U + a.kr, nr, 1, ar + b.offZh, sp, kr, b.kr, s, dyn, lds_doubles);
   }
 }
 

@@ -168,24 +168,158 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
   }
   __syncthreads();
 
+  // --- parallel resolution of the scan.  With R[q] "candidate q is rotated
+  // with its predecessor", T[q] the test with original values (bit 2) and
+  // F[q] the test after q-1 was itself rotated with q-2 (bit 4), the scan
+  // obeys R[0] = 0, R[q] = R[q-1] ? F[q] : T[q]: a composition of maps on
+  // {0, 1}, resolved by a block-wide scan.  F[q] assumes that rotation of q-1
+  // started from original values, which holds unless two rotations are
+  // adjacent; then the lane-by-lane scan below takes over.
+  for (int q = 2 + tid; q < ncand; q += blockDim.x) {
+    const int i2 = cand[q - 2], i1 = cand[q - 1], j = cand[q];
+    const double c1 = tr_c[i1], s1 = tr_s[i1];
+    const double pd = s1 * s1 * ds0[i2] + c1 * c1 * ds0[i1];
+    const double pz = tr_r[i1];
+    const double zj = zs0[j];
+    const double r = hypot(pz, zj);
+    const double c = zj / r, s = -pz / r;
+    if (fabs((ds0[j] - pd) * c * s) <= tol) flg[j] |= 4;
+  }
+  __syncthreads();
+  // maps encoded as out(0) | out(1) << 1; identity = 2; a-then-b composition
+  auto mbit = [](int m, int b) { return (m >> b) & 1; };
+  auto mcomp = [&](int a, int b) { return mbit(b, mbit(a, 0)) | (mbit(b, mbit(a, 1)) << 1); };
+  const int perQ = (ncand + blockDim.x - 1) / blockDim.x;
+  const int qa = min(ncand, tid * perQ), qb = min(ncand, qa + perQ);
+  int mp = 2;
+  for (int q = qa; q < qb; ++q) {
+    const int f = flg[cand[q]];
+    const int mq = (q == 0) ? 0 : (((f >> 1) & 1) | (((f >> 2) & 1) << 1));
+    mp = mcomp(mp, mq);
+  }
+  __syncthreads();
+  shi[tid] = mp;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int y = (tid >= off) ? shi[tid - off] : 2;
+    __syncthreads();
+    shi[tid] = mcomp(y, shi[tid]);
+    __syncthreads();
+  }
+  int bcur = (tid == 0) ? 0 : mbit(shi[tid - 1], 0);
+  __syncthreads();
+  for (int q = qa; q < qb; ++q) {
+    const int f = flg[cand[q]];
+    const int mq = (q == 0) ? 0 : (((f >> 1) & 1) | (((f >> 2) & 1) << 1));
+    bcur = mbit(mq, bcur);
+    if (bcur) flg[cand[q]] = f | 8;
+  }
+  __syncthreads();
+  __shared__ int s_adj;
+  if (tid == 0) s_adj = 0;
+  __syncthreads();
+  for (int q = 1 + tid; q < ncand; q += blockDim.x)
+    if ((flg[cand[q]] & 8) && (flg[cand[q - 1]] & 8)) s_adj = 1;
+  __syncthreads();
+  const bool parallel_ok = (s_adj == 0);
+
+  __shared__ int st_K, st_nd, st_nrot, st_prev, st_psupp, st_pmod;
+  __shared__ double st_pd, st_pz;
+  int32_t* __restrict__ sp = B.supp + s0;
+  double* __restrict__ ds = B.dsort + s0;
+  double* __restrict__ zs = B.zsort + s0;
+  if (parallel_ok) {
+    // every position of this thread's range [j0, j1): type 1, rotated into
+    // (the predecessor deflates, event here), deflated by its successor, or
+    // survivor; lists in position order of their events
+    int q = base;  // candidate index of the first candidate in the range
+    int nev = 0, nsv = 0, nrt = 0;
+    for (int j = j0; j < j1; ++j) {
+      const int f = flg[j];
+      if (f == 1) {
+        ++nev;
+        continue;
+      }
+      const bool rin = f & 8;
+      const bool rnext = (q + 1 < ncand) && (flg[cand[q + 1]] & 8);
+      nev += rin;
+      nrt += rin;
+      nsv += !rnext;
+      ++q;
+    }
+    const int bev = block_exclusive_scan(nev, shi);
+    const int tot_ev = shi[blockDim.x];
+    __syncthreads();
+    const int bsv = block_exclusive_scan(nsv, shi);
+    const int tot_sv = shi[blockDim.x];
+    __syncthreads();
+    const int brt = block_exclusive_scan(nrt, shi);
+    const int tot_rt = shi[blockDim.x];
+    __syncthreads();
+    q = base;
+    int iev = bev, isv = bsv, irt = brt;
+    for (int j = j0; j < j1; ++j) {
+      const int f = flg[j];
+      if (f == 1) {
+        B.defl[s0 + iev++] = j;
+        continue;
+      }
+      const bool rin = f & 8;
+      const bool rnext = (q + 1 < ncand) && (flg[cand[q + 1]] & 8);
+      double pd = ds0[j], pz = zs0[j];
+      if (rin) {
+        const int i = cand[q - 1];
+        const double c = tr_c[j], s = tr_s[j];
+        const double di = ds0[i];
+        B.defl[s0 + iev++] = i;
+        B.rot_i[s0 + irt] = i;
+        B.rot_j[s0 + irt] = j;
+        B.rot_c[s0 + irt] = c;
+        B.rot_s[s0 + irt] = s;
+        B.rot_f[s0 + irt] = sp[i] | (sp[j] << 2);
+        ++irt;
+        ds[i] = c * c * di + s * s * pd;
+        pd = s * s * di + c * c * pd;
+        pz = tr_r[j];
+      }
+      if (!rnext) {
+        B.surv[s0 + isv] = j;
+        B.dS[s0 + isv] = pd;
+        B.zS[s0 + isv] = pz;
+        ++isv;
+      }
+      ++q;
+    }
+    __syncthreads();
+    // supports of rotated pairs become the union (after every flag was read)
+    for (int t = tid; t < tot_rt; t += blockDim.x) {
+      const int i = B.rot_i[s0 + t], j = B.rot_j[s0 + t];
+      const int u = sp[i] | sp[j];
+      sp[i] = u;
+      sp[j] = u;
+      zs[i] = 0.0;
+    }
+    if (tid == 0) {
+      st_K = tot_sv;
+      st_nd = tot_ev;
+      st_nrot = tot_rt;
+    }
+    __syncthreads();
+  }
+
   // --- the scan in pole order, one lane, over LDS-staged chunks; the test of
   // a candidate is recomputed only when its predecessor was just rotated.
   constexpr int CH = 2048;
   __shared__ double c_d[CH], c_z[CH], c_r[CH], c_c[CH], c_s[CH];
   __shared__ int c_f[CH], c_p[CH];
-  __shared__ int st_K, st_nd, st_nrot, st_prev, st_psupp, st_pmod;
-  __shared__ double st_pd, st_pz;
-  if (tid == 0) {
+  if (tid == 0 && !parallel_ok) {
     st_K = st_nd = st_nrot = 0;
     st_prev = -1;
     st_psupp = 0;
     st_pmod = 0;
     st_pd = st_pz = 0.0;
   }
-  int32_t* __restrict__ sp = B.supp + s0;
-  double* __restrict__ ds = B.dsort + s0;
-  double* __restrict__ zs = B.zsort + s0;
-  for (int c0 = 0; c0 < n; c0 += CH) {
+  for (int c0 = 0; !parallel_ok && c0 < n; c0 += CH) {
     const int cl = min(CH, n - c0);
     __syncthreads();
     for (int t = tid; t < cl; t += blockDim.x) {
@@ -228,7 +362,7 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
           r = c_r[t];
           c = c_c[t];
           s = c_s[t];
-          rot = (f == 2);
+          rot = (f & 2) != 0;
         } else {
           r = hypot(pz, zj);
           c = zj / r;
@@ -276,7 +410,7 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
     }
   }
   __syncthreads();
-  if (tid == 0 && st_prev >= 0) {
+  if (tid == 0 && !parallel_ok && st_prev >= 0) {
     B.surv[s0 + st_K] = st_prev;
     B.dS[s0 + st_K] = st_pd;
     B.zS[s0 + st_K] = st_pz;

@@ -24,6 +24,47 @@ namespace {
 
 constexpr int MAXW = 16;
 
+// 1/x: hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each of which squares the relative error.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// s += sum z_j^2/(delta_j - t), ds += sum z_j^2/(delta_j - t)^2, ea += sum |.|
+// over j in [ja, jb), delta_j = d_j - dorg; two independent accumulator sets.
+__device__ __forceinline__ void pole_sums(const double* __restrict__ d, const double* __restrict__ z, int ja, int jb,
+                                          double dorg, double t, double& s, double& ds, double& ea) {
+  double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0, e0 = 0.0, e1 = 0.0;
+  int j = ja;
+  for (; j + 1 < jb; j += 2) {
+    const double za = z[j], zb = z[j + 1];
+    const double ta = za * rcp_nr((d[j] - dorg) - t);
+    const double tb = zb * rcp_nr((d[j + 1] - dorg) - t);
+    const double ua = za * ta, ub = zb * tb;
+    s0 += ua;
+    s1 += ub;
+    q0 = fma(ta, ta, q0);
+    q1 = fma(tb, tb, q1);
+    e0 += fabs(ua);
+    e1 += fabs(ub);
+  }
+  if (j < jb) {
+    const double za = z[j];
+    const double ta = za * rcp_nr((d[j] - dorg) - t);
+    const double ua = za * ta;
+    s0 += ua;
+    q0 = fma(ta, ta, q0);
+    e0 += fabs(ua);
+  }
+  s += s0 + s1;
+  ds += q0 + q1;
+  ea += e0 + e1;
+}
+
 __device__ __forceinline__ double bits_mid(double lo, double hi) {
   // midpoint over the ordered set of doubles of one sign (|lo| < |hi| or the
   // reverse); both have the sign of hi or are zero.
@@ -69,6 +110,9 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
   const int chunk = (K + W - 1) / W;
   const int j0 = wv * chunk;
   const int j1 = min(K, j0 + chunk);
+  // split index sp_i = i (K-2 for the last root): its range over the block
+  const int spmin = min(rb.i0, K - 2);
+  const int spmax = min(rb.i0 + 63, K - 2);
 
   // wave-0 lane state
   double lo = 0.0, hi = 0.0, gap = 0.0, tau = 0.0;
@@ -88,7 +132,9 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
   if (wv == 0) {
     if (valid) {
       gap = last ? INFINITY : (d[i + 1] - d[i]);
-      tau = last ? rho : 0.5 * gap;  // phase 0 point, frame d_i
+      // phase 0 point, frame d_i: the midpoint for interior roots; for the
+      // last root rho z_K^2, a lower bound of its distance to d_K
+      tau = last ? fmax(rho * z[i] * z[i], 1e-300) : 0.5 * gap;
       org = i;
     }
     s_tau[lane] = tau;
@@ -106,11 +152,13 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
     const double dorg = valid ? d[o_l] : 0.0;
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
     if (act) {
-      for (int j = j0; j < j1; ++j) {
-        const double dj = d[j];
+      // poles j <= spmin belong to psi for every lane, j > spmax to phi
+      const int ja = min(j1, max(j0, spmin + 1));
+      const int jb = min(j1, max(ja, spmax + 1));
+      pole_sums(d, z, j0, ja, dorg, t_l, psi, dpsi, eabs);
+      for (int j = ja; j < jb; ++j) {
         const double zj = z[j];
-        const double del = (dj - dorg) - t_l;
-        const double t = zj / del;
+        const double t = zj * rcp_nr((d[j] - dorg) - t_l);
         const double term = zj * t;
         if (j <= sp) {
           psi += term;
@@ -121,6 +169,7 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
         }
         eabs += fabs(term);
       }
+      pole_sums(d, z, jb, j1, dorg, t_l, phi, dphi, eabs);
     }
     s_part[0][wv][lane] = psi;
     s_part[1][wv][lane] = dpsi;

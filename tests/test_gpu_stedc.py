@@ -43,3 +43,53 @@ def test_random_dense_vs_oracle(ctx, N, seed):
     check_result(a, b, w, Z, w_o)
     ks = np.array([0, N // 3, N - 1])
     assert np.max(np.abs(w[ks] - sturm.eigenvalues_by_index(a, b, ks))) <= 1e-13 * odc.tnorm1(a, b)
+
+
+def glued(copies, m=20, glue=1e-10, seed=7):
+    """copies of one random m x m tridiagonal block joined by tiny off-diagonals:
+    every eigenvalue of the block appears `copies` times to within ~glue, so
+    deflation meets chains of nearly equal poles."""
+    rng = np.random.default_rng(seed)
+    a0 = rng.uniform(-1, 1, m)
+    b0 = rng.uniform(0.1, 1, m - 1)
+    a = np.tile(a0, copies)
+    b = np.concatenate([np.concatenate([b0, [glue]]) for _ in range(copies)])[:-1]
+    return a, b
+
+
+@pytest.mark.parametrize("kind", ["toeplitz", "random", "glued"])
+def test_deflation_counts_match_oracle(ctx, kind):
+    """Integer parity: the number of survivors of deflation, summed per tree
+    level, equals the oracle's (same tolerance, same scan order)."""
+    print(f"deflation counts {kind}", flush=True)
+    if kind == "toeplitz":
+        a, b = workloads.toeplitz(3000)
+    elif kind == "random":
+        a, b = workloads.random_uniform(3000, 5)
+    else:
+        a, b = glued(120)
+    w, Z, rep = solve(ctx, a, b, force_dense=1)
+    rep_o = {}
+    w_o, _ = odc.stedc(a, b, leaf=32, report=rep_o)
+    # oracle merges in processing order: deepest level first, left to right
+    lev = odc.split_tree(len(a), 32)
+    per = []
+    idx = 0
+    for t in range(len(lev) - 1, -1, -1):
+        cnt = sum(1 for (s0, m) in lev[t] if m > 32)
+        if cnt:
+            per.append((t, sum(rep_o["merges"][idx + u]["K"] for u in range(cnt))))
+            idx += cnt
+    for t, k in per:
+        assert rep["K_per_level"][t] == k, (t, rep["K_per_level"][t], k)
+    check_result(a, b, w, Z, w_o)
+
+
+def test_glued_clusters(ctx):
+    print("glued clusters", flush=True)
+    a, b = glued(200, glue=1e-12)
+    w, Z, rep = solve(ctx, a, b, force_dense=1)
+    ks = np.array([0, 1, 2, 1000, len(a) - 1])
+    ref = sturm.eigenvalues_by_index(a, b, ks)
+    assert np.max(np.abs(w[ks] - ref)) <= 1e-13 * odc.tnorm1(a, b)
+    assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
