@@ -265,8 +265,11 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
                      (const SampleJob*)(dj + o_sj), 1, 1, (const double*)nullptr, (double*)nullptr, 0);
   HIP_OK(hipGetLastError());
   c->timer.mark(st, 5);
-  int lds = ncand_max * sp_max;
-  if (lds > 15360) lds = 0;
+  // dynamic LDS of every node job: its ID matrix when it fits (odd leading
+  // dimension sp + 1), else the staging of its small products
+  (void)ncand_max;
+  (void)sp_max;
+  const int lds = 15360;
   static bool attr_set = false;
   if (!attr_set) {
     hipFuncSetAttribute((const void*)k_hss_compress, hipFuncAttributeMaxDynamicSharedMemorySize, 15360 * 8);

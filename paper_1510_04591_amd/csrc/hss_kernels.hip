@@ -179,7 +179,6 @@ __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__
 namespace {
 constexpr int CMAX = 512;  // candidates
 constexpr int SMAX = 256;  // samples
-constexpr int NCH = 4;     // row chunks of the per-column reductions
 
 // (value, index) maximum with ties to the smaller index
 __device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int oi) {
@@ -190,123 +189,94 @@ __device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int o
 }
 
 __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
-                       double* part, double* redv, int* redi) {
+                       double* redv, int* redi) {
+  (void)redv;
+  (void)redi;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  __shared__ int s_stop, s_p;
-  __shared__ double s_r11, s_pn, s_alpha, s_vn2;
-  for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
+  const int lane = tid & 63, wv = tid >> 6;
+  __shared__ int s_stop;
+  __shared__ double s_r11, s_vn2;
+  // squared norms of every column (a thread per column, rows in order)
+  for (int c = tid; c < n; c += blockDim.x) {
+    perm[c] = c;
+    const double* col = A + (int64_t)c * lda;
+    double s2 = 0.0;
+    for (int r = 0; r < m; ++r) s2 += col[r] * col[r];
+    nrm[c] = s2;
+  }
+  __syncthreads();
   const int kmax = min(m, n);
   int k = 0;
   for (; k < kmax; ++k) {
-    const int rows = m - k;
-    const int clen = (rows + NCH - 1) / NCH;
-    // squared norms of the remaining columns: partial sums over row chunks
-    for (int t = tid; t < NCH * (n - k); t += blockDim.x) {
-      const int c = k + t / NCH, ch = t % NCH;
-      const int r0 = k + ch * clen, r1 = min(m, r0 + clen);
-      const double* col = A + (int64_t)c * lda;
-      double s2 = 0.0;
-      for (int r = r0; r < r1; ++r) s2 += col[r] * col[r];
-      part[ch * CMAX + c] = s2;
-    }
-    __syncthreads();
-    double best = -1.0;
-    int bi = n;
-    for (int c = k + tid; c < n; c += blockDim.x) {
-      double s2 = 0.0;
-      for (int ch = 0; ch < NCH; ++ch) s2 += part[ch * CMAX + c];
-      nrm[c] = s2;
-      argmax_merge(best, bi, s2, c);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      argmax_merge(best, bi, ov, oi);
-    }
-    if (lane == 0) {
-      redv[wv] = best;
-      redi[wv] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double v = redv[0];
-      int i = redi[0];
-      for (int w2 = 1; w2 < nw; ++w2) argmax_merge(v, i, redv[w2], redi[w2]);
-      const double pn = sqrt(fmax(v, 0.0));
-      if (k == 0) s_r11 = pn;
-      s_p = i;
-      s_pn = pn;
-      s_stop = (i >= n) || (pn == 0.0) || (pn <= tol * s_r11);
+    if (wv == 0) {
+      // pivot: largest remaining norm, ties to the smaller index
+      double best = -1.0;
+      int bi = n;
+      for (int c = k + lane; c < n; c += 64) argmax_merge(best, bi, nrm[c], c);
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        argmax_merge(best, bi, ov, oi);
+      }
+      const double pn = sqrt(fmax(best, 0.0));
+      const double r11 = (k == 0) ? pn : s_r11;
+      const int stop = (bi >= n) || (pn == 0.0) || (pn <= tol * r11);
+      if (!stop) {
+        double* ck = A + (int64_t)k * lda;
+        if (bi != k) {
+          double* ci = A + (int64_t)bi * lda;
+          for (int r = lane; r < m; r += 64) {
+            const double t = ck[r];
+            ck[r] = ci[r];
+            ci[r] = t;
+          }
+        }
+        // Householder vector v = x - alpha e_1, alpha = -sign(x_0)||x||,
+        // v^T v = 2 ||x|| (||x|| + |x_0|)
+        const double x0 = ck[k];
+        const double alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
+        for (int r = k + lane; r < m; r += 64) {
+          const double x = ck[r];
+          vv[r] = (r == k) ? x - alpha : x;
+          ck[r] = (r == k) ? alpha : 0.0;
+        }
+        if (lane == 0) {
+          if (bi != k) {
+            const int t = perm[k];
+            perm[k] = perm[bi];
+            perm[bi] = t;
+            nrm[bi] = nrm[k];
+          }
+          s_vn2 = 2.0 * pn * (pn + fabs(x0));
+        }
+      }
+      if (lane == 0) {
+        if (k == 0) s_r11 = pn;
+        s_stop = stop;
+      }
     }
     __syncthreads();
     if (s_stop) break;
-    const int p = s_p;
-    const double pn = s_pn;
-    if (p != k) {
-      for (int r = tid; r < m; r += blockDim.x) {
-        const double t = A[r + (int64_t)k * lda];
-        A[r + (int64_t)k * lda] = A[r + (int64_t)p * lda];
-        A[r + (int64_t)p * lda] = t;
-      }
-      if (tid == 0) {
-        const int t = perm[k];
-        perm[k] = perm[p];
-        perm[p] = t;
-      }
-      __syncthreads();
-    }
-    // Householder vector v = x - alpha e_1, alpha = -sign(x_0) ||x||
-    if (wv == 0) {
-      const double x0 = A[k + (int64_t)k * lda];
-      const double alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
-      double sq = 0.0;
-      for (int r = k + lane; r < m; r += 64) {
-        double x = A[r + (int64_t)k * lda];
-        if (r == k) x -= alpha;
-        vv[r] = x;
-        sq += x * x;
-      }
-      sq = wave_sum(sq);
-      if (lane == 0) {
-        s_vn2 = sq;
-        s_alpha = alpha;
-      }
-    }
-    __syncthreads();
     const double vn2 = s_vn2;
-    // partial dots v^T A(:, c) over row chunks
-    for (int t = tid; t < NCH * (n - k - 1); t += blockDim.x) {
-      const int c = k + 1 + t / NCH, ch = t % NCH;
-      const int r0 = k + ch * clen, r1 = min(m, r0 + clen);
-      const double* col = A + (int64_t)c * lda;
-      double dt = 0.0;
-      for (int r = r0; r < r1; ++r) dt += vv[r] * col[r];
-      part[ch * CMAX + c] = dt;
-    }
-    __syncthreads();
+    // a thread per remaining column: reflect it and take its norm below row k
     for (int c = k + 1 + tid; c < n; c += blockDim.x) {
-      double dt = 0.0;
-      for (int ch = 0; ch < NCH; ++ch) dt += part[ch * CMAX + c];
-      nrm[c] = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;  // reflection coefficient of column c
-    }
-    __syncthreads();
-    // A(k:m, c) -= f_c v for c > k (a wave per column, lanes over rows);
-    // column k becomes (alpha, 0, ..., 0)
-    for (int c = k + wv; c < n; c += nw) {
       double* col = A + (int64_t)c * lda;
-      if (c == k) {
-        for (int r = k + lane; r < m; r += 64) col[r] = (r == k) ? s_alpha : 0.0;
-      } else {
-        const double f = nrm[c];
-        for (int r = k + lane; r < m; r += 64) col[r] -= f * vv[r];
+      double dt = 0.0;
+      for (int r = k; r < m; ++r) dt += vv[r] * col[r];
+      const double f = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;
+      double s2 = 0.0;
+      for (int r = k; r < m; ++r) {
+        const double x = col[r] - f * vv[r];
+        col[r] = x;
+        if (r > k) s2 += x * x;
       }
+      nrm[c] = s2;
     }
     __syncthreads();
   }
   // T = R11^-1 R12 in place: back substitution, a wave per column (the
   // update of the remaining rows is spread over the lanes)
-  for (int c = k + wv; c < n; c += nw) {
+  for (int c = k + wv; c < n; c += (int)(blockDim.x >> 6)) {
     double* col = A + (int64_t)c * lda;
     for (int j = k - 1; j >= 0; --j) {
       const double xj = col[j] / A[j + (int64_t)j * lda];
@@ -393,7 +363,6 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
                                                       const NodeJob* __restrict__ jobs, int lds_doubles) {
   extern __shared__ double dyn[];
   __shared__ double s_nrm[CMAX];
-  __shared__ double s_part[NCH * CMAX];
   __shared__ int s_perm[CMAX];
   __shared__ int s_inv[CMAX];
   __shared__ int s_cand[CMAX];
@@ -467,12 +436,17 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     }
     __syncthreads();
     // working copy: columns = candidates, rows = samples (ld sp)
-    double* Aw = (lds_doubles >= nc * sp) ? dyn : (W0 + (int64_t)nc * sp);
-    for (int e = tid; e < nc * sp; e += blockDim.x) Aw[e] = W0[e];
+    // working copy with an odd leading dimension in LDS (no bank aliasing of
+    // columns), or the second half of the work area
+    const bool in_lds = lds_doubles >= nc * (sp + 1);
+    const int lw = in_lds ? sp + 1 : sp;
+    double* Aw = in_lds ? dyn : (W0 + (int64_t)nc * sp);
+    for (int c = tid >> 6; c < nc; c += blockDim.x >> 6)
+      for (int r = tid & 63; r < sp; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
     __syncthreads();
-    const int k = cpqr_id(Aw, sp, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_part, s_redv, s_redi);
+    const int k = cpqr_id(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
     double* U = ar + (side ? nd.offV : nd.offU);
-    write_interp(Aw, sp, nc, k, s_perm, s_inv, U);
+    write_interp(Aw, lw, nc, k, s_perm, s_inv, U);
     int* skel = ia + (side ? nd.offSc : nd.offSr);
     double* sk = ar + (side ? nd.offTs : nd.offPs);
     for (int j = tid; j < k; j += blockDim.x) skel[j] = s_cand[s_perm[j]];
