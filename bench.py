@@ -143,26 +143,37 @@ def main():
 
     head = "hss" if "hss" in out else "dense"
     t_head, reps = out[head]
-    # dominant kernel of the headline path: the phase with the largest time
-    ph = np.sum([r["t_phase"] for r in reps], axis=0)
-    pf = np.sum([r["phase_flops"] for r in reps], axis=0)
-    pb = np.sum([r["phase_bytes"] for r in reps], axis=0)
-    pl = np.sum([r["phase_launches"] for r in reps], axis=0)
     names = ["leaves", "deflation", "secular", "loewner_v", "dense_gemm", "hss_sampling", "hss_compress",
              "hss_check", "hss_multiply", "order_pack"]
-    dom = int(np.argmax(ph[:10] * (pf[:10] > 0))) if np.any(pf[:10] > 0) else int(np.argmax(ph[:10]))
-    launches = max(1, int(pl[dom]))
-    avg_dur = ph[dom] / launches
-    if pf[dom] > 0 and pf[dom] / max(pb[dom], 1) > 10:
-        achieved = pf[dom] / launches / avg_dur / 1e12
+    ph = np.sum([r["t_phase"] for r in reps], axis=0)
+    # dominant kernel: the largest total time among the kernels whose
+    # algorithmic flops or bytes the library counts; each launch is
+    # bracketed by HIP events on the library's stream
+    kt = np.sum([r["kern_time"] for r in reps], axis=0)
+    kf = np.sum([r["kern_flops"] for r in reps], axis=0)
+    kb = np.sum([r["kern_bytes"] for r in reps], axis=0)
+    kl = np.sum([r["kern_launches"] for r in reps], axis=0)
+    kn = adc.adc_report.KERNELS
+    counted = [i for i in range(len(kn)) if kl[i] > 0 and (kf[i] > 0 or kb[i] > 0)]
+    dom = max(counted, key=lambda i: kt[i])
+    launches = int(kl[dom])
+    avg_dur = kt[dom] / launches
+    if kf[dom] / max(kb[dom], 1.0) > PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+        achieved = kf[dom] / launches / avg_dur / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
     else:
-        achieved = pb[dom] / launches / avg_dur / 1e9
+        achieved = kb[dom] / launches / avg_dur / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = names[dom]
+    roof["kernel"] = kn[dom]
+    roof["launches_per_step"] = launches / len(reps)
     roof["avg_launch_ms"] = 1e3 * avg_dur
+    kernels = {kn[i]: {"ms_per_step": 1e3 * kt[i] / len(reps), "launches_per_step": kl[i] / len(reps),
+                       "avg_launch_us": 1e6 * kt[i] / max(kl[i], 1),
+                       "tflops": (kf[i] / kt[i] / 1e12) if kf[i] > 0 else None,
+                       "gbs": (kb[i] / kt[i] / 1e9) if kb[i] > 0 else None}
+               for i in range(len(kn)) if kl[i] > 0}
 
     r0 = reps[-1]
     res = {
@@ -187,6 +198,7 @@ def main():
         "phases_s": {n_: float(ph[i] / len(reps)) for i, n_ in enumerate(names)},
         "validation": val,
         "roofline": roof,
+        "kernels": kernels,
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()

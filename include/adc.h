@@ -107,6 +107,15 @@ typedef struct adc_report {
   double  flops_model;       /* algorithmic flops of the eigenvector updates   */
   double  bytes_model;       /* algorithmic HBM bytes of the updates           */
   double  check_err_max;     /* largest HSS check error accepted               */
+  /* Per-kernel figures, each launch bracketed by HIP events on the context
+   * stream: 0 k_gemm_f64 (128-wide FP64 MFMA GEMM), 1 k_gemm_f64_n64
+   * (64-wide), 2 k_hss_sample, 3 k_pack_rot, 4 k_secular, 5 k_hss_compress.
+   * Times in seconds; flops and bytes are the algorithmic counts of the
+   * launches (operands read once, results written once). */
+  double  kern_time[8];
+  double  kern_flops[8];
+  double  kern_bytes[8];
+  int32_t kern_launches[8];
 } adc_report;
 
 /* ---------------------------------------------------------------- context */

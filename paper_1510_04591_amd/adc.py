@@ -47,7 +47,11 @@ class adc_report(C.Structure):
         ("t_phase", C.c_double * 12), ("phase_flops", C.c_double * 12), ("phase_bytes", C.c_double * 12),
         ("phase_launches", C.c_int32 * 12), ("flops_model", C.c_double), ("bytes_model", C.c_double),
         ("check_err_max", C.c_double),
+        ("kern_time", C.c_double * 8), ("kern_flops", C.c_double * 8), ("kern_bytes", C.c_double * 8),
+        ("kern_launches", C.c_int32 * 8),
     ]
+
+    KERNELS = ("k_gemm_f64", "k_gemm_f64_n64", "k_hss_sample", "k_pack_rot", "k_secular", "k_hss_compress")
 
     def as_dict(self):
         L = self.levels
@@ -58,7 +62,9 @@ class adc_report(C.Structure):
                     samples=self.samples, t_phase=list(self.t_phase), phase_flops=list(self.phase_flops),
                     phase_bytes=list(self.phase_bytes), phase_launches=list(self.phase_launches),
                     flops_model=self.flops_model,
-                    bytes_model=self.bytes_model, check_err_max=self.check_err_max)
+                    bytes_model=self.bytes_model, check_err_max=self.check_err_max,
+                    kern_time=list(self.kern_time), kern_flops=list(self.kern_flops),
+                    kern_bytes=list(self.kern_bytes), kern_launches=list(self.kern_launches))
 
 
 class AdcError(RuntimeError):

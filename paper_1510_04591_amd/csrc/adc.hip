@@ -91,6 +91,7 @@ void adc_ctx_s::release() {
   host_stage = nullptr;
   host_stage_bytes = 0;
   timer.destroy();
+  ktimer.destroy();
   mlp_release(this);
 }
 

@@ -67,6 +67,63 @@ struct PhaseTimer {
   }
 };
 
+// Per-launch timing of selected kernels: an event pair around each launch,
+// resolved after the stream has been synchronised.
+enum KernId { KT_GEMM = 0, KT_GEMM64 = 1, KT_SAMPLE = 2, KT_PACK = 3, KT_SECULAR = 4, KT_COMPRESS = 5 };
+struct KernTimer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kid;
+  std::vector<double> fl, by;
+  bool on = false;
+  void begin(bool enable) {
+    on = enable;
+    kid.clear();
+    fl.clear();
+    by.clear();
+  }
+  void pre(hipStream_t s) {
+    if (!on) return;
+    const size_t i = kid.size();
+    while (ev.size() < 2 * i + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      ev.push_back(e);
+    }
+    hipEventRecord(ev[2 * i], s);
+  }
+  void post(hipStream_t s, int k, double flops, double bytes) {
+    if (!on) return;
+    const size_t i = kid.size();
+    hipEventRecord(ev[2 * i + 1], s);
+    kid.push_back(k);
+    fl.push_back(flops);
+    by.push_back(bytes);
+  }
+  // the stream must have been synchronised
+  void collect(adc_report* rep) {
+    if (!on) return;
+    for (size_t i = 0; i < kid.size(); ++i) {
+      float ms = 0.f;
+      if (rep && hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+        rep->kern_time[kid[i]] += 1e-3 * ms;
+        rep->kern_flops[kid[i]] += fl[i];
+        rep->kern_bytes[kid[i]] += by[i];
+        rep->kern_launches[kid[i]] += 1;
+      }
+    }
+    kid.clear();
+    fl.clear();
+    by.clear();
+  }
+  void destroy() {
+    for (auto e : ev) hipEventDestroy(e);
+    ev.clear();
+  }
+};
+
 struct adc_ctx_s {
   struct Buf {
     void* ptr = nullptr;
@@ -80,6 +137,7 @@ struct adc_ctx_s {
   MlpState* mlp = nullptr;
   void* batch_cache = nullptr;  // graph cache of the batched solver
   PhaseTimer timer;
+  KernTimer ktimer;
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);
   void release();

@@ -267,6 +267,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     std::memcpy(h_lm, lm[0].data(), n0 * 4);
     std::memcpy(h_lm + n0, lm[1].data(), lm[1].size() * 4);
     HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
+    c->ktimer.begin(rep != nullptr);
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_tear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag, offdiag, d_sp,
                        (int)plan.splits.size(), L.a, n);
@@ -281,6 +282,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, L.noconv, INT32_MAX);
     HIP_OK(hipStreamSynchronize(st));  // staging buffer is reused below
     c->timer.collect(rep);
+    c->ktimer.collect(rep);
   }
 
   if (rep) rep->levels = nlev;
@@ -349,6 +351,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     HIP_OK(hipMemcpyAsync(h_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     c->timer.collect(rep);
+    c->ktimer.collect(rep);
 
     // --- host decisions and launch lists
     int64_t Kmax = 0, Ksum = 0, nsum = 0;
@@ -394,6 +397,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     GemmProb* h_gp = ha.take<GemmProb>(2 * nm);
     GemmProb* d_gp = da.take<GemmProb>(2 * nm);
     int ngp = 0, gtiles = 0;
+    double lvl_gf = 0.0, lvl_gb = 0.0;
     for (int g2 = 0; g2 < nm; ++g2) {
       const MergeDev& M = h_m[g2];
       if (M.K == 0 || M.mode != 0) continue;
@@ -425,6 +429,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
         const double by = 8.0 * ((double)P.M * P.K + (double)P.K * P.N + (double)P.M * P.N);
         flops += f;
         bytes += by;
+        lvl_gf += f;
+        lvl_gb += by;
         if (rep) {
           rep->phase_flops[4] += f;
           rep->phase_bytes[4] += by;
@@ -438,19 +444,30 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     const int W = pick_waves(Kmax);
     c->timer.start(st, rep != nullptr);
     if (nrb) {
+      c->ktimer.pre(st);
       hipLaunchKernelGGL(k_secular, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.lam, L.gam, L.mu,
                          o.max_iter, L.noconv);
+      c->ktimer.post(st, KT_SECULAR, 0.0, 0.0);
       c->timer.mark(st, 2);
       hipLaunchKernelGGL(k_lowner, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.gam, L.mu, L.uh);
       hipLaunchKernelGGL(k_vnorm, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.gam, L.mu, L.uh, L.v);
       c->timer.mark(st, 3);
     }
     hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
+    // packing: every column's support rows read once, all n rows written
+    double pack_by = 0.0;
+    for (int g2 = 0; g2 < nm; ++g2) pack_by += 12.0 * (double)h_m[g2].n * h_m[g2].n;
+    c->ktimer.pre(st);
     hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B);
+    c->ktimer.post(st, KT_PACK, 0.0, pack_by);
     HIP_OK(hipGetLastError());
     if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, ncols, 1);
     c->timer.mark(st, 9);
-    if (gtiles) hipLaunchKernelGGL(k_gemm_f64, dim3(gtiles), dim3(256), 0, st, d_gp, ngp);
+    if (gtiles) {
+      c->ktimer.pre(st);
+      hipLaunchKernelGGL(k_gemm_f64, dim3(gtiles), dim3(256), 0, st, d_gp, ngp);
+      c->ktimer.post(st, KT_GEMM, lvl_gf, lvl_gb);
+    }
     c->timer.mark(st, 4);
     HIP_OK(hipGetLastError());
     if (hss_here) {
@@ -458,6 +475,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     }
     HIP_OK(hipStreamSynchronize(st));  // staging buffer reused by the next level
     c->timer.collect(rep);
+    c->ktimer.collect(rep);
 
     if (rep && t < 64) {
       rep->n_per_level[t] = nsum;
@@ -471,6 +489,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
   int nc = INT32_MAX;
   HIP_OK(hipMemcpyAsync(&nc, L.noconv, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
+  c->ktimer.begin(false);
   if (rep) {
     rep->flops_model += flops;
     rep->bytes_model += bytes;

@@ -259,10 +259,21 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   for (int l = 0; l <= Lmax; ++l) o_lj[l] = put(lj[l].data(), lj[l].size() * sizeof(NodeJob));
   HIP_OK(hipMemcpyAsync(dj, hj.data(), off, hipMemcpyHostToDevice, st));
 
-  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms,
-                     (const SampleJob*)(dj + o_sj), 0, 1, (const double*)nullptr, (double*)nullptr, 0);
-  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms,
-                     (const SampleJob*)(dj + o_sj), 1, 1, (const double*)nullptr, (double*)nullptr, 0);
+  // algorithmic flops of one sampling pass: the off-diagonal-block part of
+  // Q' times s columns; bytes: Omega read, the samples written
+  double sfl = 0.0, sby = 0.0;
+  for (auto& m : hb.ms) {
+    double dsq = 0.0;
+    for (size_t i = 0; i + 1 < m.bounds.size(); ++i) dsq += (double)(m.bounds[i + 1] - m.bounds[i]) * (m.bounds[i + 1] - m.bounds[i]);
+    sfl += 2.0 * m.s * ((double)m.K * m.K - dsq);
+    sby += 16.0 * m.K * m.s;
+  }
+  for (int tr = 0; tr < 2; ++tr) {
+    c->ktimer.pre(st);
+    hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms,
+                       (const SampleJob*)(dj + o_sj), tr, 1, (const double*)nullptr, (double*)nullptr, 0);
+    c->ktimer.post(st, KT_SAMPLE, sfl, sby);
+  }
   HIP_OK(hipGetLastError());
   c->timer.mark(st, 5);
   // dynamic LDS of every node job: its ID matrix when it fits (odd leading
@@ -277,8 +288,10 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   }
   for (int l = Lmax; l >= 0; --l) {
     if (lj[l].empty()) continue;
+    c->ktimer.pre(st);
     hipLaunchKernelGGL(k_hss_compress, dim3((unsigned)lj[l].size()), dim3(1024), (size_t)lds * 8, st, hb.d_ms,
                        (const NodeJob*)(dj + o_lj[l]), lds);
+    c->ktimer.post(st, KT_COMPRESS, 0.0, 0.0);
     HIP_OK(hipGetLastError());
   }
   c->timer.mark(st, 6);
@@ -311,10 +324,17 @@ static void push_prob(std::vector<GemmProb>& v, const GemmProb& p) { v.push_back
 static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops) {
   if (probs.empty()) return ADC_OK;
   std::vector<GemmProb> narrow, wide;
+  double pf[2] = {0.0, 0.0}, pb[2] = {0.0, 0.0};
   for (auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
-    if (flops) *flops += 2.0 * p.M * (double)p.N * (p.K + p.K2);
-    (p.N <= 64 ? narrow : wide).push_back(p);
+    const double f = 2.0 * p.M * (double)p.N * (p.K + p.K2);
+    const double by = 8.0 * ((double)p.M * (p.K + p.K2) + (double)(p.K + p.K2) * p.N +
+                             (double)p.M * p.N * (p.beta != 0.0 ? 2 : 1));
+    if (flops) *flops += f;
+    const int w = p.N <= 64 ? 0 : 1;
+    pf[w] += f;
+    pb[w] += by;
+    (w ? wide : narrow).push_back(p);
   }
   hipStream_t st = c->stream;
   for (int pass = 0; pass < 2; ++pass) {
@@ -330,10 +350,12 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
     void* dp;
     ADC_TRY(c->buffer(pass ? SLOT_GEMM_B : SLOT_GEMM_A, L.size() * sizeof(GemmProb) + 256, &dp));
     HIP_OK(hipMemcpyAsync(dp, L.data(), L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
+    c->ktimer.pre(st);
     if (pass)
       hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, st, (const GemmProb*)dp, (int)L.size());
     else
       hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(256), 0, st, (const GemmProb*)dp, (int)L.size());
+    c->ktimer.post(st, pass ? KT_GEMM : KT_GEMM64, pf[pass], pb[pass]);
     HIP_OK(hipGetLastError());
     // the descriptor arrays are host vectors: wait before they are reused
     HIP_OK(hipStreamSynchronize(st));
@@ -716,6 +738,7 @@ extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const
                                     const double* uh, const double* v, const double* omega, int32_t s,
                                     const adc_opts* opts_in, adc_hss* out) {
   if (!c || !out || K < 2 || K > (1 << 24) || !d || !gam || !mu || !uh || !v) return ADC_ERR_ARG;
+  c->ktimer.begin(false);
   *out = nullptr;
   adc_opts o;
   if (opts_in) o = *opts_in;
@@ -805,6 +828,7 @@ extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const
 extern "C" adc_status adc_hss_apply(adc_ctx c, adc_hss h, int64_t P, const double* X, int64_t ldx, double* Y,
                                     int64_t ldy) {
   if (!c || !h || P < 0 || P > INT32_MAX || !X || !Y || ldx < P || ldy < P) return ADC_ERR_ARG;
+  c->ktimer.begin(false);
   if (P == 0) return ADC_OK;
   DeviceGuard gd(c->device);
   HssBatch hb;
