@@ -51,7 +51,10 @@ typedef struct adc_hss_s* adc_hss;
 
 /* How the HSS sample count s = r + p is chosen for one merge.
  * BOUND: r from eq. (bounds) over neighbouring leaf segments (Section 4.1).
- * MLP:   r from the learned rank predictor (adc_mlp_*), BOUND as a floor of 8.
+ * MLP:   r from the learned rank predictor (adc_mlp_*): per leaf boundary a
+ *        prediction y_b of log2 of the ID rank, r = ceil(2^max_b y_b) + 4,
+ *        clamped to [8, r_cap]; the BOUND estimate while no model is set.
+ *        The adaptive check (opts.check_tol) judges either choice.
  * FIXED: r = opts.fixed_rank. */
 typedef enum adc_rank_mode { ADC_RANK_BOUND = 0, ADC_RANK_MLP = 1, ADC_RANK_FIXED = 2 } adc_rank_mode;
 
@@ -215,22 +218,40 @@ adc_status adc_hss_free(adc_hss h);
 
 /* -------------------------------------------- learned rank predictor (MLP) */
 
-/* The predictor is a 16-64-64-1 FP32 MLP with ReLU (weights owned by the
- * context).  Features (16 per HSS block boundary) are produced by
- * adc_mlp_features; targets are log2 of the ID rank observed at that boundary.
+/* The predictor replaces the a-priori rank of eq. (bounds) (Section 4.1):
+ * per interior leaf boundary of an HSS merge it predicts log2 of the rank
+ * the interpolative decompositions find there (the largest row or column
+ * ID rank of the HSS nodes whose index range starts or ends at it).  It is a
+ * 16-64-64-1 FP32 MLP with ReLU whose weights the context owns: 5313
+ * parameters packed as W1 (64x16), b1, W2 (64x64), b2, W3 (1x64), b3, each W
+ * row-major [out][in].
  *
- * adc_mlp_features: for the generators (d, gam, mu) of a merge of size K and
- *   the leaf boundaries bounds[nb+2] (host, first 0, last K), writes the
- *   feature matrix feat[nb x 16] (device, FP32, row-major).
- * adc_mlp_init:  random init from `seed` (host call; weights on device).
- * adc_mlp_train: `epochs` passes of Adam (lr, beta1 0.9, beta2 0.999, eps
- *   1e-8) over B samples (X[B x 16], y[B], device FP32) in minibatches of
- *   `batch`; *loss_out (host) receives the final-epoch mean squared error.
- * adc_mlp_infer: y[B] = MLP(X[B x 16]).
- * adc_mlp_grad:  loss and gradients of one minibatch, for checking
- *   (g_out: device FP32 array of the 5377 parameters, layer order W1 b1 W2 b2
- *   W3 b3, row-major W[out x in]).
- * adc_mlp_get/set: copy the 5377 parameters to/from a device FP32 array. */
+ * adc_mlp_features: for the generators (d, gam, mu; device FP64, eq.
+ *   (d-lambda)) of a merge of size K and the leaf boundaries bounds[nb+2]
+ *   (host, strictly increasing, first 0, last K), writes feat[nb x 16]
+ *   (device FP32, row-major), row b for the boundary bounds[b+1].  The 16
+ *   features are scale-free ratios of pole gaps and root distances (the
+ *   list is in mlp.hip).  Asynchronous.
+ * adc_mlp_init:  uniform fan-in initialisation from `seed`, biases zero, Adam
+ *   state cleared.  Blocking.
+ * adc_mlp_train: `epochs` passes of Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ *   step lr) over the B rows of X[B x 16], y[B] (device FP32) in minibatches
+ *   of `batch` rows taken in order (shuffle beforehand if wanted); loss: mean
+ *   squared error; *loss_out (host) gets the last pass's mean of the
+ *   minibatch losses before their updates.  Blocking.  ADC_ERR_ARG before
+ *   adc_mlp_init / adc_mlp_set.
+ * adc_mlp_infer: y[B] = MLP(X[B x 16]), device FP32.  Asynchronous.
+ * adc_mlp_grad:  loss and gradient of the mean squared error over all B rows
+ *   (g_out: device FP32, 5313 values packed like the parameters).  Blocking.
+ * adc_mlp_get/set: copy the 5313 parameters to / from a device FP32 array
+ *   (set clears the Adam state).  Blocking.
+ * adc_mlp_collect: runs adc_stedc on (diag, offdiag) with `opts` (rank
+ *   estimate forced to BOUND) and, for every HSS merge that passes the check,
+ *   appends one row per leaf boundary to X[max_rows x 16] (features) and
+ *   y[max_rows] (log2 of the observed boundary rank), device FP32, as long
+ *   as the merge's rows fit; *rows_out (host) receives the count.  Use opts
+ *   with small hss_min_k and hss_leaf and hss_levels = -1 to collect from
+ *   matrices whose merges would not use HSS otherwise.  Blocking. */
 adc_status adc_mlp_features(adc_ctx ctx, int64_t K, const double* d, const double* gam,
                             const double* mu, const int64_t* bounds, int32_t nb, float* feat);
 adc_status adc_mlp_init(adc_ctx ctx, uint64_t seed);
@@ -241,6 +262,9 @@ adc_status adc_mlp_grad(adc_ctx ctx, int32_t B, const float* X, const float* y, 
                         float* loss_out);
 adc_status adc_mlp_get(adc_ctx ctx, float* params);
 adc_status adc_mlp_set(adc_ctx ctx, const float* params);
+adc_status adc_mlp_collect(adc_ctx ctx, int64_t n, const double* diag, const double* offdiag,
+                           double* w, double* Z, int64_t ldz, const adc_opts* opts,
+                           int64_t max_rows, float* X, float* y, int64_t* rows_out);
 
 #ifdef __cplusplus
 }

@@ -105,6 +105,7 @@ _SIGS = {
     "adc_mlp_grad": (_P, _I32, _P, _P, _P, C.POINTER(C.c_float)),
     "adc_mlp_get": (_P, _P),
     "adc_mlp_set": (_P, _P),
+    "adc_mlp_collect": (_P, _I64, _P, _P, _P, _P, _I64, C.POINTER(adc_opts), _I64, _P, _P, C.POINTER(_I64)),
 }
 EXPORTS = tuple(_SIGS) + ("adc_status_string",)
 
@@ -262,6 +263,14 @@ def adc_mlp_get(ctx, params):
 
 def adc_mlp_set(ctx, params):
     return lib().adc_mlp_set(ctx, _ptr(params))
+
+
+def adc_mlp_collect(ctx, n, diag, offdiag, w, Z, ldz, o, max_rows, X, y):
+    rows = _I64()
+    st = lib().adc_mlp_collect(ctx, int(n), _ptr(diag), _ptr(offdiag), _ptr(w), _ptr(Z), int(ldz),
+                               C.byref(o) if o is not None else None, int(max_rows), _ptr(X), _ptr(y),
+                               C.byref(rows))
+    return st, rows.value
 
 
 # ------------------------------------------------------------ convenience

@@ -183,9 +183,16 @@ adc_status validate_opts_ext(const adc_opts& o);
 // order (the fallback of a failed HSS check).
 adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const MergeDev& M, const LevelBufs& B,
                                double* flops);
-// HSS sample rank from the learned predictor (r_bound when no model is loaded).
+// HSS sample rank from the learned predictor (r_bound when no model is
+// loaded); d, gam, mu are device arrays of the merge.
 int mlp_rank(adc_ctx c, const double* d, const double* gam, const double* mu, int K, const std::vector<int>& bounds,
              const adc_opts& o, int r_bound);
+// Collection mode of adc_mlp_collect: features and observed boundary ranks
+// of one HSS merge (device generators, host node table).
+bool mlp_collecting(adc_ctx c);
+adc_status mlp_collect_merge(adc_ctx c, const double* d, const double* gam, const double* mu, int K,
+                             const std::vector<int>& bounds, const std::vector<int>& lo, const std::vector<int>& hi,
+                             const std::vector<int>& kr, const std::vector<int>& kc);
 // Rank estimate of eq. (bounds) over leaf boundaries (may move boundaries).
 int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
                       const adc_opts& o);

@@ -688,7 +688,8 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     HIP_OK(hipStreamSynchronize(st));
     m.r = hss_rank_estimate(d.data(), g2.data(), mu.data(), M.K, m.bounds, o);
     if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
-    if (o.rank_mode == ADC_RANK_MLP) m.r = mlp_rank(c, d.data(), g2.data(), mu.data(), M.K, m.bounds, o, m.r);
+    if (o.rank_mode == ADC_RANK_MLP && !mlp_collecting(c))
+      m.r = mlp_rank(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, o, m.r);
     m.dev.d = B.dS + M.s0;
     m.dev.gam = B.gam + M.s0;
     m.dev.mu = B.mu + M.s0;
@@ -708,6 +709,16 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
       rep->max_rank = std::max(rep->max_rank, m.max_rank);
       rep->samples = std::max(rep->samples, m.s);
       if (m.pass) rep->check_err_max = std::max(rep->check_err_max, m.err);
+    }
+    if (m.pass && mlp_collecting(c)) {
+      std::vector<int> lo, hi, kr, kc;
+      for (auto& nd : m.nodes) {
+        lo.push_back(nd.lo);
+        hi.push_back(nd.hi);
+        kr.push_back(nd.kr);
+        kc.push_back(nd.kc);
+      }
+      ADC_TRY(mlp_collect_merge(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, lo, hi, kr, kc));
     }
     if (m.pass) {
       aj.push_back(ApplyJob{(int)t, B.pk + M.zoff, (int64_t)M.n, M.n, B.Znew + M.s0 + M.s0 * B.ldn, B.ldn,

@@ -99,3 +99,21 @@ def spectrum(kind, N, seed=5):
         raise ValueError(kind)
     w = rng.standard_normal(N)
     return lam, w / np.linalg.norm(w)
+
+
+def prescribed_tridiagonal(kind, N, seed=5):
+    """Tridiagonal matrix with the spectrum `spectrum(kind, N, seed)`: the
+    Jacobi matrix of the weights w_i^2 at the nodes lam_i, i.e. Lanczos on
+    diag(lam) started from w, computed stably as the Householder
+    tridiagonalization of H diag(lam) H with H the reflector taking e_1 to w
+    (the first column of the reduction's basis stays e_1).  Off-diagonals are
+    returned as absolute values (a diagonal sign similarity)."""
+    from scipy.linalg import hessenberg
+    lam, w = spectrum(kind, N, seed)
+    u = w.copy()
+    u[0] -= 1.0 if w[0] < 0 else -1.0  # u = w + sign(w_0) e_1: H e_1 = -sign(w_0) w
+    u /= np.linalg.norm(u)
+    Lu = lam * u
+    A = np.diag(lam) - 2.0 * (np.outer(u, Lu) + np.outer(Lu, u)) + 4.0 * float(u @ Lu) * np.outer(u, u)
+    Hs = hessenberg(A, overwrite_a=True, check_finite=False)
+    return np.diag(Hs).copy(), np.abs(np.diag(Hs, -1)).copy()

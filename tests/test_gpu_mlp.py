@@ -1,0 +1,191 @@
+"""Learned rank predictor on the GPU vs the FP64 oracle: features, forward,
+gradient, Adam steps; then the collection mode, training on the GPU and the
+gain over eq. (bounds) on matrices with prescribed spectra."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dc as odc, mlp as omlp, secular as osec
+from paper_1510_04591_amd import adc, workloads
+from conftest import cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def gens(K, seed, spread):
+    d, z, rho = workloads.random_merge(K, seed, spread)
+    _, gam, mu, _ = osec.secular_roots(d, z, rho)
+    return d, gam, mu
+
+
+@pytest.mark.parametrize("K,spread,bounds", [
+    (300, "uniform", [0, 37, 75, 150, 225, 300]),
+    (1000, "clustered", [0, 125, 250, 375, 500, 625, 750, 875, 1000]),
+    (2500, "normal", [0, 156, 312, 469, 625, 781, 937, 1094, 1250, 1406, 1562, 1719, 1875, 2031, 2187, 2344,
+                      2500]),
+    (40, "uniform", [0, 20, 40]),
+])
+def test_features_match_oracle(ctx, K, spread, bounds):
+    print(f"features K={K} {spread}", flush=True)
+    d, gam, mu = gens(K, 3, spread)
+    nb = len(bounds) - 2
+    feat = torch.empty((nb, 16), dtype=torch.float32, device="cuda")
+    st = adc.adc_mlp_features(ctx.h, K, cuda(d), cuda(gam), cuda(mu), bounds, feat)
+    assert st == adc.ADC_OK
+    torch.cuda.synchronize()
+    F = omlp.features(d, gam, mu, bounds)
+    err = np.abs(feat.cpu().numpy().astype(np.float64) - F)
+    assert np.max(err) <= 1e-6 + 1e-6 * np.max(np.abs(F)), np.unravel_index(np.argmax(err), err.shape)
+
+
+def set_params(ctx, theta):
+    p = torch.from_numpy(np.asarray(theta, np.float32)).cuda()
+    assert adc.adc_mlp_set(ctx.h, p) == adc.ADC_OK
+
+
+def get_params(ctx):
+    p = torch.empty(omlp.NPARAM, dtype=torch.float32, device="cuda")
+    assert adc.adc_mlp_get(ctx.h, p) == adc.ADC_OK
+    return p.cpu().numpy().astype(np.float64)
+
+
+def test_forward_matches_oracle(ctx):
+    rng = np.random.default_rng(11)
+    th = rng.normal(0, 0.3, omlp.NPARAM).astype(np.float32).astype(np.float64)
+    set_params(ctx, th)
+    X = rng.normal(0, 1, (1000, 16)).astype(np.float32)
+    y = torch.empty(1000, dtype=torch.float32, device="cuda")
+    assert adc.adc_mlp_infer(ctx.h, 1000, torch.from_numpy(X).cuda(), y) == adc.ADC_OK
+    ref = omlp.forward(th, X.astype(np.float64))
+    assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+    assert np.allclose(get_params(ctx), th, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("B", [1, 64, 300])
+def test_gradient_matches_oracle(ctx, B):
+    print(f"gradient B={B}", flush=True)
+    rng = np.random.default_rng(12 + B)
+    th = rng.normal(0, 0.3, omlp.NPARAM).astype(np.float32).astype(np.float64)
+    set_params(ctx, th)
+    X = rng.normal(0, 1, (B, 16)).astype(np.float32)
+    y = rng.normal(0, 2, B).astype(np.float32)
+    g = torch.empty(omlp.NPARAM, dtype=torch.float32, device="cuda")
+    st, loss = adc.adc_mlp_grad(ctx.h, B, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), g)
+    assert st == adc.ADC_OK
+    loss_o, g_o = omlp.loss_grad(th, X.astype(np.float64), y.astype(np.float64))
+    assert abs(loss - loss_o) <= 1e-5 * loss_o
+    gg = g.cpu().numpy()
+    assert np.max(np.abs(gg - g_o)) <= 1e-4 * np.max(np.abs(g_o)) + 1e-7
+
+
+def test_adam_steps_match_oracle(ctx):
+    """Two passes over 250 rows in minibatches of 100 (ragged last batch and
+    ragged 64-row chunks): parameters and the reported loss follow the FP64
+    Adam of the oracle."""
+    rng = np.random.default_rng(13)
+    th0 = rng.normal(0, 0.3, omlp.NPARAM).astype(np.float32).astype(np.float64)
+    set_params(ctx, th0)
+    X = rng.normal(0, 1, (250, 16)).astype(np.float32)
+    y = (X @ rng.normal(0, 1, 16) + 1.0).astype(np.float32)
+    st, loss = adc.adc_mlp_train(ctx.h, 250, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), 2, 100, 1e-3)
+    assert st == adc.ADC_OK
+    th_o, _, loss_o = omlp.adam_train(th0, X.astype(np.float64), y.astype(np.float64), 2, 100, 1e-3)
+    th = get_params(ctx)
+    step = np.linalg.norm(th_o - th0)
+    assert np.linalg.norm(th - th_o) <= 1e-2 * step
+    # most parameters agree closely; a first Adam step is lr sign(g), so a
+    # gradient component at rounding level may take either sign
+    close = np.abs(th - th_o) <= 1e-6 + 1e-3 * np.abs(th_o - th0)
+    assert np.mean(close) >= 0.99
+    assert abs(loss - loss_o) <= 1e-3 * loss_o
+
+
+def collect(ctx, a, b, o, cap=1 << 16):
+    n = len(a)
+    X = torch.empty((cap, 16), dtype=torch.float32, device="cuda")
+    y = torch.empty(cap, dtype=torch.float32, device="cuda")
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    st, rows = adc.adc_mlp_collect(ctx.h, n, cuda(a), cuda(b), w, Z, n, o, cap, X, y)
+    assert st == adc.ADC_OK
+    torch.cuda.synchronize()
+    return X[:rows].clone(), y[:rows].clone(), w.cpu().numpy(), Z.t().cpu().numpy()
+
+
+def test_collection_rows_match_oracle_features(ctx):
+    """Collected rows are finite, scale-free features and targets log2 of
+    ranks >= 1, and the solve that produced them stays exact."""
+    a, b = workloads.toeplitz(1024)
+    o = adc.opts(dc_leaf=32, hss_leaf=64, hss_min_k=128, hss_levels=-1)
+    X, y, w, Z = collect(ctx, a, b, o)
+    assert X.shape[0] > 0
+    yy = y.cpu().numpy()
+    assert np.all(yy >= 0) and np.all(yy <= np.log2(200))
+    assert np.all(np.isfinite(X.cpu().numpy())) and np.max(np.abs(X.cpu().numpy())) <= 2.0
+    k = np.arange(1, 1025)
+    assert np.max(np.abs(w - np.sort(2 + 2 * np.cos(k * np.pi / 1025)))) <= 1e-13 * 4
+    assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
+
+
+_TRAINED = {}
+
+
+def trained_model(ctx):
+    """Collect from the training families (Toeplitz, random uniform and the
+    mixed batch of 200..4000), train on the GPU, return the final loss."""
+    if "loss" in _TRAINED:
+        set_params(ctx, _TRAINED["theta"])
+        return _TRAINED["loss"]
+    Xs, ys = [], []
+    mats = [workloads.toeplitz(4096), workloads.random_uniform(4096, 2)]
+    mats += [workloads.batched(8, 4)[i] for i in (0, 1, 5, 6)]
+    for a, b in mats:
+        print(f"collect N={len(a)}", flush=True)
+        for leaf in (32, 64, 128):
+            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=2 * leaf, hss_levels=-1)
+            X, y, _, _ = collect(ctx, a, b, o)
+            Xs.append(X)
+            ys.append(y)
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    perm = torch.from_numpy(np.random.default_rng(0).permutation(X.shape[0])).cuda()
+    X = X[perm].contiguous()
+    y = y[perm].contiguous()
+    print(f"training rows {X.shape[0]}", flush=True)
+    assert adc.adc_mlp_init(ctx.h, 7) == adc.ADC_OK
+    st, loss = adc.adc_mlp_train(ctx.h, X.shape[0], X, y, 150, 64, 1e-3)
+    assert st == adc.ADC_OK
+    _TRAINED["theta"] = get_params(ctx)
+    _TRAINED["loss"] = loss
+    _TRAINED["var"] = float(torch.var(y))
+    return loss
+
+
+def test_training_fits_observed_ranks(ctx):
+    loss = trained_model(ctx)
+    print(f"final loss {loss:.4f} target variance {_TRAINED['var']:.4f}", flush=True)
+    assert loss < 0.25 * _TRAINED["var"]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "geometric", "clusters"])
+def test_gain_over_the_bound(ctx, kind):
+    """Prescribed spectra (not in the training families), N = 4096, HSS at the
+    merges with K >= 2048: the MLP's sample count is below the bound's and
+    the result is as accurate."""
+    trained_model(ctx)
+    a, b = workloads.prescribed_tridiagonal(kind, 4096)
+    lam, _ = workloads.spectrum(kind, 4096)
+    res = {}
+    for mode in (adc.ADC_RANK_BOUND, adc.ADC_RANK_MLP):
+        w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), dc_leaf=32, hss_leaf=128, hss_min_k=2048,
+                                         hss_levels=-1, rank_mode=mode)
+        torch.cuda.synchronize()
+        w, Z = w.cpu().numpy(), Z.cpu().numpy()
+        tn = odc.tnorm1(a, b)
+        assert np.max(np.abs(w - np.sort(lam))) <= 1e-12 * tn
+        assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
+        assert rep["hss_merges"] >= 1 and rep["hss_fallbacks"] == 0
+        res[mode] = rep
+        print(f"{kind} mode {mode}: samples {rep['samples']} max rank {rep['max_rank']} "
+              f"retries {rep['retries']} hss merges {rep['hss_merges']}", flush=True)
+    assert res[adc.ADC_RANK_MLP]["samples"] < res[adc.ADC_RANK_BOUND]["samples"]

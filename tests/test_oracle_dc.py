@@ -143,3 +143,15 @@ def test_negative_and_zero_offdiagonals():
     ref = eigh_tridiagonal(a, b, eigvals_only=True, lapack_driver="stebz")
     assert np.max(np.abs(w - ref)) <= 1e-13 * dc.tnorm1(a, b)
     assert dc.residual(a, b, w, Z) <= 1e-14 and dc.orthogonality(Z) <= 1e-13
+
+
+@pytest.mark.parametrize("kind", ["uniform", "geometric", "clusters"])
+def test_prescribed_spectrum_generator(kind):
+    """The generated Jacobi matrix has the prescribed eigenvalues (LAPACK)
+    and a positive off-diagonal."""
+    from scipy.linalg import eigh_tridiagonal
+    a, b = workloads.prescribed_tridiagonal(kind, 512)
+    lam, _ = workloads.spectrum(kind, 512)
+    ev = eigh_tridiagonal(a, b, eigvals_only=True)
+    assert np.max(np.abs(ev - np.sort(lam))) <= 1e-13
+    assert np.all(b > 0)
