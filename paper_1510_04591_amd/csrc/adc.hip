@@ -93,6 +93,7 @@ void adc_ctx_s::release() {
   timer.destroy();
   ktimer.destroy();
   mlp_release(this);
+  batch_release(this);
 }
 
 adc_status adc_ctx_s::buffer(int slot, size_t bytes, void** p) {

@@ -172,6 +172,7 @@ struct Arena {
 adc_status check_finite(adc_ctx c, const double* x, int64_t n, bool* ok);
 int pick_waves(int64_t K);
 void mlp_release(adc_ctx c);
+void batch_release(adc_ctx c);
 
 __global__ void k_check_finite(const double* __restrict__ x, int64_t n, int* __restrict__ flag);
 __global__ void k_set_int(int* p, int v);

@@ -159,8 +159,8 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   P.lda = M.n;
   P.B = B.qc + M.zoff;
   P.ldb = M.K;
-  P.C = B.Znew + M.s0 + M.s0 * B.ldn;
-  P.ldc = B.ldn;
+  P.C = M.zn;
+  P.ldc = M.ldn;
   P.colmap = B.posR + M.s0;
   P.vscale = B.v + M.s0;
   P.tiles_m = (P.M + 127) / 128;
@@ -235,7 +235,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
   size_t max_merges = 1;
   for (auto& lv : plan.merge_levels) max_merges = std::max(max_merges, lv.size());
   const size_t blocks64 = (size_t)(n / 64 + 2 * max_merges + 8);
-  const size_t desc_bytes = 4096 + nleaf * 16 + plan.splits.size() * 8 + max_merges * sizeof(MergeDev) +
+  const size_t desc_bytes = 4096 + nleaf * 32 + plan.splits.size() * 8 + max_merges * sizeof(MergeDev) +
                             3 * blocks64 * sizeof(RootBlock) + 2 * max_merges * sizeof(GemmProb) +
                             (size_t)n * 8 + 2 * ((size_t)n / 8 + max_merges + 8) * 4 + 32 * 256;
   char* hs;
@@ -252,6 +252,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     int64_t* d_ls = da.take<int64_t>(nleaf);
     int32_t* h_lm = ha.take<int32_t>(nleaf);
     int32_t* d_lm = da.take<int32_t>(nleaf);
+    LeafOut* h_lo = ha.take<LeafOut>(nleaf);
+    LeafOut* d_lo = da.take<LeafOut>(nleaf);
     if (!plan.splits.empty()) std::memcpy(h_sp, plan.splits.data(), plan.splits.size() * 8);
     // leaves grouped by the buffer they go to (depth parity)
     std::vector<int64_t> ls[2];
@@ -266,17 +268,16 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     std::memcpy(h_ls + n0, ls[1].data(), ls[1].size() * 8);
     std::memcpy(h_lm, lm[0].data(), n0 * 4);
     std::memcpy(h_lm + n0, lm[1].data(), lm[1].size() * 4);
+    for (size_t i = 0; i < n0; ++i) h_lo[i] = LeafOut{Z + ls[0][i] + ls[0][i] * ldz, ldz};
+    for (size_t i = 0; i < ls[1].size(); ++i) h_lo[n0 + i] = LeafOut{L.Zb + ls[1][i] + ls[1][i] * n, n};
     HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
     c->ktimer.begin(rep != nullptr);
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_tear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag, offdiag, d_sp,
                        (int)plan.splits.size(), L.a, n);
-    if (n0)
-      hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)n0), dim3(256), 0, st, L.a, offdiag, d_ls, d_lm, w, Z, ldz,
-                         40);
-    if (ls[1].size())
-      hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)ls[1].size()), dim3(256), 0, st, L.a, offdiag, d_ls + n0,
-                         d_lm + n0, w, L.Zb, (int64_t)n, 40);
+    if (nleaf)
+      hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)nleaf), dim3(256), 0, st, L.a, offdiag, d_ls, d_lm, w,
+                         (const LeafOut*)d_lo, 40);
     HIP_OK(hipGetLastError());
     c->timer.mark(st, 0);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, L.noconv, INT32_MAX);
@@ -297,10 +298,10 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     B.w_out = w;
     B.off = offdiag;
     const bool out_user = (t % 2) == 0;
-    B.Znew = out_user ? Z : L.Zb;
-    B.ldn = out_user ? ldz : n;
-    B.Zold = out_user ? L.Zb : Z;
-    B.ldo = out_user ? n : ldz;
+    double* Znew = out_user ? Z : L.Zb;
+    const int64_t ldn = out_user ? ldz : n;
+    const double* Zold = out_user ? L.Zb : Z;
+    const int64_t ldo = out_user ? n : ldz;
     B.dsort = L.dsort;
     B.zsort = L.zsort;
     B.src = L.src;
@@ -340,6 +341,10 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       M.gbase = lev[g2].s0;
       M.n = lev[g2].n;
       M.n1 = lev[g2].n / 2;
+      M.zo = Zold + M.s0 + M.s0 * ldo;
+      M.zn = Znew + M.s0 + M.s0 * ldn;
+      M.ldo = ldo;
+      M.ldn = ldn;
       nmax = std::max(nmax, M.n);
     }
     HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -417,8 +422,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
         P.lda = M.n;
         P.B = L.qc + M.zoff + (half ? M.k1 : 0);
         P.ldb = M.K;
-        P.C = B.Znew + (M.s0 + (half ? M.n1 : 0)) + M.s0 * B.ldn;
-        P.ldc = B.ldn;
+        P.C = M.zn + (half ? M.n1 : 0);
+        P.ldc = M.ldn;
         P.colmap = L.posR + M.s0;
         P.vscale = L.v + M.s0;
         P.tiles_m = (P.M + 127) / 128;

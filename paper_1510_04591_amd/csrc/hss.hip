@@ -721,7 +721,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
       ADC_TRY(mlp_collect_merge(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, lo, hi, kr, kc));
     }
     if (m.pass) {
-      aj.push_back(ApplyJob{(int)t, B.pk + M.zoff, (int64_t)M.n, M.n, B.Znew + M.s0 + M.s0 * B.ldn, B.ldn,
+      aj.push_back(ApplyJob{(int)t, B.pk + M.zoff, (int64_t)M.n, M.n, M.zn, M.ldn,
                             B.posR + M.s0});
     } else {
       dense_fb.push_back(which[t]);

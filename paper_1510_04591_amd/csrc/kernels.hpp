@@ -18,6 +18,17 @@ struct MergeDev {
   int32_t mode;    // 0 dense update, 1 HSS update (host decision)
   double rho;      // rho after normalising z
   double tol;      // deflation tolerance
+  // eigenvector blocks: zo = the children's (block diagonal), zn = the merged
+  // block; both point at the merge's (first row, first column) corner
+  const double* zo;
+  double* zn;
+  int64_t ldo, ldn;
+};
+
+// Output block of one leaf: z points at its (first row, first column) corner.
+struct LeafOut {
+  double* z;
+  int64_t ld;
 };
 
 // 64 consecutive roots (columns) of one merge.
@@ -50,9 +61,6 @@ struct LevelBufs {
   const double* w_in;   // children's eigenvalues (copy of w)
   double* w_out;        // merged eigenvalues
   const double* off;    // off-diagonal of T (b_k of every tear)
-  double* Zold;         // eigenvectors of the children (block diagonal)
-  double* Znew;         // merged eigenvectors
-  int64_t ldo, ldn;     // leading dimensions of Zold and Znew
   double* dsort;        // d after merging the two runs (and rotation updates)
   double* zsort;        // z likewise
   int32_t* src;         // sorted position -> block-local source column
@@ -85,7 +93,7 @@ struct LevelBufs {
 // ---- kernels
 __global__ void k_leaf_jacobi(const double* __restrict__ a, const double* __restrict__ b,
                               const int64_t* __restrict__ leaf_s0, const int32_t* __restrict__ leaf_m,
-                              double* __restrict__ w, double* __restrict__ Z, int64_t ldz, int max_sweeps);
+                              double* __restrict__ w, const LeafOut* __restrict__ outs, int max_sweeps);
 
 __global__ void k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B);
 
@@ -107,10 +115,6 @@ __global__ void k_vnorm(const MergeDev* __restrict__ merges, const RootBlock* __
 __global__ void k_final_order(const MergeDev* __restrict__ merges, LevelBufs B,
                               const RootBlock* __restrict__ blocks);
 
-__global__ void k_rotate(const MergeDev* __restrict__ merges, LevelBufs B, const RootBlock* __restrict__ blocks);
-
-__global__ void k_pack(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
-                       const int32_t* __restrict__ col_idx, LevelBufs B, int sorted_pack);
 __global__ void k_pack_rot(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
                            const int32_t* __restrict__ col_idx, LevelBufs B);
 

@@ -5,7 +5,7 @@
 // round-robin pairing) on the dense leaf matrix held in LDS: all m/2 disjoint
 // rotations of a round are computed together, then applied to the columns of
 // A and V and to the rows of A.  Eigenvalues are sorted ascending and the
-// eigenvectors written into the diagonal block of the global Z.
+// eigenvectors written into the leaf's output block.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -14,7 +14,7 @@
 __global__ void __launch_bounds__(256) k_leaf_jacobi(const double* __restrict__ a, const double* __restrict__ b,
                                                      const int64_t* __restrict__ leaf_s0,
                                                      const int32_t* __restrict__ leaf_m, double* __restrict__ w,
-                                                     double* __restrict__ Z, int64_t ldz, int max_sweeps) {
+                                                     const LeafOut* __restrict__ outs, int max_sweeps) {
   __shared__ double A[LEAF_MAX][LEAF_MAX + 1];
   __shared__ double V[LEAF_MAX][LEAF_MAX + 1];
   __shared__ double s_c[LEAF_MAX / 2], s_s[LEAF_MAX / 2];
@@ -137,9 +137,11 @@ __global__ void __launch_bounds__(256) k_leaf_jacobi(const double* __restrict__ 
     s_red[i] = (double)rk;
   }
   __syncthreads();
+  double* __restrict__ Z = outs[blockIdx.x].z;
+  const int64_t ldz = outs[blockIdx.x].ld;
   for (int e = tid; e < m * m; e += blockDim.x) {
     const int r = e % m, i = e / m;
     const int rk = (int)s_red[i];
-    Z[(s0 + r) + (s0 + rk) * ldz] = V[r][i];
+    Z[r + rk * ldz] = V[r][i];
   }
 }

@@ -95,12 +95,13 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
   const double* __restrict__ win = B.w_in + s0;
   const double* __restrict__ d1 = win;
   const double* __restrict__ d2 = win + n1;
-  const int64_t ldz = B.ldo;
+  const int64_t ldz = M.ldo;
+  const double* __restrict__ zo = M.zo;
 
   // ||u||^2 with u = [last row of Q1; +-first row of Q2]
   double ss = 0.0;
   for (int j = tid; j < n; j += blockDim.x) {
-    const double u = (j < n1) ? B.Zold[(s0 + n1 - 1) + (s0 + j) * ldz] : sg * B.Zold[(s0 + n1) + (s0 + j) * ldz];
+    const double u = (j < n1) ? zo[(n1 - 1) + j * ldz] : sg * zo[n1 + j * ldz];
     ss += u * u;
   }
   const double nu2 = block_reduce(ss, sh, OpAdd());
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
 
   double md = 0.0, mz = 0.0;
   for (int j = tid; j < n; j += blockDim.x) {
-    const double u = (j < n1) ? B.Zold[(s0 + n1 - 1) + (s0 + j) * ldz] : sg * B.Zold[(s0 + n1) + (s0 + j) * ldz];
+    const double u = (j < n1) ? zo[(n1 - 1) + j * ldz] : sg * zo[n1 + j * ldz];
     const double dj = win[j];
     int pos;
     if (j < n1) pos = j + lower_bound_d(d2, n2, dj);
@@ -498,9 +499,9 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
       return B.pk + M.zoff + (int64_t)pk * n;
     }
     const int q = -1 - role;
-    return B.Znew + s0 + (s0 + B.posD[s0 + q]) * B.ldn;
+    return M.zn + B.posD[s0 + q] * M.ldn;
   };
-  auto src_of = [&](int pos) -> const double* { return B.Zold + s0 + (s0 + B.src[s0 + pos]) * B.ldo; };
+  auto src_of = [&](int pos) -> const double* { return M.zo + B.src[s0 + pos] * M.ldo; };
   auto supp_of = [&](int pos) { return (B.src[s0 + pos] < n1) ? 1 : 2; };
   const int t0 = B.rot_i_of[s0 + p];
   if (t0 < 0) {
@@ -578,63 +579,6 @@ __global__ void __launch_bounds__(256) k_final_order(const MergeDev* __restrict_
     B.posD[s0 + q] = pos;
   }
   B.w_out[s0 + pos] = x;
-}
-
-// ---------------------------------------------------------------------------
-// blocks: RootBlock(merge, row0), one thread per row of the merge block.
-__global__ void __launch_bounds__(256) k_rotate(const MergeDev* __restrict__ merges, LevelBufs B,
-                                                const RootBlock* __restrict__ blocks) {
-  const RootBlock rb = blocks[blockIdx.x];
-  const MergeDev& M = merges[rb.merge];
-  const int nrot = M.nrot;
-  if (nrot == 0 || rb.i0 >= M.n) return;
-  const int r = rb.i0 + threadIdx.x;
-  const bool valid = r < M.n;
-  const int64_t s0 = M.s0;
-  const int bit = (r < M.n1) ? 1 : 2;
-  double* __restrict__ row = B.Zold + (s0 + r);
-  const int64_t ldz = B.ldo;
-  for (int t = 0; t < nrot; ++t) {
-    const int i = B.rot_i[s0 + t], j = B.rot_j[s0 + t];
-    const int f = B.rot_f[s0 + t];
-    const int fi = f & 3, fj = f >> 2;
-    if (!valid || !((fi | fj) & bit)) continue;
-    const double c = B.rot_c[s0 + t], s = B.rot_s[s0 + t];
-    const int64_t ci = (s0 + B.src[s0 + i]) * ldz;
-    const int64_t cj = (s0 + B.src[s0 + j]) * ldz;
-    const double xi = (fi & bit) ? row[ci] : 0.0;
-    const double xj = (fj & bit) ? row[cj] : 0.0;
-    row[ci] = c * xi + s * xj;
-    row[cj] = -s * xi + c * xj;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// one block per column job: job -> (merge col_merge[job], local column col_idx[job]).
-__global__ void __launch_bounds__(256) k_pack(const MergeDev* __restrict__ merges,
-                                              const int32_t* __restrict__ col_merge,
-                                              const int32_t* __restrict__ col_idx, LevelBufs B, int sorted_pack) {
-  const MergeDev& M = merges[col_merge[blockIdx.x]];
-  const int64_t s0 = M.s0;
-  const int n = M.n, n1 = M.n1, K = M.K;
-  const int c = col_idx[blockIdx.x];
-  int sp;
-  double* __restrict__ dst;
-  if (c < K) {
-    const int r = (sorted_pack || M.mode == 1) ? c : B.gorder[s0 + c];
-    sp = B.surv[s0 + r];
-    dst = B.pk + M.zoff + (int64_t)c * n;
-  } else {
-    const int q = c - K;
-    sp = B.defl[s0 + q];
-    dst = B.Znew + s0 + (s0 + B.posD[s0 + q]) * B.ldn;
-  }
-  const int f = B.supp[s0 + sp];
-  const double* __restrict__ srcc = B.Zold + s0 + (s0 + B.src[s0 + sp]) * B.ldo;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    const int bit = (r < n1) ? 1 : 2;
-    dst[r] = (f & bit) ? srcc[r] : 0.0;
-  }
 }
 
 // ---------------------------------------------------------------------------
