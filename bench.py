@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-validate", action="store_true")
     p.add_argument("--mode", choices=["both", "hss", "dense"], default="both")
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--batched-only", action="store_true")
     return p.parse_args()
 
 
@@ -87,6 +89,61 @@ def cpu_baseline():
             "sample": f"oracle dense DC of Toeplitz N={n} took {dt:.2f} s; x{scale:.0f} (N^3) to N=32768"}
 
 
+def run_batched(torch, adc, ctx, steps, warmup, sequential=True):
+    """256 matrices, N ~ U{200..4000}, half Toeplitz half random (seed 4),
+    dense update, through adc_stedc_batched: the first call tunes and
+    captures the HIP graph (warm-up), the timed calls replay it.  Also the
+    same batch through adc_stedc one matrix at a time, for context."""
+    from paper_1510_04591_amd import workloads
+    mats = workloads.batched(256, 4)
+    ns = [len(a) for a, _ in mats]
+    ds = [torch.from_numpy(a).cuda() for a, _ in mats]
+    os_ = [torch.from_numpy(b).cuda() for _, b in mats]
+    ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in ns]
+    Zs = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n in ns]
+    o = adc.opts(dc_leaf=32, force_dense=1)
+
+    def call():
+        st = adc.adc_stedc_batched(ctx.h, ns, ds, os_, ws, Zs, ns, o, None)
+        if st != adc.ADC_OK:
+            raise adc.AdcError(st, "adc_stedc_batched")
+
+    for _ in range(max(1, warmup)):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "256 tridiagonal matrices, N ~ U{200..4000} (sum %d), half Toeplitz(2,1), half "
+                       "random U(-1,1)/U(0,1), seed 4, DC leaf 32, dense update" % sum(ns),
+           "value": 256.0 / dt, "unit": "matrices/s", "s_per_batch": dt, "steps": steps}
+    # correctness of the timed result: residual of every matrix on the device
+    worst = 0.0
+    for (a, b), w, Zt, n in zip(mats, ws, Zs, ns):
+        ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        Z = Zt.t()
+        TZ = ad[:, None] * Z
+        TZ[:-1] += bd[:, None] * Z[1:]
+        TZ[1:] += bd[:, None] * Z[:-1]
+        tn = float(np.max(np.abs(a) + np.concatenate([[0], np.abs(b)]) + np.concatenate([np.abs(b), [0]])))
+        worst = max(worst, float(torch.linalg.norm(TZ - Z * w[None, :])) / (n * tn))
+    out["max_resid"] = worst
+    if sequential:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d_, o_, w_, Z_, n in zip(ds, os_, ws, Zs, ns):
+            st = adc.adc_stedc(ctx.h, n, d_, o_, w_, Z_, n, None, 0, o, None)
+            if st != adc.ADC_OK:
+                raise adc.AdcError(st, "adc_stedc")
+        torch.cuda.synchronize()
+        out["sequential_matrices_per_s"] = 256.0 / (time.perf_counter() - t0)
+    del Zs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -95,6 +152,11 @@ def main():
         sys.exit(2)
     import torch
     from paper_1510_04591_amd import adc, workloads
+    if args.batched_only:
+        ctx = adc.Context(0)
+        print(json.dumps({"batched": run_batched(torch, adc, ctx, args.steps, args.warmup)}), flush=True)
+        ctx.close()
+        return
 
     N = args.n
     a, b = workloads.toeplitz(N)
@@ -200,6 +262,9 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_batched:
+        res["batched"] = run_batched(torch, adc, ctx, max(args.steps, 3), 1)
+        print(f"# batched: {res['batched']['value']:.1f} matrices/s", flush=True)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
     ctx.close()
