@@ -111,8 +111,9 @@ typedef struct adc_report {
   double  bytes_model;       /* algorithmic HBM bytes of the updates           */
   double  check_err_max;     /* largest HSS check error accepted               */
   /* Per-kernel figures, each launch bracketed by HIP events on the context
-   * stream: 0 k_gemm_f64 (128-wide FP64 MFMA GEMM), 1 k_gemm_f64_n64
-   * (64-wide), 2 k_hss_sample, 3 k_pack_rot, 4 k_secular, 5 k_hss_compress.
+   * stream: 0 k_gemm_f64 (128 x 128 FP64 MFMA GEMM tiles), 1 k_gemm_f64_n64
+   * (128 x 64), 2 k_hss_sample, 3 k_pack_rot, 4 k_secular, 5 k_hss_compress,
+   * 6 k_gemm_f64_big (256 x 128, the dense update).
    * Times in seconds; flops and bytes are the algorithmic counts of the
    * launches (operands read once, results written once). */
   double  kern_time[8];

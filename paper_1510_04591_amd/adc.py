@@ -51,7 +51,8 @@ class adc_report(C.Structure):
         ("kern_launches", C.c_int32 * 8),
     ]
 
-    KERNELS = ("k_gemm_f64", "k_gemm_f64_n64", "k_hss_sample", "k_pack_rot", "k_secular", "k_hss_compress")
+    KERNELS = ("k_gemm_f64", "k_gemm_f64_n64", "k_hss_sample", "k_pack_rot", "k_secular", "k_hss_compress",
+               "k_gemm_f64_big")
 
     def as_dict(self):
         L = self.levels

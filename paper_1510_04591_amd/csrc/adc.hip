@@ -256,7 +256,7 @@ extern "C" adc_status adc_cauchy_gemm(adc_ctx c, int64_t P, int64_t K, const dou
   gp.N = (int32_t)K;
   gp.K = (int32_t)K;
   gp.tile0 = 0;
-  gp.tiles_m = (int32_t)((P + 127) / 128);
+  gp.tiles_m = (int32_t)((P + 255) / 256);
   const int tiles = gp.tiles_m * (int)((K + 127) / 128);
   void* dev;
   const size_t need = sizeof(MergeDev) + sizeof(GemmProb) + 2 * tm.size() * sizeof(int32_t) + 256;
@@ -273,7 +273,7 @@ extern "C" adc_status adc_cauchy_gemm(adc_ctx c, int64_t P, int64_t K, const dou
   HIP_OK(hipMemcpyAsync(dtm, tm.data(), tm.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_OK(hipMemcpyAsync(dtc, tc.data(), tc.size() * 4, hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(k_cauchy, dim3((unsigned)tm.size()), dim3(256), 0, c->stream, dm, dtm, dtc, B, ncols, 0);
-  hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, c->stream, dg, 1);
+  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, dg, 1);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(c->stream));
   return ADC_OK;

@@ -69,7 +69,15 @@ struct PhaseTimer {
 
 // Per-launch timing of selected kernels: an event pair around each launch,
 // resolved after the stream has been synchronised.
-enum KernId { KT_GEMM = 0, KT_GEMM64 = 1, KT_SAMPLE = 2, KT_PACK = 3, KT_SECULAR = 4, KT_COMPRESS = 5 };
+enum KernId {
+  KT_GEMM = 0,
+  KT_GEMM64 = 1,
+  KT_SAMPLE = 2,
+  KT_PACK = 3,
+  KT_SECULAR = 4,
+  KT_COMPRESS = 5,
+  KT_GEMMBIG = 6
+};
 struct KernTimer {
   std::vector<hipEvent_t> ev;
   std::vector<int> kid;

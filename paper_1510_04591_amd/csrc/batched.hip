@@ -10,7 +10,7 @@
 // dense update are filled in on the device.  The whole sequence (input
 // gather, tears, leaves, all levels, output scatter) is therefore fixed by
 // the sizes alone: the first call for a size set runs it eagerly, tuning the
-// GEMM tile width and the secular kernel's wave count per level with HIP
+// GEMM tile shape and the secular kernel's wave count per level with HIP
 // events, and captures it in a HIP graph that later calls with the same sizes
 // replay.  Caller pointers live in device descriptor arrays refreshed before
 // each replay, so they may change between calls.
@@ -60,14 +60,14 @@ __global__ void k_scatter_w(int count, const double* __restrict__ wg, double* co
 // child against both and bottom-only), from the deflation results.  tile0
 // and tiles_m were set by the host for the worst case N = n.
 __global__ void k_build_probs(const MergeDev* __restrict__ ms, int nm, GemmProb* __restrict__ pa,
-                              GemmProb* __restrict__ pb, const double* __restrict__ pk,
+                              GemmProb* __restrict__ pb, GemmProb* __restrict__ pc, const double* __restrict__ pk,
                               const double* __restrict__ qc, const double* __restrict__ v,
                               const int32_t* __restrict__ posR) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nm) return;
   const MergeDev& M = ms[g];
-  for (int which = 0; which < 2; ++which) {
-    GemmProb* arr = which ? pb : pa;
+  for (int which = 0; which < 3; ++which) {
+    GemmProb* arr = (which == 0) ? pa : (which == 1) ? pb : pc;
     for (int half = 0; half < 2; ++half) {
       GemmProb& P = arr[2 * g + half];
       P.N = M.K;
@@ -95,10 +95,10 @@ struct Node {
 
 struct BLevel {
   int nm = 0, nmax = 0;
-  size_t o_m = 0, o_rb = 0, o_ob = 0, o_cm = 0, o_cc = 0, o_tm = 0, o_tc = 0, o_ga = 0, o_gb = 0;
-  int nrb = 0, nob = 0, njob = 0, ntile = 0, tiles128 = 0, tiles64 = 0;
+  size_t o_m = 0, o_rb = 0, o_ob = 0, o_cm = 0, o_cc = 0, o_tm = 0, o_tc = 0, o_ga = 0, o_gb = 0, o_gc = 0;
+  int nrb = 0, nob = 0, njob = 0, ntile = 0, tiles[3] = {0, 0, 0};
   int W = 1;      // waves per secular / Loewner block
-  int bn = 128;   // GEMM tile width
+  int gv = 0;     // GEMM tile shape: 0 128x128, 1 128x64, 2 256x128
   bool tuned = false;
 };
 
@@ -133,7 +133,7 @@ struct BEntry {
 
 struct BCache {
   std::map<std::tuple<std::vector<int64_t>, int, int>, BEntry*> entries;
-  // level signature (merges, largest n, sum of n) -> (waves, tile width)
+  // level signature (merges, largest n, sum of n) -> (waves, GEMM tile shape)
   std::map<std::tuple<int, int, int64_t>, std::pair<int, int>> tune;
   hipStream_t cap = nullptr;
 };
@@ -247,8 +247,9 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
       L.ntile += (nd.n + 7) / 8;
       const int n1 = nd.n / 2, n2 = nd.n - n1;
       const int tn128 = (nd.n + 127) / 128, tn64 = (nd.n + 63) / 64;
-      L.tiles128 += ((n1 + 127) / 128 + (n2 + 127) / 128) * tn128;
-      L.tiles64 += ((n1 + 127) / 128 + (n2 + 127) / 128) * tn64;
+      L.tiles[0] += ((n1 + 127) / 128 + (n2 + 127) / 128) * tn128;
+      L.tiles[1] += ((n1 + 127) / 128 + (n2 + 127) / 128) * tn64;
+      L.tiles[2] += ((n1 + 255) / 256 + (n2 + 255) / 256) * tn128;
       nsum += nd.n;
     }
     (void)nsum;
@@ -262,6 +263,7 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
     L.o_tc = dtake((size_t)L.ntile * 4);
     L.o_ga = dtake(2 * (size_t)L.nm * sizeof(GemmProb));
     L.o_gb = dtake(2 * (size_t)L.nm * sizeof(GemmProb));
+    L.o_gc = dtake(2 * (size_t)L.nm * sizeof(GemmProb));
   }
   const size_t o_desc = take(doff);
   e->dev_bytes = off;
@@ -306,7 +308,8 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
     int32_t* tc = (int32_t*)(h + L.o_tc);
     GemmProb* ga = (GemmProb*)(h + L.o_ga);
     GemmProb* gb = (GemmProb*)(h + L.o_gb);
-    int irb = 0, iob = 0, ij = 0, it = 0, t128 = 0, t64 = 0;
+    GemmProb* gc = (GemmProb*)(h + L.o_gc);
+    int irb = 0, iob = 0, ij = 0, it = 0, t128 = 0, t64 = 0, tbig = 0;
     int64_t zoff = 0;
     for (int g = 0; g < L.nm; ++g) {
       const Node& nd = nodes[g];
@@ -335,12 +338,16 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
       for (int half = 0; half < 2; ++half) {
         GemmProb& A = ga[2 * g + half];
         GemmProb& B = gb[2 * g + half];
-        A.M = B.M = rows[half];
+        GemmProb& C = gc[2 * g + half];
+        A.M = B.M = C.M = rows[half];
         A.tiles_m = B.tiles_m = (rows[half] + 127) / 128;
+        C.tiles_m = (rows[half] + 255) / 256;
         A.tile0 = t128;
         B.tile0 = t64;
+        C.tile0 = tbig;
         t128 += A.tiles_m * ((nd.n + 127) / 128);
         t64 += B.tiles_m * ((nd.n + 63) / 64);
+        tbig += C.tiles_m * ((nd.n + 127) / 128);
       }
     }
   }
@@ -432,12 +439,15 @@ void launch_roots(BEntry* e, const BLevel& L, int W, hipStream_t st) {
                      e->max_iter, e->flags);
 }
 
-void launch_gemm(BEntry* e, const BLevel& L, int bn, hipStream_t st) {
-  if (bn == 128)
-    hipLaunchKernelGGL(k_gemm_f64, dim3(L.tiles128), dim3(256), 0, st, (const GemmProb*)(e->desc + L.o_ga),
+void launch_gemm(BEntry* e, const BLevel& L, int gv, hipStream_t st) {
+  if (gv == 0)
+    hipLaunchKernelGGL(k_gemm_f64, dim3(L.tiles[0]), dim3(512), 0, st, (const GemmProb*)(e->desc + L.o_ga),
+                       2 * L.nm);
+  else if (gv == 1)
+    hipLaunchKernelGGL(k_gemm_f64_n64, dim3(L.tiles[1]), dim3(512), 0, st, (const GemmProb*)(e->desc + L.o_gb),
                        2 * L.nm);
   else
-    hipLaunchKernelGGL(k_gemm_f64_n64, dim3(L.tiles64), dim3(256), 0, st, (const GemmProb*)(e->desc + L.o_gb),
+    hipLaunchKernelGGL(k_gemm_f64_big, dim3(L.tiles[2]), dim3(1024), 0, st, (const GemmProb*)(e->desc + L.o_gc),
                        2 * L.nm);
 }
 
@@ -479,7 +489,7 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
       auto it = bc->tune.find(key);
       if (it != bc->tune.end()) {
         L.W = it->second.first;
-        L.bn = it->second.second;
+        L.gv = it->second.second;
         L.tuned = true;
       }
     }
@@ -521,15 +531,22 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
     hipLaunchKernelGGL(k_cauchy, dim3(L.ntile), dim3(256), 0, st, dm, (const int32_t*)(d + L.o_tm),
                        (const int32_t*)(d + L.o_tc), B, 8, 1);
     hipLaunchKernelGGL(k_build_probs, dim3((L.nm + 63) / 64), dim3(64), 0, st, dm, L.nm,
-                       (GemmProb*)(d + L.o_ga), (GemmProb*)(d + L.o_gb), e->pk, e->qc, e->v, e->posR);
+                       (GemmProb*)(d + L.o_ga), (GemmProb*)(d + L.o_gb), (GemmProb*)(d + L.o_gc), e->pk, e->qc,
+                       e->v, e->posR);
     if (tune_here) {
-      const float t128 = timed([&] { launch_gemm(e, L, 128, st); });
-      const float t64 = timed([&] { launch_gemm(e, L, 64, st); });
-      L.bn = (t64 < t128) ? 64 : 128;  // both write the same values
+      // every tile shape writes the same values (same summation order)
+      float best = 1e30f;
+      for (int gv = 0; gv < 3; ++gv) {
+        const float ms = timed([&] { launch_gemm(e, L, gv, st); });
+        if (ms < best) {
+          best = ms;
+          L.gv = gv;
+        }
+      }
       L.tuned = true;
-      bc->tune[key] = std::make_pair(L.W, L.bn);
+      bc->tune[key] = std::make_pair(L.W, L.gv);
     } else {
-      launch_gemm(e, L, L.bn, st);
+      launch_gemm(e, L, L.gv, st);
     }
     if (hipGetLastError() != hipSuccess) status = ADC_ERR_HIP;
   }

@@ -163,7 +163,7 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   P.ldc = M.ldn;
   P.colmap = B.posR + M.s0;
   P.vscale = B.v + M.s0;
-  P.tiles_m = (P.M + 127) / 128;
+  P.tiles_m = (P.M + 255) / 256;
   P.tile0 = 0;
   const int tiles = P.tiles_m * ((P.N + 127) / 128);
   const size_t nt = tm.size();
@@ -176,7 +176,7 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   HIP_OK(hipMemcpyAsync(dtm, tm.data(), nt * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(dtc, tc.data(), nt * 4, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_cauchy, dim3((unsigned)nt), dim3(256), 0, st, d_m, dtm, dtc, B, ncols, 0);
-  hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, st, dg, 1);
+  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, st, dg, 1);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(st));
   if (flops) *flops += 2.0 * P.M * (double)P.N * P.K;
@@ -426,7 +426,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
         P.ldc = M.ldn;
         P.colmap = L.posR + M.s0;
         P.vscale = L.v + M.s0;
-        P.tiles_m = (P.M + 127) / 128;
+        P.tiles_m = (P.M + 255) / 256;
         P.tile0 = gtiles;
         gtiles += P.tiles_m * ((P.N + 127) / 128);
         ++ngp;
@@ -470,8 +470,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     c->timer.mark(st, 9);
     if (gtiles) {
       c->ktimer.pre(st);
-      hipLaunchKernelGGL(k_gemm_f64, dim3(gtiles), dim3(256), 0, st, d_gp, ngp);
-      c->ktimer.post(st, KT_GEMM, lvl_gf, lvl_gb);
+      hipLaunchKernelGGL(k_gemm_f64_big, dim3(gtiles), dim3(1024), 0, st, d_gp, ngp);
+      c->ktimer.post(st, KT_GEMMBIG, lvl_gf, lvl_gb);
     }
     c->timer.mark(st, 4);
     HIP_OK(hipGetLastError());

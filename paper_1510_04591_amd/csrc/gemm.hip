@@ -5,42 +5,50 @@
 // For each problem: C(:, colmap[j]) = beta C(:, colmap[j]) + vscale[j] *
 // ([A A2] [B; B2])(:, j), all column-major, the inner dimension split into a
 // first segment of K columns of A (rows of B) and an optional second segment
-// of K2; either B segment may be stored transposed.  Workgroup tile 128 x BN,
-// K step 16, four waves in a 2 x 2 grid, each wave owning 64 x BN/2 outputs as
-// tiles of v_mfma_f64_16x16x4f64.  Operand tiles are staged through LDS
+// of K2; either B segment may be stored transposed.  Workgroup tile BM x BN,
+// K step 16, WM x WN waves each owning a (BM/WM) x (BN/WN) block as tiles of
+// v_mfma_f64_16x16x4f64.  Operand tiles are staged through LDS
 // (double-buffered; the next tile is fetched into registers while the current
-// one feeds the matrix cores).  Lane layout of the 16x16x4 f64 instruction:
-// A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, D[lane/16 + 4r][lane
-// % 16] in accumulator r.
+// one feeds the matrix cores).  Eight or sixteen waves per workgroup keep
+// enough loads in flight to cover the memory latency (measured: 8 waves
+// reach about 1.5x the throughput of 4 on the same tile).  Lane layout of
+// the 16x16x4 f64 instruction: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k, D[lane/16 + 4r][lane % 16] in accumulator r.
+//
+//   k_gemm_f64       128 x 128, 4 x 2 waves (512 lanes)
+//   k_gemm_f64_n64   128 x 64,  4 x 2 waves (512 lanes), narrow products
+//   k_gemm_f64_big   256 x 128, 4 x 4 waves (1024 lanes), large updates
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace {
-constexpr int BM = 128, BK = 16;
+constexpr int BK = 16;
 constexpr int PAD = 4;
 
-template <int BN>
+template <int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
-  constexpr int WN = BN / 2;        // columns per wave
-  constexpr int TN = WN / 16;       // 16-wide tiles per wave along N
-  constexpr int BLOADS = BK * BN / 256;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN;  // rows / columns per wave
+  constexpr int TM = WTM / 16, TN = WTN / 16;  // 16 x 16 tiles per wave
+  constexpr int ALOADS = BM * BK / NT, BLOADS = BK * BN / NT;
+  static_assert(ALOADS * NT == BM * BK && BLOADS * NT == BK * BN, "tile / lane mismatch");
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int wm = wv & 1, wn = wv >> 1;
+  const int wm = wv % WM, wn = wv / WM;
   const int li = lane & 15, lk = lane >> 4;
   const int M = P.M, N = P.N;
   const int Kt = P.K + P.K2;
 
-  dbl4 acc[4][TN];
+  dbl4 acc[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  double ra[8], rb[BLOADS];
+  double ra[ALOADS], rb[BLOADS];
   // A K step lies entirely in one segment: steps of the first segment start
   // at multiples of BK below P.K and stop at P.K; those of the second start
   // at P.K + multiples of BK.
@@ -48,9 +56,9 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
     const bool s1 = k0 < P.K;
     const int lim = s1 ? P.K : Kt;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      const int r = e & (BM - 1), c = e >> 7;
+    for (int q = 0; q < ALOADS; ++q) {
+      const int e = tid + NT * q;
+      const int r = e % BM, c = e / BM;
       const int gr = m0 + r, gk = k0 + c;
       double x = 0.0;
       if (gr < M && gk < lim) x = s1 ? P.A[gr + (int64_t)gk * P.lda] : P.A2[gr + (int64_t)(gk - P.K) * P.lda2];
@@ -59,9 +67,9 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
     const bool tr = s1 ? P.transB : P.transB2;
 #pragma unroll
     for (int q = 0; q < BLOADS; ++q) {
-      const int e = tid + 256 * q;
-      const int kr = tr ? e / BN : (e & (BK - 1));
-      const int cc = tr ? e % BN : (e >> 4);
+      const int e = tid + NT * q;
+      const int kr = tr ? e / BN : (e % BK);
+      const int cc = tr ? e % BN : (e / BK);
       const int gk = k0 + kr, gn = n0 + cc;
       double x = 0.0;
       if (gk < lim && gn < N) {
@@ -76,16 +84,16 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   };
   auto sstore = [&](int buf, int k0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      As[buf][e >> 7][e & (BM - 1)] = ra[q];
+    for (int q = 0; q < ALOADS; ++q) {
+      const int e = tid + NT * q;
+      As[buf][e / BM][e % BM] = ra[q];
     }
     const bool tr = (k0 < P.K) ? P.transB : P.transB2;
 #pragma unroll
     for (int q = 0; q < BLOADS; ++q) {
-      const int e = tid + 256 * q;
+      const int e = tid + NT * q;
       if (tr) Bs[buf][e / BN][e % BN] = rb[q];
-      else Bs[buf][e & (BK - 1)][e >> 4] = rb[q];
+      else Bs[buf][e % BK][e / BK] = rb[q];
     }
   };
 
@@ -104,13 +112,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int k = kk * 4 + lk;
-      double av[4], bv[TN];
+      double av[TM], bv[TN];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) av[t] = As[buf][k][wm * 64 + t * 16 + li];
+      for (int t = 0; t < TM; ++t) av[t] = As[buf][k][wm * WTM + t * 16 + li];
 #pragma unroll
-      for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][k][wn * WN + t * 16 + li];
+      for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][k][wn * WTN + t * 16 + li];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
@@ -120,13 +128,13 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
 
 #pragma unroll
   for (int b = 0; b < TN; ++b) {
-    const int col = n0 + wn * WN + b * 16 + li;
+    const int col = n0 + wn * WTN + b * 16 + li;
     if (col >= N) continue;
     const double vs = P.vscale ? P.vscale[col] : 1.0;
     const int64_t cc = (int64_t)(P.colmap ? P.colmap[col] : col) * P.ldc;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int row0 = m0 + wm * 64 + a * 16 + lk;
+    for (int a = 0; a < TM; ++a) {
+      const int row0 = m0 + wm * WTM + a * 16 + lk;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * r;
@@ -150,20 +158,23 @@ __device__ __forceinline__ int find_prob(const GemmProb* __restrict__ probs, int
 }
 }  // namespace
 
-// Tiles of 128 x 128.
-__global__ void __launch_bounds__(256) k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs) {
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void gemm_dispatch(const GemmProb* __restrict__ probs, int nprobs) {
   const GemmProb P = probs[find_prob(probs, nprobs, blockIdx.x)];
   const int local = blockIdx.x - P.tile0;
-  const int m0 = (local % P.tiles_m) * BM, n0 = (local / P.tiles_m) * 128;
+  const int m0 = (local % P.tiles_m) * BM, n0 = (local / P.tiles_m) * BN;
   if (m0 >= P.M || n0 >= P.N) return;
-  gemm_tile<128>(P, m0, n0);
+  gemm_tile<BM, BN, WM, WN>(P, m0, n0);
 }
 
-// Tiles of 128 x 64 for the narrow products of the HSS generators.
-__global__ void __launch_bounds__(256) k_gemm_f64_n64(const GemmProb* __restrict__ probs, int nprobs) {
-  const GemmProb P = probs[find_prob(probs, nprobs, blockIdx.x)];
-  const int local = blockIdx.x - P.tile0;
-  const int m0 = (local % P.tiles_m) * BM, n0 = (local / P.tiles_m) * 64;
-  if (m0 >= P.M || n0 >= P.N) return;
-  gemm_tile<64>(P, m0, n0);
+__global__ void __launch_bounds__(512) k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs) {
+  gemm_dispatch<128, 128, 4, 2>(probs, nprobs);
+}
+
+__global__ void __launch_bounds__(512) k_gemm_f64_n64(const GemmProb* __restrict__ probs, int nprobs) {
+  gemm_dispatch<128, 64, 4, 2>(probs, nprobs);
+}
+
+__global__ void __launch_bounds__(1024) k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs) {
+  gemm_dispatch<256, 128, 4, 4>(probs, nprobs);
 }

@@ -352,9 +352,9 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
     HIP_OK(hipMemcpyAsync(dp, L.data(), L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
     c->ktimer.pre(st);
     if (pass)
-      hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(256), 0, st, (const GemmProb*)dp, (int)L.size());
+      hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
     else
-      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(256), 0, st, (const GemmProb*)dp, (int)L.size());
+      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
     c->ktimer.post(st, pass ? KT_GEMM : KT_GEMM64, pf[pass], pb[pass]);
     HIP_OK(hipGetLastError());
     // the descriptor arrays are host vectors: wait before they are reused
