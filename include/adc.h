@@ -76,7 +76,7 @@ typedef struct adc_opts {
   int32_t force_dense;   /* [0] 1: plain DC, never HSS                          */
   int32_t strict;        /* [0] 1: a failed HSS check is ADC_ERR_ACCURACY       */
   double  check_tol;     /* [1e-12] relative error allowed by the HSS check     */
-  int32_t nprobe;        /* [4] Gaussian probe vectors of the HSS check         */
+  int32_t nprobe;        /* [4] Gaussian probe vectors of the HSS check, 1..32  */
   int32_t shift_max;     /* [5] max boundary move of the rank estimate          */
   double  shift_thresh;  /* [1e-10] move a boundary when its distance is below  */
   int32_t r_cap;         /* [100] cap of the estimated rank                     */

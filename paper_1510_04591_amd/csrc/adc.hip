@@ -51,7 +51,7 @@ adc_status validate_opts_ext(const adc_opts& o) {
   if (o.dc_leaf < 2 || o.dc_leaf > 64) return ADC_ERR_ARG;
   if (o.hss_leaf < 16 || o.hss_leaf > 256) return ADC_ERR_ARG;
   if (!(o.id_tol >= 0.0) || o.oversample < 0 || o.max_retries < 0 || o.max_iter < 1) return ADC_ERR_ARG;
-  if (o.nprobe < 1 || o.nprobe > 64 || o.r_cap < 1 || !(o.rank_eps > 0.0)) return ADC_ERR_ARG;
+  if (o.nprobe < 1 || o.nprobe > 32 || o.r_cap < 1 || !(o.rank_eps > 0.0)) return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
   return ADC_OK;
 }
@@ -90,6 +90,9 @@ void adc_ctx_s::release() {
   if (host_stage) hipHostFree(host_stage);
   host_stage = nullptr;
   host_stage_bytes = 0;
+  if (host_stage2) hipHostFree(host_stage2);
+  host_stage2 = nullptr;
+  host_stage2_bytes = 0;
   timer.destroy();
   ktimer.destroy();
   mlp_release(this);
@@ -130,6 +133,22 @@ adc_status adc_ctx_s::stage(size_t bytes, void** p) {
     host_stage_bytes = want;
   }
   *p = host_stage;
+  return ADC_OK;
+}
+
+adc_status adc_ctx_s::stage2(size_t bytes, void** p) {
+  if (host_stage2_bytes < bytes) {
+    if (host_stage2) {
+      hipStreamSynchronize(stream);
+      hipHostFree(host_stage2);
+    }
+    host_stage2 = nullptr;
+    host_stage2_bytes = 0;
+    size_t want = std::max(bytes, (size_t)(1 << 20));
+    if (hipHostMalloc(&host_stage2, want, hipHostMallocDefault) != hipSuccess) return ADC_ERR_NOMEM;
+    host_stage2_bytes = want;
+  }
+  *p = host_stage2;
   return ADC_OK;
 }
 

@@ -142,12 +142,15 @@ struct adc_ctx_s {
   Buf bufs[NSLOT];
   void* host_stage = nullptr;
   size_t host_stage_bytes = 0;
+  void* host_stage2 = nullptr;  // pinned staging of GEMM problem lists
+  size_t host_stage2_bytes = 0;
   MlpState* mlp = nullptr;
   void* batch_cache = nullptr;  // graph cache of the batched solver
   PhaseTimer timer;
   KernTimer ktimer;
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);
+  adc_status stage2(size_t bytes, void** p);
   void release();
 };
 

@@ -321,7 +321,15 @@ struct ApplyJob {
 
 static void push_prob(std::vector<GemmProb>& v, const GemmProb& p) { v.push_back(p); }
 
-static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops) {
+// Problem lists of one Algorithm 3 run: pinned host and device arrays filled
+// front to back, so that no launch waits for the previous one's descriptors.
+struct ProbArena {
+  GemmProb* h = nullptr;
+  GemmProb* d = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops, ProbArena& ar) {
   if (probs.empty()) return ADC_OK;
   std::vector<GemmProb> narrow, wide;
   double pf[2] = {0.0, 0.0}, pb[2] = {0.0, 0.0};
@@ -347,9 +355,12 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
       p.tile0 = tiles;
       tiles += p.tiles_m * ((p.N + bn - 1) / bn);
     }
-    void* dp;
-    ADC_TRY(c->buffer(pass ? SLOT_GEMM_B : SLOT_GEMM_A, L.size() * sizeof(GemmProb) + 256, &dp));
-    HIP_OK(hipMemcpyAsync(dp, L.data(), L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
+    if (ar.used + L.size() > ar.cap) return ADC_ERR_UNSUPPORTED;  // sized by the caller
+    GemmProb* hp = ar.h + ar.used;
+    GemmProb* dp = ar.d + ar.used;
+    ar.used += L.size();
+    std::memcpy(hp, L.data(), L.size() * sizeof(GemmProb));
+    HIP_OK(hipMemcpyAsync(dp, hp, L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
     c->ktimer.pre(st);
     if (pass)
       hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
@@ -357,8 +368,6 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
       hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
     c->ktimer.post(st, pass ? KT_GEMM : KT_GEMM64, pf[pass], pb[pass]);
     HIP_OK(hipGetLastError());
-    // the descriptor arrays are host vectors: wait before they are reused
-    HIP_OK(hipStreamSynchronize(st));
   }
   return ADC_OK;
 }
@@ -418,7 +427,23 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
   HIP_OK(hipGetLastError());
 
   int Lmax = 0;
-  for (auto& j : jobs) Lmax = std::max(Lmax, hb.ms[j.g].L);
+  size_t nodes_all = 0;
+  for (auto& j : jobs) {
+    Lmax = std::max(Lmax, hb.ms[j.g].L);
+    nodes_all += hb.ms[j.g].nodes.size();
+  }
+  // every node appears in at most one problem of the upsweep, two of the
+  // downsweep and one of the leaf step
+  ProbArena ar;
+  ar.cap = 4 * nodes_all + 64;
+  {
+    void* hpin;
+    void* dbuf;
+    ADC_TRY(c->stage2(ar.cap * sizeof(GemmProb), &hpin));
+    ADC_TRY(c->buffer(SLOT_GEMM_A, ar.cap * sizeof(GemmProb) + 256, &dbuf));
+    ar.h = (GemmProb*)hpin;
+    ar.d = (GemmProb*)dbuf;
+  }
   std::vector<GemmProb> probs;
   auto G = [&](size_t t, int node) {
     const auto& m = hb.ms[jobs[t].g];
@@ -460,7 +485,7 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         push_prob(probs, p);
       }
     }
-    ADC_TRY(launch_probs(c, probs, flops));
+    ADC_TRY(launch_probs(c, probs, flops, ar));
   }
   // downsweep: H_i = G_j B_j (+ F_i); then [F_i1 F_i2] = H_i V_i^T
   for (int l = 1; l <= Lmax; ++l) {
@@ -487,7 +512,7 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         push_prob(probs, p);
       }
     }
-    ADC_TRY(launch_probs(c, probs, flops));
+    ADC_TRY(launch_probs(c, probs, flops, ar));
     probs.clear();
     for (size_t t = 0; t < jobs.size(); ++t) {
       const auto& m = hb.ms[jobs[t].g];
@@ -509,7 +534,7 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         push_prob(probs, p);
       }
     }
-    ADC_TRY(launch_probs(c, probs, flops));
+    ADC_TRY(launch_probs(c, probs, flops, ar));
   }
   // leaves: out(:, t_i) = X(:, t_i) D_i + H_i V_i^T
   probs.clear();
@@ -546,7 +571,9 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       push_prob(probs, p);
     }
   }
-  ADC_TRY(launch_probs(c, probs, flops));
+  ADC_TRY(launch_probs(c, probs, flops, ar));
+  // the pinned problem lists are reused by the next run
+  HIP_OK(hipStreamSynchronize(st));
   return ADC_OK;
 }
 
@@ -562,16 +589,22 @@ static void draw_omega(adc_ctx c, const HssBatch::One& m, uint64_t seed) {
 static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double* flops) {
   hipStream_t st = c->stream;
   const int nm = (int)hb.ms.size();
-  int64_t tot = 0;
+  int64_t tot = 0, part_max = 0;
   std::vector<int64_t> base(nm);
+  std::vector<int> nseg(nm);
   for (int g = 0; g < nm; ++g) {
     base[g] = tot;
-    tot += 3 * (int64_t)hb.ms[g].K * SP_PROBE;
+    const int K = hb.ms[g].K;
+    tot += 3 * (int64_t)K * SP_PROBE;
+    // row segments so that a launch has about 2048 single-wave workgroups
+    nseg[g] = std::max(1, std::min(64, (2048 + (K + 63) / 64 - 1) / ((K + 63) / 64)));
+    part_max = std::max(part_max, (int64_t)nseg[g] * K * 8);
   }
   void* p;
-  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)tot * 8 + nm * 16 + 1024, &p));
+  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)(tot + part_max) * 8 + nm * 16 + 1024, &p));
   double* buf = (double*)p;
-  double* norms = buf + tot;
+  double* part = buf + tot;
+  double* norms = part + part_max;
   std::vector<SampleJob> sj;
   std::vector<ApplyJob> aj;
   for (int g = 0; g < nm; ++g) {
@@ -584,20 +617,21 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
                        o.nprobe, SP_PROBE, o.seed, 2u * m.stream + 1u);
     aj.push_back(ApplyJob{g, W, SP_PROBE, SP_PROBE, WH, SP_PROBE, nullptr});
   }
-  // W^T Q' per merge (sampling kernel, transposed, no exclusion)
+  // W^T Q' per merge: FP64 vector kernel over the generated entries (four
+  // probes do not fill a matrix-core tile), then the padding columns zeroed
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
-    sj.clear();
-    for (int r0 = 0; r0 < m.K; r0 += 64) sj.push_back(SampleJob{g, r0, 0});
-    void* dp;
-    ADC_TRY(c->buffer(SLOT_HSS_JOBS, sj.size() * sizeof(SampleJob) + 256, &dp));
-    HIP_OK(hipMemcpyAsync(dp, sj.data(), sj.size() * sizeof(SampleJob), hipMemcpyHostToDevice, st));
     double* W = buf + base[g];
     double* WQ = W + (int64_t)m.K * SP_PROBE;
-    hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms, (const SampleJob*)dp, 1, 0,
-                       (const double*)W, WQ, SP_PROBE);
+    const int ntj = (m.K + 63) / 64;
+    for (int c0 = 0; c0 < o.nprobe; c0 += 8) {
+      const int nc = std::min(8, o.nprobe - c0);
+      hipLaunchKernelGGL(k_probe_qt, dim3((unsigned)(ntj * nseg[g])), dim3(64), 0, st, hb.d_ms, g, (const double*)W,
+                         SP_PROBE, c0, nc, nseg[g], part);
+      hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)(((int64_t)m.K * SP_PROBE + 255) / 256)), dim3(256), 0, st,
+                         (const double*)part, m.K, nseg[g], c0, nc, o.nprobe, WQ, SP_PROBE);
+    }
     HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(st));
   }
   ADC_TRY(batch_apply(c, hb, aj, flops));
   for (int g = 0; g < nm; ++g) {

@@ -69,6 +69,10 @@ struct NodeJob {
   int32_t root;  // 1: only generate the children's B blocks
 };
 __global__ void k_hss_compress(const HssMerge* __restrict__ ms, const NodeJob* __restrict__ jobs, int lds_doubles);
+__global__ void k_probe_qt(const HssMerge* __restrict__ ms, int g, const double* __restrict__ W, int ldw, int c0,
+                           int nc, int nseg, double* __restrict__ part);
+__global__ void k_probe_sum(const double* __restrict__ part, int K, int nseg, int c0, int nc, int ntot,
+                            double* __restrict__ out, int ldo);
 __global__ void k_hss_dmat(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
                            double* __restrict__ dmat, const int64_t* __restrict__ doff);
 __global__ void k_diff_norms(const double* __restrict__ a, const double* __restrict__ b, int64_t n,

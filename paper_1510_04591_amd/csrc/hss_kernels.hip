@@ -501,6 +501,84 @@ __global__ void __launch_bounds__(256) k_hss_dmat(const HssMerge* __restrict__ m
 }
 
 // out2[0] = sum (a - b)^2, out2[1] = sum b^2 (one block, deterministic order)
+// Probe products of the accuracy check, (W^T Q')^T = Q'^T W, with W K x ldw
+// row-major and 8 probe columns c0..c0+7 per pass: one column j of Q' per
+// lane, the row range split into nseg segments (one per workgroup row) whose
+// partial sums part[seg][j][8] k_probe_sum adds.  Q'(i, j) = uh_i v_j /
+// (d_i - lam_j) (eq. Ev-Q, differences by eq. d-lambda) is generated in FP64
+// registers; the reciprocal is the hardware estimate refined by two Newton
+// steps.
+__device__ __forceinline__ double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__global__ void __launch_bounds__(64) k_probe_qt(const HssMerge* __restrict__ ms, int g, const double* __restrict__ W,
+                                                 int ldw, int c0, int nc, int nseg, double* __restrict__ part) {
+  __shared__ double s_d[65], s_u[64], s_w[64][8];
+  const HssMerge& M = ms[g];
+  const int K = M.K;
+  const int ntj = (K + 63) / 64;
+  const int jt = blockIdx.x % ntj, seg = blockIdx.x / ntj;
+  const int lane = threadIdx.x;
+  const int j = jt * 64 + lane;
+  const bool valid = j < K;
+  const int len = (K + nseg - 1) / nseg;
+  const int ia = seg * len, ib = min(K, ia + len);
+  double dj = 0.0, dj1 = 0.0, gj = 0.0, mj = 0.0, vj = 0.0;
+  if (valid) {
+    dj = M.d[j];
+    dj1 = (j + 1 < K) ? M.d[j + 1] : 0.0;
+    gj = M.gam[j];
+    mj = M.mu[j];
+    vj = M.v[j];
+  }
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int i0 = ia; i0 < ib; i0 += 64) {
+    __syncthreads();
+    const int i = i0 + lane;
+    s_d[lane] = (i < ib) ? M.d[i] : 0.0;
+    s_u[lane] = (i < ib) ? M.uh[i] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s_w[lane][c] = (i < ib && c < nc) ? W[(int64_t)i * ldw + c0 + c] : 0.0;
+    __syncthreads();
+    const int cnt = min(64, ib - i0);
+    if (valid) {
+      for (int t = 0; t < cnt; ++t) {
+        const double dl = d_minus_lam(i0 + t, j, s_d[t], dj, dj1, gj, mj);
+        const double q = s_u[t] * vj * rcp_refined(dl);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = fma(q, s_w[t][c], acc[c]);
+      }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) part[((int64_t)seg * K + j) * 8 + c] = acc[c];
+  }
+}
+
+// out[j ldo + col] = sum over segments of part[seg][j][col - c0] for col in
+// [c0, c0 + nc); columns at or beyond ntot (the probe count) are zeroed.
+__global__ void k_probe_sum(const double* __restrict__ part, int K, int nseg, int c0, int nc, int ntot,
+                            double* __restrict__ out, int ldo) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)K * ldo) return;
+  const int j = (int)(e / ldo), col = (int)(e % ldo);
+  if (col >= c0 && col < c0 + nc) {
+    double x = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) x += part[((int64_t)sg * K + j) * 8 + (col - c0)];
+    out[e] = x;
+  } else if (col >= ntot) {
+    out[e] = 0.0;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_diff_norms(const double* __restrict__ a, const double* __restrict__ b,
                                                      int64_t n, double* __restrict__ out2) {
   __shared__ double s0[1024], s1[1024];
