@@ -188,36 +188,78 @@ __device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int o
   }
 }
 
+// Lane exchanges inside a wave by DPP (no LDS round trip): CTRL 0xB1 swaps
+// neighbours (quad_perm 1,0,3,2), 0x4E swaps pairs (quad_perm 2,3,0,1),
+// 0x141 mirrors each half row of 8 lanes, 0x140 each row of 16.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+// sum over an aligned group of 8 lanes, the same value in every lane of it
+__device__ __forceinline__ double sum8(double x) {
+  x += dpp_d<0xB1>(x);
+  x += dpp_d<0x4E>(x);
+  x += dpp_d<0x141>(x);
+  return x;
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+  const double ov = dpp_d<CTRL>(v);
+  const int oi = dpp_i<CTRL>(i);
+  argmax_merge(v, i, ov, oi);
+}
+
+// The work on columns is spread over groups of 8 lanes (rows split between
+// the lanes, sums by DPP inside the group); wave 0 takes the pivot and builds
+// the reflector.  in_global: A lives in global memory, where stores of one
+// lane are fenced before other lanes of the group read them.
 __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
-                       double* redv, int* redi) {
-  (void)redv;
-  (void)redi;
+                       double* redv, int* redi, bool in_global) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  const int grp = tid >> 3, q = tid & 7, ngrp = (int)(blockDim.x >> 3);
   __shared__ int s_stop;
   __shared__ double s_r11, s_vn2;
-  // squared norms of every column (a thread per column, rows in order)
-  for (int c = tid; c < n; c += blockDim.x) {
-    perm[c] = c;
-    const double* col = A + (int64_t)c * lda;
+  for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
+  // squared column norms
+  for (int c0 = 0; c0 < n; c0 += ngrp) {
+    const int c = c0 + grp;
     double s2 = 0.0;
-    for (int r = 0; r < m; ++r) s2 += col[r] * col[r];
-    nrm[c] = s2;
+    if (c < n) {
+      const double* col = A + (int64_t)c * lda;
+      for (int r = q; r < m; r += 8) s2 = fma(col[r], col[r], s2);
+    }
+    s2 = sum8(s2);
+    if (c < n && q == 0) nrm[c] = s2;
   }
   __syncthreads();
   const int kmax = min(m, n);
   int k = 0;
   for (; k < kmax; ++k) {
     if (wv == 0) {
-      // pivot: largest remaining norm, ties to the smaller index
+      // pivot: largest remaining norm, ties to the smaller index; rows of 16
+      // lanes by DPP, the four rows through LDS
       double best = -1.0;
       int bi = n;
       for (int c = k + lane; c < n; c += 64) argmax_merge(best, bi, nrm[c], c);
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        argmax_merge(best, bi, ov, oi);
+      argmax_step<0xB1>(best, bi);
+      argmax_step<0x4E>(best, bi);
+      argmax_step<0x141>(best, bi);
+      argmax_step<0x140>(best, bi);
+      if ((lane & 15) == 0) {
+        redv[lane >> 4] = best;
+        redi[lane >> 4] = bi;
       }
+      __builtin_amdgcn_wave_barrier();
+      best = redv[0];
+      bi = redi[0];
+      for (int w = 1; w < 4; ++w) argmax_merge(best, bi, redv[w], redi[w]);
       const double pn = sqrt(fmax(best, 0.0));
       const double r11 = (k == 0) ? pn : s_r11;
       const int stop = (bi >= n) || (pn == 0.0) || (pn <= tol * r11);
@@ -230,6 +272,7 @@ __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, 
             ck[r] = ci[r];
             ci[r] = t;
           }
+          if (in_global) __threadfence_block();
         }
         // Householder vector v = x - alpha e_1, alpha = -sign(x_0)||x||,
         // v^T v = 2 ||x|| (||x|| + |x_0|)
@@ -258,30 +301,48 @@ __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, 
     __syncthreads();
     if (s_stop) break;
     const double vn2 = s_vn2;
-    // a thread per remaining column: reflect it and take its norm below row k
-    for (int c = k + 1 + tid; c < n; c += blockDim.x) {
-      double* col = A + (int64_t)c * lda;
-      double dt = 0.0;
-      for (int r = k; r < m; ++r) dt += vv[r] * col[r];
+    // a group per remaining column: reflect it and take its norm below row k
+    for (int c0 = k + 1; c0 < n; c0 += ngrp) {
+      const int c = c0 + grp;
+      const bool act = c < n;
+      double* col = A + (int64_t)(act ? c : k) * lda;
+      double d0 = 0.0, d1 = 0.0;
+      if (act) {
+        int r = k + q;
+        for (; r + 8 < m; r += 16) {
+          d0 = fma(vv[r], col[r], d0);
+          d1 = fma(vv[r + 8], col[r + 8], d1);
+        }
+        if (r < m) d0 = fma(vv[r], col[r], d0);
+      }
+      const double dt = sum8(d0 + d1);
       const double f = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;
       double s2 = 0.0;
-      for (int r = k; r < m; ++r) {
-        const double x = col[r] - f * vv[r];
-        col[r] = x;
-        if (r > k) s2 += x * x;
+      if (act) {
+        for (int r = k + q; r < m; r += 8) {
+          const double x = col[r] - f * vv[r];
+          col[r] = x;
+          if (r > k) s2 = fma(x, x, s2);
+        }
       }
-      nrm[c] = s2;
+      s2 = sum8(s2);
+      if (act && q == 0) nrm[c] = s2;
     }
     __syncthreads();
   }
-  // T = R11^-1 R12 in place: back substitution, a wave per column (the
-  // update of the remaining rows is spread over the lanes)
-  for (int c = k + wv; c < n; c += (int)(blockDim.x >> 6)) {
-    double* col = A + (int64_t)c * lda;
-    for (int j = k - 1; j >= 0; --j) {
-      const double xj = col[j] / A[j + (int64_t)j * lda];
-      for (int r = lane; r < j; r += 64) col[r] -= xj * A[r + (int64_t)j * lda];
-      if (lane == 0) col[j] = xj;
+  // T = R11^-1 R12 in place: back substitution, a group per column (rows of
+  // the update split between its lanes)
+  for (int c0 = k; c0 < n; c0 += ngrp) {
+    const int c = c0 + grp;
+    if (c < n) {
+      double* col = A + (int64_t)c * lda;
+      for (int j = k - 1; j >= 0; --j) {
+        const double xj = col[j] / A[j + (int64_t)j * lda];
+        const double* aj = A + (int64_t)j * lda;
+        for (int r = q; r < j; r += 8) col[r] = fma(-xj, aj[r], col[r]);
+        if (q == 0) col[j] = xj;
+        if (in_global) __threadfence_block();
+      }
     }
   }
   __syncthreads();
@@ -444,7 +505,7 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     for (int c = tid >> 6; c < nc; c += blockDim.x >> 6)
       for (int r = tid & 63; r < sp; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
     __syncthreads();
-    const int k = cpqr_id(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+    const int k = cpqr_id(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi, !in_lds);
     double* U = ar + (side ? nd.offV : nd.offU);
     write_interp(Aw, lw, nc, k, s_perm, s_inv, U);
     int* skel = ia + (side ? nd.offSc : nd.offSr);

@@ -487,10 +487,12 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
 __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
                                                   const int32_t* __restrict__ col_merge,
                                                   const int32_t* __restrict__ col_idx, LevelBufs B) {
+  constexpr int CHMAX = 8;  // rotation steps held in registers
   const MergeDev& M = merges[col_merge[blockIdx.x]];
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1;
   const int p = col_idx[blockIdx.x];
+  const int bs = blockDim.x, tid = threadIdx.x;
   if (B.rot_j_of[s0 + p] >= 0) return;  // inside a chain: done by its head
   auto dst_of = [&](int pos) -> double* {
     const int role = B.pidx[s0 + pos];
@@ -505,13 +507,26 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
   auto supp_of = [&](int pos) { return (B.src[s0 + pos] < n1) ? 1 : 2; };
   const int t0 = B.rot_i_of[s0 + p];
   if (t0 < 0) {
-    const double* sc = src_of(p);
-    double* dc = dst_of(p);
+    const double* __restrict__ sc = src_of(p);
+    double* __restrict__ dc = dst_of(p);
     const int f = supp_of(p);
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-      const int bit = (r < n1) ? 1 : 2;
-      dc[r] = (f & bit) ? sc[r] : 0.0;
+    // rows outside the support are zero; the dense path's grouped GEMM never
+    // reads them in a packed column, every other destination needs them
+    const bool zero = !(B.pidx[s0 + p] >= 0 && M.mode == 0);
+    const int lo = (f & 1) ? 0 : n1, hi = (f & 2) ? n : n1;
+    if (zero) {
+      for (int r = tid; r < lo; r += bs) dc[r] = 0.0;
+      for (int r = hi + tid; r < n; r += bs) dc[r] = 0.0;
     }
+    int r = lo + tid;
+    for (; r + 3 * bs < hi; r += 4 * bs) {
+      const double x0 = sc[r], x1 = sc[r + bs], x2 = sc[r + 2 * bs], x3 = sc[r + 3 * bs];
+      dc[r] = x0;
+      dc[r + bs] = x1;
+      dc[r + 2 * bs] = x2;
+      dc[r + 3 * bs] = x3;
+    }
+    for (; r < hi; r += bs) dc[r] = sc[r];
     return;
   }
   // chain t0, t0+1, ... while rot_i[t+1] == rot_j[t]
@@ -519,8 +534,44 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
   int t1 = t0;
   while (t1 + 1 < nrot && B.rot_i[s0 + t1 + 1] == B.rot_j[s0 + t1]) ++t1;
   const int fa = supp_of(p);
-  const double* sa = src_of(p);
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+  const double* __restrict__ sa = src_of(p);
+  if (t1 - t0 < CHMAX) {
+    // every step's operands in registers, so that the row loop reloads
+    // nothing but the column entries
+    const int L = t1 - t0 + 1;
+    const double* sj[CHMAX];
+    double* di[CHMAX];
+    double cs[CHMAX], sn[CHMAX];
+    int fj[CHMAX];
+#pragma unroll
+    for (int u = 0; u < CHMAX; ++u) {
+      if (u < L) {
+        const int t = t0 + u;
+        const int pj = B.rot_j[s0 + t];
+        sj[u] = src_of(pj);
+        fj[u] = supp_of(pj);
+        di[u] = dst_of(B.rot_i[s0 + t]);
+        cs[u] = B.rot_c[s0 + t];
+        sn[u] = B.rot_s[s0 + t];
+      }
+    }
+    double* __restrict__ dlast = dst_of(B.rot_j[s0 + t1]);
+    for (int r = tid; r < n; r += bs) {
+      const int bit = (r < n1) ? 1 : 2;
+      double a = (fa & bit) ? sa[r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < CHMAX; ++u) {
+        if (u < L) {
+          const double b = (fj[u] & bit) ? sj[u][r] : 0.0;
+          di[u][r] = cs[u] * a + sn[u] * b;
+          a = -sn[u] * a + cs[u] * b;
+        }
+      }
+      dlast[r] = a;
+    }
+    return;
+  }
+  for (int r = tid; r < n; r += bs) {
     const int bit = (r < n1) ? 1 : 2;
     double a = (fa & bit) ? sa[r] : 0.0;
     for (int t = t0; t <= t1; ++t) {
