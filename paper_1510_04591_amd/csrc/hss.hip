@@ -216,13 +216,28 @@ static adc_status batch_upload(adc_ctx c, HssBatch& hb) {
 static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   hipStream_t st = c->stream;
   const int nm = (int)hb.ms.size();
-  // sampling jobs
+  // sampling jobs: Y and Z in one launch, the inner dimension split into
+  // segments until about six waves per SIMD are resident (each 64-row job is
+  // four waves); segment partial sums are added afterwards
+  int64_t Ksum = 0;
+  for (auto& m : hb.ms) Ksum += m.K;
+  const int64_t waves = 2 * ((Ksum + 15) / 16);
+  const int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(8, (6144 + waves - 1) / waves));
   std::vector<SampleJob> sj;
+  std::vector<int64_t> pb(nm, 0);
+  int64_t ptot = 0;
   for (int g = 0; g < nm; ++g) {
     const auto& m = hb.ms[g];
-    for (int r0 = 0; r0 < m.K; r0 += 64)
-      for (int c0 = 0; c0 < m.sp; c0 += 32) sj.push_back(SampleJob{g, r0, c0});
+    pb[g] = ptot;
+    if (nseg > 1) ptot += (int64_t)2 * nseg * m.K * m.sp;
+    for (int tr = 0; tr < 2; ++tr)
+      for (int sg = 0; sg < nseg; ++sg)
+        for (int r0 = 0; r0 < m.K; r0 += 64)
+          for (int c0 = 0; c0 < m.sp; c0 += 128)
+            sj.push_back(SampleJob{g, r0, c0, tr, sg, nseg, pb[g] + (int64_t)(tr * nseg + sg) * m.K * m.sp});
   }
+  double* part = nullptr;
+  if (nseg > 1) ADC_TRY(c->buffer(SLOT_HSS2, (size_t)ptot * 8 + 256, (void**)&part));
   // compression jobs per level
   int Lmax = 0;
   for (auto& m : hb.ms) Lmax = std::max(Lmax, m.L);
@@ -241,12 +256,12 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
       }
     }
   }
-  size_t njobs = sj.size();
-  for (auto& v : lj) njobs += v.size();
+  size_t jbytes = sj.size() * sizeof(SampleJob) + 256 * (Lmax + 2);
+  for (auto& v : lj) jbytes += v.size() * sizeof(NodeJob);
   void* dp;
-  ADC_TRY(c->buffer(SLOT_HSS_JOBS, njobs * 16 + 4096, &dp));
+  ADC_TRY(c->buffer(SLOT_HSS_JOBS, jbytes, &dp));
   char* dj = (char*)dp;
-  std::vector<char> hj(njobs * 16 + 4096);
+  std::vector<char> hj(jbytes);
   size_t off = 0;
   auto put = [&](const void* src, size_t n) {
     const size_t o = off;
@@ -268,11 +283,19 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
     sfl += 2.0 * m.s * ((double)m.K * m.K - dsq);
     sby += 16.0 * m.K * m.s;
   }
-  for (int tr = 0; tr < 2; ++tr) {
-    c->ktimer.pre(st);
-    hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms,
-                       (const SampleJob*)(dj + o_sj), tr, 1, (const double*)nullptr, (double*)nullptr, 0);
-    c->ktimer.post(st, KT_SAMPLE, sfl, sby);
+  c->ktimer.pre(st);
+  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms, (const SampleJob*)(dj + o_sj),
+                     1, part);
+  c->ktimer.post(st, KT_SAMPLE, 2.0 * sfl, 2.0 * sby);
+  if (nseg > 1) {
+    for (int g = 0; g < nm; ++g) {
+      const auto& m = hb.ms[g];
+      const int64_t n = (int64_t)m.K * m.sp;
+      for (int tr = 0; tr < 2; ++tr)
+        hipLaunchKernelGGL(k_sample_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (const double*)(part + pb[g] + (int64_t)tr * nseg * n), nseg, n,
+                           tr ? m.dev.theta : m.dev.phi);
+    }
   }
   HIP_OK(hipGetLastError());
   c->timer.mark(st, 5);
@@ -280,10 +303,10 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   // dimension sp + 1), else the staging of its small products
   (void)ncand_max;
   (void)sp_max;
-  const int lds = 15360;
+  const int lds = 18432;  // dynamic LDS doubles of a node job (144 KiB)
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_hss_compress, hipFuncAttributeMaxDynamicSharedMemorySize, 15360 * 8);
+    hipFuncSetAttribute((const void*)k_hss_compress, hipFuncAttributeMaxDynamicSharedMemorySize, lds * 8);
     attr_set = true;
   }
   for (int l = Lmax; l >= 0; --l) {

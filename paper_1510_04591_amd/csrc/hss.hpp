@@ -57,12 +57,16 @@ __global__ void k_philox_normal(double* __restrict__ out, int64_t K, int s, int 
                                 uint32_t stream);
 struct SampleJob {
   int32_t merge;
-  int32_t r0;   // first output row
-  int32_t c0;   // first sample column (multiple of 32)
+  int32_t r0;     // first output row
+  int32_t c0;     // first sample column (multiple of 128)
+  int32_t trans;  // 0: rows of Q' (Y = Q' Omega), 1: columns (Z = Q'^T Omega)
+  int32_t seg;    // segment of the inner dimension
+  int32_t nseg;   // segments; > 1: partial sums go to part + pbase
+  int64_t pbase;  // element offset of this (merge, trans, seg) partial block
 };
-__global__ void k_hss_sample(const HssMerge* __restrict__ ms, const SampleJob* __restrict__ jobs, int trans,
-                             int exclude_diag, const double* __restrict__ omega_override,
-                             double* __restrict__ out_override, int sp_override);
+__global__ void k_hss_sample(const HssMerge* __restrict__ ms, const SampleJob* __restrict__ jobs, int exclude_diag,
+                             double* __restrict__ part);
+__global__ void k_sample_sum(const double* __restrict__ part, int nseg, int64_t n, double* __restrict__ out);
 struct NodeJob {
   int32_t merge;
   int32_t node;  // heap index

@@ -76,22 +76,44 @@ __global__ void k_philox_normal(double* __restrict__ out, int64_t K, int s, int 
 }
 
 // ---------------------------------------------------------------------------
-// sampling: rows r0..r0+63 (16 per wave) x columns c0..c0+31 of the output
+// sampling: rows r0..r0+63 (16 per wave) x columns c0..c0+127 of the output
+// (those below sp).  Each lane generates one 16 x 4 fragment entry of Q' per
+// step and feeds it to every 16-column tile of the job, so that an entry is
+// generated once for all samples; Omega is staged through LDS 32 rows at a
+// time (row stride = 16 (mod 32) doubles: the four k-rows of a fragment read
+// fall on the two bank halves).
+namespace {
+__device__ __forceinline__ double rcp2(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+}  // namespace
+
 __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__ ms,
-                                                    const SampleJob* __restrict__ jobs, int trans, int exclude_diag,
-                                                    const double* __restrict__ omega_override,
-                                                    double* __restrict__ out_override, int sp_override) {
-  constexpr int JT = 64;
-  __shared__ double s_om[JT][33];
+                                                    const SampleJob* __restrict__ jobs, int exclude_diag,
+                                                    double* __restrict__ part) {
+  constexpr int JT = 32;   // rows of Omega per staging round
+  constexpr int NT = 8;    // 16-column tiles per job
+  constexpr int LDO = 16 * NT + 16;
+  __shared__ double s_om[JT][LDO];
   __shared__ double s_g0[JT + 1], s_g1[JT], s_g2[JT], s_g3[JT];
   const SampleJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
   const int K = M.K;
-  const int sp = sp_override > 0 ? sp_override : M.sp;
-  const double* __restrict__ om = omega_override ? omega_override : M.omega;
-  double* __restrict__ out = out_override ? out_override : (trans ? M.theta : M.phi);
+  const int sp = M.sp;
+  const int trans = jb.trans;
+  const double* __restrict__ om = M.omega;
+  double* __restrict__ out = (jb.nseg > 1) ? part + jb.pbase : (trans ? M.theta : M.phi);
+  // inner-dimension segment, whole staging rounds
+  const int len = ((K + jb.nseg - 1) / jb.nseg + JT - 1) / JT * JT;
+  const int qa = jb.seg * len, qb = min(K, qa + len);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int ncols = min(16 * NT, sp - jb.c0);
+  const int ntl = (ncols + 15) / 16;
   const int rr = jb.r0 + wv * 16 + li;  // this lane's output row
   const bool rvalid = rr < K;
   int lo_r = 0, hi_r = 0;
@@ -112,13 +134,15 @@ __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__
       ru = M.uh[rr];
     }
   }
-  dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
-  for (int q0 = 0; q0 < K; q0 += JT) {
+  dbl4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int q0 = qa; q0 < qb; q0 += JT) {
     __syncthreads();
-    for (int e = tid; e < JT * 32; e += 256) {
-      const int qr = e >> 5, cc = e & 31;
-      const int q = q0 + qr, c = jb.c0 + cc;
-      s_om[qr][cc] = (q < K && c < sp) ? om[(int64_t)q * sp + c] : 0.0;
+    for (int e = tid; e < JT * 16 * NT; e += 256) {
+      const int qr = e / (16 * NT), cc = e % (16 * NT);
+      const int q = q0 + qr;
+      s_om[qr][cc] = (q < qb && cc < ncols) ? om[(int64_t)q * sp + jb.c0 + cc] : 0.0;
     }
     if (tid < JT) {
       const int q = q0 + tid;
@@ -138,29 +162,29 @@ __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__
     }
     if (tid == 0) s_g0[JT] = (q0 + JT < K) ? M.d[q0 + JT] : 0.0;
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
     for (int kk = 0; kk < JT / 4; ++kk) {
       const int ql = kk * 4 + lk;
       const int q = q0 + ql;
       double a = 0.0;
-      if (rvalid && q < K && !(q >= lo_r && q < hi_r)) {
+      if (rvalid && q < qb && !(q >= lo_r && q < hi_r)) {
         if (trans) {
           // Q'(q, rr): i = q (inner), j = rr
-          a = cauchy_entry(q, rr, s_g0[ql], s_g1[ql], rd, rd1, rg, rm, rv);
+          a = s_g1[ql] * rv * rcp2(d_minus_lam(q, rr, s_g0[ql], rd, rd1, rg, rm));
         } else {
           // Q'(rr, q): i = rr, j = q
           const double dq1 = (q + 1 < K) ? s_g0[ql + 1] : 0.0;
-          a = cauchy_entry(rr, q, rd, ru, s_g0[ql], dq1, s_g1[ql], s_g2[ql], s_g3[ql]);
+          a = ru * s_g3[ql] * rcp2(d_minus_lam(rr, q, rd, s_g0[ql], dq1, s_g1[ql], s_g2[ql]));
         }
       }
-      const double b0 = s_om[ql][li];
-      const double b1 = s_om[ql][16 + li];
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[1], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        if (t < ntl) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, s_om[ql][16 * t + li], acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
+    if (t >= ntl) continue;
     const int col = jb.c0 + 16 * t + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -168,6 +192,15 @@ __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__
       if (row < K && col < sp) out[(int64_t)row * sp + col] = acc[t][r];
     }
   }
+}
+
+// out[e] = sum over the nseg partial blocks of n elements each
+__global__ void k_sample_sum(const double* __restrict__ part, int nseg, int64_t n, double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double x = 0.0;
+  for (int sg = 0; sg < nseg; ++sg) x += part[(int64_t)sg * n + e];
+  out[e] = x;
 }
 
 // ---------------------------------------------------------------------------
@@ -305,22 +338,23 @@ __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, 
     for (int c0 = k + 1; c0 < n; c0 += ngrp) {
       const int c = c0 + grp;
       const bool act = c < n;
-      double* col = A + (int64_t)(act ? c : k) * lda;
+      double* __restrict__ col = A + (int64_t)(act ? c : k) * lda;
+      const double* __restrict__ v = vv;
       double d0 = 0.0, d1 = 0.0;
       if (act) {
         int r = k + q;
         for (; r + 8 < m; r += 16) {
-          d0 = fma(vv[r], col[r], d0);
-          d1 = fma(vv[r + 8], col[r + 8], d1);
+          d0 = fma(v[r], col[r], d0);
+          d1 = fma(v[r + 8], col[r + 8], d1);
         }
-        if (r < m) d0 = fma(vv[r], col[r], d0);
+        if (r < m) d0 = fma(v[r], col[r], d0);
       }
       const double dt = sum8(d0 + d1);
       const double f = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;
       double s2 = 0.0;
       if (act) {
         for (int r = k + q; r < m; r += 8) {
-          const double x = col[r] - f * vv[r];
+          const double x = col[r] - f * v[r];
           col[r] = x;
           if (r > k) s2 = fma(x, x, s2);
         }
@@ -499,11 +533,14 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     // working copy: columns = candidates, rows = samples (ld sp)
     // working copy with an odd leading dimension in LDS (no bank aliasing of
     // columns), or the second half of the work area
-    const bool in_lds = lds_doubles >= nc * (sp + 1);
-    const int lw = in_lds ? sp + 1 : sp;
+    // in LDS the column stride is = 8 (mod 32) doubles, so that the eight
+    // 8-lane column groups of a wave fall on different banks
+    const int lw_lds = s + (((8 - s) % 32) + 32) % 32;
+    const bool in_lds = lds_doubles >= nc * lw_lds;
+    const int lw = in_lds ? lw_lds : sp;
     double* Aw = in_lds ? dyn : (W0 + (int64_t)nc * sp);
     for (int c = tid >> 6; c < nc; c += blockDim.x >> 6)
-      for (int r = tid & 63; r < sp; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
+      for (int r = tid & 63; r < s; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
     __syncthreads();
     const int k = cpqr_id(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi, !in_lds);
     double* U = ar + (side ? nd.offV : nd.offU);
