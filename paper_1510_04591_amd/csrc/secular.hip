@@ -40,6 +40,23 @@ __device__ __forceinline__ void pole_sums(const double* __restrict__ d, const do
                                           double dorg, double t, double& s, double& ds, double& ea) {
   double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0, e0 = 0.0, e1 = 0.0;
   int j = ja;
+  // four poles per step: their (wave-uniform) loads are all issued before
+  // the first is used
+  for (; j + 3 < jb; j += 4) {
+    const double z0 = z[j], z1 = z[j + 1], z2 = z[j + 2], z3 = z[j + 3];
+    const double d0 = d[j], d1 = d[j + 1], d2 = d[j + 2], d3 = d[j + 3];
+    const double t0 = z0 * rcp_nr((d0 - dorg) - t);
+    const double t1 = z1 * rcp_nr((d1 - dorg) - t);
+    const double t2 = z2 * rcp_nr((d2 - dorg) - t);
+    const double t3 = z3 * rcp_nr((d3 - dorg) - t);
+    const double u0 = z0 * t0, u1 = z1 * t1, u2 = z2 * t2, u3 = z3 * t3;
+    s0 += u0 + u2;
+    s1 += u1 + u3;
+    q0 = fma(t0, t0, fma(t2, t2, q0));
+    q1 = fma(t1, t1, fma(t3, t3, q1));
+    e0 += fabs(u0) + fabs(u2);
+    e1 += fabs(u1) + fabs(u3);
+  }
   for (; j + 1 < jb; j += 2) {
     const double za = z[j], zb = z[j + 1];
     const double ta = za * rcp_nr((d[j] - dorg) - t);
