@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only copy 1 GiB between two device buffers three times (HBM counter calibration)")
     p.add_argument("--batched-only", action="store_true")
+    p.add_argument("--c5", action="store_true",
+                   help="only the learned rank predictor at N = 32768 on prescribed spectra (trains first)")
     return p.parse_args()
 
 
@@ -183,6 +185,76 @@ def recorded_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
+def run_c5(torch, adc, ctx, steps):
+    """Learned rank predictor at full size: collect boundary ranks from the
+    training families (Toeplitz N = 4096 and 32768, random uniform N = 8192
+    seed 2, four matrices of the 256-matrix batch) with HSS forced on every
+    merge, train the MLP on the GPU, then solve N = 32768 matrices with
+    prescribed spectra (uniform, geometric, clusters; not seen in training)
+    with the sample count from eq. (bounds) and from the MLP."""
+    from paper_1510_04591_amd import workloads
+    Xs, ys = [], []
+    train = [workloads.toeplitz(4096), workloads.toeplitz(32768), workloads.random_uniform(8192, 2)]
+    train += [workloads.batched(8, 4)[i] for i in (0, 1, 5, 6)]
+    for a, b in train:
+        n = len(a)
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        for leaf in ((32, 64, 128) if n <= 8192 else (128,)):
+            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=max(2 * leaf, 256 if n > 8192 else 0), hss_levels=-1)
+            cap = 1 << 17
+            X = torch.empty((cap, 16), dtype=torch.float32, device="cuda")
+            y = torch.empty(cap, dtype=torch.float32, device="cuda")
+            st, rows = adc.adc_mlp_collect(ctx.h, n, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), w, Z, n,
+                                           o, cap, X, y)
+            if st != adc.ADC_OK:
+                raise adc.AdcError(st, "adc_mlp_collect")
+            Xs.append(X[:rows].clone())
+            ys.append(y[:rows].clone())
+        del Z
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    perm = torch.from_numpy(np.random.default_rng(0).permutation(X.shape[0])).cuda()
+    X, y = X[perm].contiguous(), y[perm].contiguous()
+    if adc.adc_mlp_init(ctx.h, 7) != adc.ADC_OK:
+        raise RuntimeError("adc_mlp_init")
+    t0 = time.perf_counter()
+    st, loss = adc.adc_mlp_train(ctx.h, X.shape[0], X, y, 150, 64, 1e-3)
+    t_train = time.perf_counter() - t0
+    out = {"training_rows": int(X.shape[0]), "train_loss": loss, "target_var": float(torch.var(y)),
+           "train_s": t_train, "spectra": {}}
+    N = 32768
+    w = torch.empty(N, dtype=torch.float64, device="cuda")
+    Zt = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    for kind in ("uniform", "geometric", "clusters"):
+        a, b = workloads.prescribed_tridiagonal(kind, N)
+        lam, _ = workloads.spectrum(kind, N)
+        ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        res = {}
+        for name, mode in (("bound", adc.ADC_RANK_BOUND), ("mlp", adc.ADC_RANK_MLP)):
+            o = adc.opts(dc_leaf=32, hss_leaf=128, hss_min_k=2048, hss_levels=-1, rank_mode=mode)
+            times = []
+            for it in range(steps + 1):
+                rep = adc.adc_report()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = adc.adc_stedc(ctx.h, N, ad, bd, w, Zt, N, None, 0, o, rep)
+                torch.cuda.synchronize()
+                if st != adc.ADC_OK:
+                    raise adc.AdcError(st, "adc_stedc", rep.as_dict())
+                if it > 0:
+                    times.append(time.perf_counter() - t0)
+            r = rep.as_dict()
+            v = validate(torch, a, b, w, Zt.t(), np.sort(lam))
+            res[name] = {"s": float(np.median(times)), "samples": r["samples"], "max_rank": r["max_rank"],
+                         "retries": r["retries"], "hss_merges": r["hss_merges"], "fallbacks": r["hss_fallbacks"],
+                         "hss_sampling_s": r["t_phase"][5] / 1.0, "validation": v}
+        out["spectra"][kind] = res
+        print(f"# C5 {kind}: bound {res['bound']['s']:.4f} s (s={res['bound']['samples']}), "
+              f"mlp {res['mlp']['s']:.4f} s (s={res['mlp']['samples']})", flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -200,6 +272,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
                           "copies": 3}), flush=True)
+        return
+    if args.c5:
+        ctx = adc.Context(0)
+        print(json.dumps({"c5": run_c5(torch, adc, ctx, args.steps)}), flush=True)
+        ctx.close()
         return
     if args.batched_only:
         ctx = adc.Context(0)

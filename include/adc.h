@@ -113,7 +113,8 @@ typedef struct adc_report {
   /* Per-kernel figures, each launch bracketed by HIP events on the context
    * stream: 0 k_gemm_f64 (128 x 128 FP64 MFMA GEMM tiles), 1 k_gemm_f64_n64
    * (128 x 64), 2 k_hss_sample, 3 k_pack_rot, 4 k_secular, 5 k_hss_compress,
-   * 6 k_gemm_f64_big (256 x 128, the dense update).
+   * 6 k_gemm_f64_big (256 x 128, the dense update), 7 k_gemm_f64_n96
+   * (128 x 96).
    * Times in seconds; flops and bytes are the algorithmic counts of the
    * launches (operands read once, results written once). */
   double  kern_time[8];

@@ -52,7 +52,7 @@ class adc_report(C.Structure):
     ]
 
     KERNELS = ("k_gemm_f64", "k_gemm_f64_n64", "k_hss_sample", "k_pack_rot", "k_secular", "k_hss_compress",
-               "k_gemm_f64_big")
+               "k_gemm_f64_big", "k_gemm_f64_n96")
 
     def as_dict(self):
         L = self.levels

@@ -54,7 +54,25 @@ def build(force=False, verbose=True):
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    build_gen(verbose)
     return LIB
+
+
+GEN_SRC = os.path.join(HERE, "jacobi_gen.c")
+GEN_LIB = os.path.join(HERE, "libadcgen.so")
+
+
+def build_gen(verbose=True):
+    """The host-side test-input generator (plain C, gcc)."""
+    tmp = GEN_LIB + ".tmp"
+    cmd = ["gcc", "-O3", "-shared", "-fPIC", "-o", tmp, GEN_SRC, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, GEN_LIB)
+    if verbose:
+        print("built", GEN_LIB)
+    return GEN_LIB
 
 
 if __name__ == "__main__":

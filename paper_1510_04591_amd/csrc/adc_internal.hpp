@@ -76,7 +76,8 @@ enum KernId {
   KT_PACK = 3,
   KT_SECULAR = 4,
   KT_COMPRESS = 5,
-  KT_GEMMBIG = 6
+  KT_GEMMBIG = 6,
+  KT_GEMM96 = 7
 };
 struct KernTimer {
   std::vector<hipEvent_t> ev;

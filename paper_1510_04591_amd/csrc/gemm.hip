@@ -17,6 +17,7 @@
 //
 //   k_gemm_f64       128 x 128, 4 x 2 waves (512 lanes)
 //   k_gemm_f64_n64   128 x 64,  4 x 2 waves (512 lanes), narrow products
+//   k_gemm_f64_n96   128 x 96,  4 x 2 waves (512 lanes), products 65..96 wide
 //   k_gemm_f64_big   256 x 128, 4 x 4 waves (1024 lanes), large updates
 #include "common.hpp"
 #include "kernels.hpp"
@@ -173,6 +174,10 @@ __global__ void __launch_bounds__(512) k_gemm_f64(const GemmProb* __restrict__ p
 
 __global__ void __launch_bounds__(512) k_gemm_f64_n64(const GemmProb* __restrict__ probs, int nprobs) {
   gemm_dispatch<128, 64, 4, 2>(probs, nprobs);
+}
+
+__global__ void __launch_bounds__(512) k_gemm_f64_n96(const GemmProb* __restrict__ probs, int nprobs) {
+  gemm_dispatch<128, 96, 4, 2>(probs, nprobs);
 }
 
 __global__ void __launch_bounds__(1024) k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs) {

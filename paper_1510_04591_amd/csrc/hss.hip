@@ -354,24 +354,26 @@ struct ProbArena {
 
 static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops, ProbArena& ar) {
   if (probs.empty()) return ADC_OK;
-  std::vector<GemmProb> narrow, wide;
-  double pf[2] = {0.0, 0.0}, pb[2] = {0.0, 0.0};
+  // tile width by the product width: 64, 96 or 128 columns
+  std::vector<GemmProb> cls[3];
+  double pf[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
   for (auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
     const double f = 2.0 * p.M * (double)p.N * (p.K + p.K2);
     const double by = 8.0 * ((double)p.M * (p.K + p.K2) + (double)(p.K + p.K2) * p.N +
                              (double)p.M * p.N * (p.beta != 0.0 ? 2 : 1));
     if (flops) *flops += f;
-    const int w = p.N <= 64 ? 0 : 1;
+    const int w = (p.N <= 64) ? 0 : (p.N <= 96) ? 1 : 2;
     pf[w] += f;
     pb[w] += by;
-    (w ? wide : narrow).push_back(p);
+    cls[w].push_back(p);
   }
   hipStream_t st = c->stream;
-  for (int pass = 0; pass < 2; ++pass) {
-    auto& L = pass ? wide : narrow;
+  static const int BN[3] = {64, 96, 128};
+  for (int w = 0; w < 3; ++w) {
+    auto& L = cls[w];
     if (L.empty()) continue;
-    const int bn = pass ? 128 : 64;
+    const int bn = BN[w];
     int tiles = 0;
     for (auto& p : L) {
       p.tiles_m = (p.M + 127) / 128;
@@ -385,11 +387,13 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
     std::memcpy(hp, L.data(), L.size() * sizeof(GemmProb));
     HIP_OK(hipMemcpyAsync(dp, hp, L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
     c->ktimer.pre(st);
-    if (pass)
-      hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
-    else
+    if (w == 0)
       hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
-    c->ktimer.post(st, pass ? KT_GEMM : KT_GEMM64, pf[pass], pb[pass]);
+    else if (w == 1)
+      hipLaunchKernelGGL(k_gemm_f64_n96, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
+    else
+      hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
+    c->ktimer.post(st, w == 0 ? KT_GEMM64 : w == 1 ? KT_GEMM96 : KT_GEMM, pf[w], pb[w]);
     HIP_OK(hipGetLastError());
   }
   return ADC_OK;
@@ -623,11 +627,13 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
     nseg[g] = std::max(1, std::min(64, (2048 + (K + 63) / 64 - 1) / ((K + 63) / 64)));
     part_max = std::max(part_max, (int64_t)nseg[g] * K * 8);
   }
+  constexpr int NBLK = 128;  // blocks of the norm partial sums
   void* p;
-  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)(tot + part_max) * 8 + nm * 16 + 1024, &p));
+  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)(tot + part_max + 2 * NBLK * nm) * 8 + nm * 16 + 1024, &p));
   double* buf = (double*)p;
   double* part = buf + tot;
-  double* norms = part + part_max;
+  double* npart = part + part_max;
+  double* norms = npart + 2 * NBLK * nm;
   std::vector<SampleJob> sj;
   std::vector<ApplyJob> aj;
   for (int g = 0; g < nm; ++g) {
@@ -661,7 +667,9 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
     double* W = buf + base[g];
     double* WQ = W + (int64_t)hb.ms[g].K * SP_PROBE;
     double* WH = WQ + (int64_t)hb.ms[g].K * SP_PROBE;
-    hipLaunchKernelGGL(k_diff_norms, dim3(1), dim3(1024), 0, st, WH, WQ, (int64_t)hb.ms[g].K * SP_PROBE,
+    hipLaunchKernelGGL(k_diff_norms, dim3(NBLK), dim3(256), 0, st, WH, WQ, (int64_t)hb.ms[g].K, SP_PROBE, o.nprobe,
+                       npart + 2 * NBLK * g);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, st, (const double*)(npart + 2 * NBLK * g), NBLK,
                        norms + 2 * g);
   }
   std::vector<double> hn(2 * nm);

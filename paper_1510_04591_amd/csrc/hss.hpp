@@ -79,8 +79,9 @@ __global__ void k_probe_sum(const double* __restrict__ part, int K, int nseg, in
                             double* __restrict__ out, int ldo);
 __global__ void k_hss_dmat(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
                            double* __restrict__ dmat, const int64_t* __restrict__ doff);
-__global__ void k_diff_norms(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
-                             double* __restrict__ out2);
+__global__ void k_diff_norms(const double* __restrict__ a, const double* __restrict__ b, int64_t K, int ld, int nc,
+                             double* __restrict__ part);
+__global__ void k_sum_pairs(const double* __restrict__ part, int nblk, double* __restrict__ out2);
 
 adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
                             const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes);

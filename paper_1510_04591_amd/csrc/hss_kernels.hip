@@ -598,7 +598,6 @@ __global__ void __launch_bounds__(256) k_hss_dmat(const HssMerge* __restrict__ m
   }
 }
 
-// out2[0] = sum (a - b)^2, out2[1] = sum b^2 (one block, deterministic order)
 // Probe products of the accuracy check, (W^T Q')^T = Q'^T W, with W K x ldw
 // row-major and 8 probe columns c0..c0+7 per pass: one column j of Q' per
 // lane, the row range split into nseg segments (one per workgroup row) whose
@@ -677,11 +676,16 @@ __global__ void k_probe_sum(const double* __restrict__ part, int K, int nseg, in
   }
 }
 
-__global__ void __launch_bounds__(1024) k_diff_norms(const double* __restrict__ a, const double* __restrict__ b,
-                                                     int64_t n, double* __restrict__ out2) {
-  __shared__ double s0[1024], s1[1024];
+// Partial sums of the check norms over rows of a K x ld row-major pair,
+// columns < nc: part[2 blk] = sum (a - b)^2, part[2 blk + 1] = sum b^2 over
+// the block's rows (fixed order); k_sum_pairs adds the blocks' pairs.
+__global__ void __launch_bounds__(256) k_diff_norms(const double* __restrict__ a, const double* __restrict__ b,
+                                                    int64_t K, int ld, int nc, double* __restrict__ part) {
+  __shared__ double s0[256], s1[256];
   double x0 = 0.0, x1 = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  const int64_t n = K * nc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = (e / nc) * ld + (e % nc);
     const double dd = a[i] - b[i];
     x0 += dd * dd;
     x1 += b[i] * b[i];
@@ -697,7 +701,18 @@ __global__ void __launch_bounds__(1024) k_diff_norms(const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out2[0] = s0[0];
-    out2[1] = s1[0];
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
   }
+}
+
+__global__ void k_sum_pairs(const double* __restrict__ part, int nblk, double* __restrict__ out2) {
+  if (threadIdx.x != 0) return;
+  double x0 = 0.0, x1 = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    x0 += part[2 * i];
+    x1 += part[2 * i + 1];
+  }
+  out2[0] = x0;
+  out2[1] = x1;
 }

@@ -123,4 +123,5 @@ __global__ void k_cauchy(const MergeDev* __restrict__ merges, const int32_t* __r
 
 __global__ void k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs);
 __global__ void k_gemm_f64_n64(const GemmProb* __restrict__ probs, int nprobs);
+__global__ void k_gemm_f64_n96(const GemmProb* __restrict__ probs, int nprobs);
 __global__ void k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs);

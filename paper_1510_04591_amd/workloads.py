@@ -101,15 +101,45 @@ def spectrum(kind, N, seed=5):
     return lam, w / np.linalg.norm(w)
 
 
-def prescribed_tridiagonal(kind, N, seed=5):
+def jacobi_from_spectrum(lam, w):
+    """Tridiagonal (diag, |offdiag|) with eigenvalues lam whose eigenvector
+    matrix has first row w (unit vector): Lanczos on diag(lam) from w, by
+    the O(n^2) Givens reconstruction in jacobi_gen.c (built next to this
+    file by build.build_gen)."""
+    import ctypes
+    import os
+    lib_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libadcgen.so")
+    if not os.path.exists(lib_path):
+        from . import build as _build
+        _build.build_gen(verbose=False)
+    L = ctypes.CDLL(lib_path)
+    P = ctypes.POINTER(ctypes.c_double)
+    L.adc_gen_jacobi.argtypes = [ctypes.c_int, P, P, P, P]
+    L.adc_gen_jacobi.restype = ctypes.c_int
+    lam = np.ascontiguousarray(lam, np.float64)
+    w = np.ascontiguousarray(w, np.float64)
+    n = len(lam)
+    a = np.zeros(n)
+    b = np.zeros(max(n - 1, 0))
+    st = L.adc_gen_jacobi(n, lam.ctypes.data_as(P), w.ctypes.data_as(P), a.ctypes.data_as(P),
+                          b.ctypes.data_as(P) if n > 1 else None)
+    if st != 0:
+        raise MemoryError("adc_gen_jacobi")
+    return a, b
+
+
+def prescribed_tridiagonal(kind, N, seed=5, method="givens"):
     """Tridiagonal matrix with the spectrum `spectrum(kind, N, seed)`: the
     Jacobi matrix of the weights w_i^2 at the nodes lam_i, i.e. Lanczos on
-    diag(lam) started from w, computed stably as the Householder
-    tridiagonalization of H diag(lam) H with H the reflector taking e_1 to w
-    (the first column of the reduction's basis stays e_1).  Off-diagonals are
+    diag(lam) started from w.  method "givens": the O(N^2) reconstruction of
+    jacobi_from_spectrum; "householder": the Householder tridiagonalization
+    (scipy, O(N^3)) of H diag(lam) H with H the reflector taking e_1 to w (the
+    first column of the reduction's basis stays e_1).  Off-diagonals are
     returned as absolute values (a diagonal sign similarity)."""
-    from scipy.linalg import hessenberg
     lam, w = spectrum(kind, N, seed)
+    if method == "givens":
+        return jacobi_from_spectrum(lam, w)
+    from scipy.linalg import hessenberg
     u = w.copy()
     u[0] -= 1.0 if w[0] < 0 else -1.0  # u = w + sign(w_0) e_1: H e_1 = -sign(w_0) w
     u /= np.linalg.norm(u)

@@ -155,3 +155,13 @@ def test_prescribed_spectrum_generator(kind):
     ev = eigh_tridiagonal(a, b, eigvals_only=True)
     assert np.max(np.abs(ev - np.sort(lam))) <= 1e-13
     assert np.all(b > 0)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "geometric"])
+def test_givens_generator_matches_householder(kind):
+    """The O(n^2) reconstruction and the Householder tridiagonalization
+    produce the same Jacobi matrix (it is unique for given nodes and weights
+    with positive off-diagonals) where it is well conditioned."""
+    a1, b1 = workloads.prescribed_tridiagonal(kind, 512, method="givens")
+    a2, b2 = workloads.prescribed_tridiagonal(kind, 512, method="householder")
+    assert np.max(np.abs(a1 - a2)) <= 1e-10 and np.max(np.abs(b1 - b2)) <= 1e-10
