@@ -52,7 +52,7 @@ typedef struct adc_hss_s* adc_hss;
 /* How the HSS sample count s = r + p is chosen for one merge.
  * BOUND: r from eq. (bounds) over neighbouring leaf segments (Section 4.1).
  * MLP:   r from the learned rank predictor (adc_mlp_*): per leaf boundary a
- *        prediction y_b of log2 of the ID rank, r = ceil(2^max_b y_b) + 4,
+ *        prediction y_b of log2 of the ID rank, r = ceil(1.25 2^max_b y_b) + 4,
  *        clamped to [8, r_cap]; the BOUND estimate while no model is set.
  *        The adaptive check (opts.check_tol) judges either choice.
  * FIXED: r = opts.fixed_rank. */
@@ -75,7 +75,7 @@ typedef struct adc_opts {
   uint64_t seed;         /* [20151015] seed of the Gaussian sampling matrices  */
   int32_t force_dense;   /* [0] 1: plain DC, never HSS                          */
   int32_t strict;        /* [0] 1: a failed HSS check is ADC_ERR_ACCURACY       */
-  double  check_tol;     /* [1e-12] relative error allowed by the HSS check     */
+  double  check_tol;     /* [1e-13] relative error allowed by the HSS check     */
   int32_t nprobe;        /* [4] Gaussian probe vectors of the HSS check, 1..32  */
   int32_t shift_max;     /* [5] max boundary move of the rank estimate          */
   double  shift_thresh;  /* [1e-10] move a boundary when its distance is below  */

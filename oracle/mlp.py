@@ -175,12 +175,12 @@ def adam_train(theta, X, y, epochs, batch, lr, beta1=0.9, beta2=0.999, eps=1e-8,
     return theta, state, last
 
 
-def predicted_rank(yhat, margin=4, floor=8, cap=100):
+def predicted_rank(yhat, margin=4, floor=8, cap=100, scale=1.25):
     """Rank of a merge from the per-boundary predictions of log2(rank):
-    ceil(2^max) + margin, clamped to [floor, cap]."""
+    ceil(scale 2^max) + margin, clamped to [floor, cap]."""
     if len(yhat) == 0:
         return floor
-    r = int(math.ceil(2.0 ** float(np.max(yhat)))) + margin
+    r = int(math.ceil(scale * 2.0 ** float(np.max(yhat)))) + margin
     return max(floor, min(cap, r))
 
 

@@ -38,7 +38,7 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   o->seed = 20151015ull;
   o->force_dense = 0;
   o->strict = 0;
-  o->check_tol = 1e-12;
+  o->check_tol = 1e-13;
   o->nprobe = 4;
   o->shift_max = 5;
   o->shift_thresh = 1e-10;

@@ -43,6 +43,7 @@ constexpr int LDH = NH + 1;
 // dynamic LDS of k_mlp_train, in floats
 constexpr int LDS_TRAIN = NP + CH * NF + CH + CH + 4 * CH * LDH;
 constexpr int RANK_MARGIN = 4;
+constexpr double RANK_SCALE = 1.25;  // the prediction's rank is scaled up before the margin
 constexpr int RANK_FLOOR = 8;
 
 __device__ __forceinline__ double clg(double x) {
@@ -396,7 +397,7 @@ static adc_status launch_train(adc_ctx c, MlpState* s, int B, const float* X, co
   return ADC_OK;
 }
 
-// Rank of one HSS merge from the predictor: ceil(2^max_b yhat_b) + margin,
+// Rank of one HSS merge from the predictor: ceil(1.25 2^max_b yhat_b) + margin,
 // clamped to [8, r_cap]; r_bound when no model has been initialised.
 int mlp_rank(adc_ctx c, const double* d, const double* gam, const double* mu, int K, const std::vector<int>& bounds,
              const adc_opts& o, int r_bound) {
@@ -418,7 +419,7 @@ int mlp_rank(adc_ctx c, const double* d, const double* gam, const double* mu, in
   float mx = -INFINITY;
   for (float v : h) mx = std::max(mx, v);
   if (!std::isfinite(mx)) return r_bound;
-  const double r = std::ceil(std::exp2(std::min(mx, 7.0f))) + RANK_MARGIN;
+  const double r = std::ceil(RANK_SCALE * std::exp2(std::min(mx, 7.0f))) + RANK_MARGIN;
   return std::max(RANK_FLOOR, std::min(o.r_cap, (int)r));
 }
 

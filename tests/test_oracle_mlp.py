@@ -140,6 +140,6 @@ def test_boundary_targets_and_predicted_rank():
     kc = [0, 4, 9, 1, 3, 2, 2]
     t = mlp.boundary_targets(lo, hi, kr, kc, [0, 2, 4, 6, 8])
     assert np.allclose(t, np.log2([3, 9, 7]))
-    assert mlp.predicted_rank(np.log2([3.0, 9.0, 7.0])) == 13
+    assert mlp.predicted_rank(np.log2([3.0, 9.0, 7.0])) == 16  # ceil(1.25 * 9) + 4
     assert mlp.predicted_rank(np.array([0.0])) == 8
     assert mlp.predicted_rank(np.array([9.0])) == 100
