@@ -31,16 +31,23 @@ sys.path.insert(0, ROOT)
 # kernel and its launches are unchanged (first 16 hex digits of their
 # SHA-256); otherwise the traffic is reported as null.
 TRAFFIC = {
-    "k_gemm_f64": {"bytes_per_launch": 496.8e6,
-                   "sources": {"gemm.hip": "eb160af22ced5169", "hss.hip": "f441330887a72338",
-                               "dc.hip": "b04feee61a3c93c0"}},
-    "k_gemm_f64_n64": {"bytes_per_launch": 478.3e6,
-                       "sources": {"gemm.hip": "eb160af22ced5169", "hss.hip": "f441330887a72338"}},
-    "k_gemm_f64_big": {"bytes_per_launch": 1139.6e6,
-                       "sources": {"gemm.hip": "eb160af22ced5169", "dc.hip": "b04feee61a3c93c0"}},
-    "k_pack_rot": {"bytes_per_launch": 2587.9e6,
-                   "sources": {"merge.hip": "fa8ab74b592da6cf", "dc.hip": "b04feee61a3c93c0"}},
+    "k_gemm_f64_n64": {"bytes_per_launch": 467.1e6,
+                       "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "d193b9f0441b2099"}},
+    "k_gemm_f64": {"bytes_per_launch": 1140.0e6,
+                   "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "d193b9f0441b2099"}},
+    "k_gemm_f64_n96": {"bytes_per_launch": 147.6e6,
+                       "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "d193b9f0441b2099"}},
+    "k_hss_sample": {"bytes_per_launch": 264.3e6,
+                     "sources": {"hss_kernels.hip": "764103e1389605a7", "hss.hip": "d193b9f0441b2099"}},
+    "k_pack_rot": {"bytes_per_launch": 2569.6e6,
+                   "sources": {"merge.hip": "5ccb844d13b5b4bc", "dc.hip": "b04feee61a3c93c0"}},
 }
+# the dense-update GEMM of the dense-DC run (bench.py --mode dense)
+TRAFFIC_DENSE = {
+    "k_gemm_f64_big": {"bytes_per_launch": 31177.4e6,
+                       "sources": {"gemm.hip": "ea8b930235887c5b", "dc.hip": "b04feee61a3c93c0"}},
+}
+
 
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
@@ -167,11 +174,11 @@ def run_batched(torch, adc, ctx, steps, warmup, sequential=True):
     return out
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(kernel, table=None):
     """Bytes per launch of `kernel` from the counter record, or None when a
     source it depends on has changed since the counters were taken."""
     import hashlib
-    rec = TRAFFIC.get(kernel)
+    rec = (TRAFFIC if table is None else table).get(kernel)
     if rec is None:
         return None
     for fn, want in rec["sources"].items():
@@ -354,7 +361,7 @@ def main():
         achieved = kb[dom] / launches / avg_dur / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["traffic"] = recorded_traffic(kn[dom])
+    roof["traffic"] = recorded_traffic(kn[dom], TRAFFIC if head == "hss" else TRAFFIC_DENSE)
     roof["kernel"] = kn[dom]
     roof["launches_per_step"] = launches / len(reps)
     roof["avg_launch_ms"] = 1e3 * avg_dur
