@@ -556,18 +556,51 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
       }
     }
     double* __restrict__ dlast = dst_of(B.rot_j[s0 + t1]);
-    for (int r = tid; r < n; r += bs) {
-      const int bit = (r < n1) ? 1 : 2;
-      double a = (fa & bit) ? sa[r] : 0.0;
+    // rows of the first child, then of the second: which source columns
+    // have support there is fixed per half, so the loads are unconditional
+    // inside the loop and four rows of them are in flight
+    for (int half = 0; half < 2; ++half) {
+      const int bit = half ? 2 : 1;
+      const int r0 = half ? n1 : 0, r1 = half ? n : n1;
+      const bool ha = (fa & bit) != 0;
+      bool hj[CHMAX];
 #pragma unroll
-      for (int u = 0; u < CHMAX; ++u) {
-        if (u < L) {
-          const double b = (fj[u] & bit) ? sj[u][r] : 0.0;
-          di[u][r] = cs[u] * a + sn[u] * b;
-          a = -sn[u] * a + cs[u] * b;
+      for (int u = 0; u < CHMAX; ++u) hj[u] = (u < L) && (fj[u] & bit) != 0;
+      int r = r0 + tid;
+      for (; r + 3 * bs < r1; r += 4 * bs) {
+        double a[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[v] = ha ? sa[r + v * bs] : 0.0;
+#pragma unroll
+        for (int u = 0; u < CHMAX; ++u) {
+          if (u < L) {
+            const double* __restrict__ su = sj[u];
+            double* __restrict__ du = di[u];
+            double b[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b[v] = hj[u] ? su[r + v * bs] : 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              du[r + v * bs] = cs[u] * a[v] + sn[u] * b[v];
+              a[v] = -sn[u] * a[v] + cs[u] * b[v];
+            }
+          }
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dlast[r + v * bs] = a[v];
       }
-      dlast[r] = a;
+      for (; r < r1; r += bs) {
+        double a = ha ? sa[r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < CHMAX; ++u) {
+          if (u < L) {
+            const double b = hj[u] ? sj[u][r] : 0.0;
+            di[u][r] = cs[u] * a + sn[u] * b;
+            a = -sn[u] * a + cs[u] * b;
+          }
+        }
+        dlast[r] = a;
+      }
     }
     return;
   }
