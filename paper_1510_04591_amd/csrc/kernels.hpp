@@ -16,6 +16,7 @@ struct MergeDev {
   int32_t nrot;    // Givens rotations of type-2 deflation
   int32_t k1, k2, k3;  // survivors whose column lives in rows: top only, both, bottom only
   int32_t mode;    // 0 dense update, 1 HSS update (host decision)
+  int32_t dsorted; // 1 when the deflated values are non-decreasing in scan order
   double rho;      // rho after normalising z
   double tol;      // deflation tolerance
   // eigenvector blocks: zo = the children's (block diagonal), zn = the merged

@@ -464,7 +464,14 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
     B.rot_i_of[s0 + B.rot_i[s0 + t]] = t;
     B.rot_j_of[s0 + B.rot_j[s0 + t]] = t;
   }
+  // deflated values in scan order: non-decreasing unless a rotated value
+  // passed a pole deflated between the pair (then the ordering counts)
+  double uns = 0.0;
+  for (int q = tid + 1; q < n - K; q += blockDim.x)
+    if (B.dsort[s0 + B.defl[s0 + q - 1]] > B.dsort[s0 + B.defl[s0 + q]]) uns = 1.0;
+  uns = block_reduce(uns, sh, OpMax());
   if (tid == 0) {
+    M.dsorted = (uns == 0.0) ? 1 : 0;
     M.K = K;
     M.nrot = nrot;
     M.k1 = k1;
@@ -636,6 +643,25 @@ __global__ void __launch_bounds__(256) k_final_order(const MergeDev* __restrict_
   double x = 0.0;
   if (valid) x = isroot ? B.lam[s0 + item] : B.dsort[s0 + B.defl[s0 + q]];
   int cnt = 0;
+  if (M.dsorted) {
+    // sorted deflated values: a root counts those strictly below it (binary
+    // search), a deflated value counts exactly its predecessors
+    if (valid) {
+      if (isroot) {
+        const int32_t* __restrict__ df = B.defl + s0;
+        const double* __restrict__ ds = B.dsort + s0;
+        int lo = 0, hi = D;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (ds[df[mid]] < x) lo = mid + 1;
+          else hi = mid;
+        }
+        cnt = lo;
+      } else {
+        cnt = q;
+      }
+    }
+  } else
   for (int t0 = 0; t0 < D; t0 += 256) {
     const int tq = t0 + threadIdx.x;
     tile[threadIdx.x] = (tq < D) ? B.dsort[s0 + B.defl[s0 + tq]] : 0.0;
