@@ -350,6 +350,13 @@ struct ProbArena {
   GemmProb* h = nullptr;
   GemmProb* d = nullptr;
   size_t cap = 0, used = 0;
+  struct Launch {
+    int cls;      // 0: 64-wide tiles, 1: 96, 2: 128
+    size_t off;   // first problem in the arena
+    int count, tiles;
+    double flops, bytes;
+  };
+  std::vector<Launch> launches;  // recorded in order, issued by flush_probs
 };
 
 static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops, ProbArena& ar) {
@@ -381,21 +388,31 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
       tiles += p.tiles_m * ((p.N + bn - 1) / bn);
     }
     if (ar.used + L.size() > ar.cap) return ADC_ERR_UNSUPPORTED;  // sized by the caller
-    GemmProb* hp = ar.h + ar.used;
-    GemmProb* dp = ar.d + ar.used;
+    std::memcpy(ar.h + ar.used, L.data(), L.size() * sizeof(GemmProb));
+    ar.launches.push_back(ProbArena::Launch{w, ar.used, (int)L.size(), tiles, pf[w], pb[w]});
     ar.used += L.size();
-    std::memcpy(hp, L.data(), L.size() * sizeof(GemmProb));
-    HIP_OK(hipMemcpyAsync(dp, hp, L.size() * sizeof(GemmProb), hipMemcpyHostToDevice, st));
-    c->ktimer.pre(st);
-    if (w == 0)
-      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
-    else if (w == 1)
-      hipLaunchKernelGGL(k_gemm_f64_n96, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
-    else
-      hipLaunchKernelGGL(k_gemm_f64, dim3(tiles), dim3(512), 0, st, (const GemmProb*)dp, (int)L.size());
-    c->ktimer.post(st, w == 0 ? KT_GEMM64 : w == 1 ? KT_GEMM96 : KT_GEMM, pf[w], pb[w]);
-    HIP_OK(hipGetLastError());
   }
+  (void)st;
+  return ADC_OK;
+}
+
+// One upload of every recorded problem list, then the launches back to back.
+static adc_status flush_probs(adc_ctx c, ProbArena& ar) {
+  hipStream_t st = c->stream;
+  if (ar.used == 0) return ADC_OK;
+  HIP_OK(hipMemcpyAsync(ar.d, ar.h, ar.used * sizeof(GemmProb), hipMemcpyHostToDevice, st));
+  for (const auto& l : ar.launches) {
+    const GemmProb* dp = ar.d + l.off;
+    c->ktimer.pre(st);
+    if (l.cls == 0)
+      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
+    else if (l.cls == 1)
+      hipLaunchKernelGGL(k_gemm_f64_n96, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
+    else
+      hipLaunchKernelGGL(k_gemm_f64, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
+    c->ktimer.post(st, l.cls == 0 ? KT_GEMM64 : l.cls == 1 ? KT_GEMM96 : KT_GEMM, l.flops, l.bytes);
+  }
+  HIP_OK(hipGetLastError());
   return ADC_OK;
 }
 
@@ -599,6 +616,7 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
     }
   }
   ADC_TRY(launch_probs(c, probs, flops, ar));
+  ADC_TRY(flush_probs(c, ar));
   // the pinned problem lists are reused by the next run
   HIP_OK(hipStreamSynchronize(st));
   return ADC_OK;
