@@ -138,8 +138,8 @@ void layout_merge(HssBatch::One& m) {
       a += (int64_t)kmax * sp;
       nd.offZh = a;
       a += (int64_t)kmax * sp;
-      nd.offWork = a;
-      a += (l == 0) ? 0 : 2 * (int64_t)cand * sp;
+      nd.offWork = a;  // per side (rows, columns): the block and a working copy
+      a += (l == 0) ? 0 : 4 * (int64_t)cand * sp;
       nd.offSr = ia;
       ia += kmax;
       nd.offSc = ia;
@@ -241,7 +241,9 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   // compression jobs per level
   int Lmax = 0;
   for (auto& m : hb.ms) Lmax = std::max(Lmax, m.L);
-  std::vector<std::vector<NodeJob>> lj(Lmax + 1);
+  // per level: the parents whose children's B blocks are generated first,
+  // then one job per (non-root node, side)
+  std::vector<std::vector<NodeJob>> lj(Lmax + 1), bj(Lmax + 1);
   int ncand_max = 0, sp_max = 0;
   for (int g = 0; g < nm; ++g) {
     const auto& m = hb.ms[g];
@@ -250,14 +252,19 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
       const int first = (1 << l) - 1;
       for (int q = 0; q < (1 << l); ++q) {
         const HssNode& nd = m.nodes[first + q];
-        lj[l].push_back(NodeJob{g, first + q, l == 0 ? 1 : 0});
+        if (!nd.leaf) bj[l].push_back(NodeJob{g, first + q, 0, 0});
+        if (l > 0) {
+          lj[l].push_back(NodeJob{g, first + q, 0, 0});
+          lj[l].push_back(NodeJob{g, first + q, 1, 0});
+        }
         const int cand = nd.leaf ? nd.hi - nd.lo : std::min(2 * m.s, nd.hi - nd.lo);
         if (l > 0) ncand_max = std::max(ncand_max, cand);
       }
     }
   }
-  size_t jbytes = sj.size() * sizeof(SampleJob) + 256 * (Lmax + 2);
+  size_t jbytes = sj.size() * sizeof(SampleJob) + 256 * (2 * Lmax + 3);
   for (auto& v : lj) jbytes += v.size() * sizeof(NodeJob);
+  for (auto& v : bj) jbytes += v.size() * sizeof(NodeJob);
   void* dp;
   ADC_TRY(c->buffer(SLOT_HSS_JOBS, jbytes, &dp));
   char* dj = (char*)dp;
@@ -270,8 +277,9 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
     return o;
   };
   const size_t o_sj = put(sj.data(), sj.size() * sizeof(SampleJob));
-  std::vector<size_t> o_lj(Lmax + 1);
+  std::vector<size_t> o_lj(Lmax + 1), o_bj(Lmax + 1);
   for (int l = 0; l <= Lmax; ++l) o_lj[l] = put(lj[l].data(), lj[l].size() * sizeof(NodeJob));
+  for (int l = 0; l <= Lmax; ++l) o_bj[l] = put(bj[l].data(), bj[l].size() * sizeof(NodeJob));
   HIP_OK(hipMemcpyAsync(dj, hj.data(), off, hipMemcpyHostToDevice, st));
 
   // algorithmic flops of one sampling pass: the off-diagonal-block part of
@@ -310,6 +318,9 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
     attr_set = true;
   }
   for (int l = Lmax; l >= 0; --l) {
+    if (!bj[l].empty())
+      hipLaunchKernelGGL(k_hss_bblocks, dim3((unsigned)bj[l].size()), dim3(256), 0, st, hb.d_ms,
+                         (const NodeJob*)(dj + o_bj[l]));
     if (lj[l].empty()) continue;
     c->ktimer.pre(st);
     hipLaunchKernelGGL(k_hss_compress, dim3((unsigned)lj[l].size()), dim3(1024), (size_t)lds * 8, st, hb.d_ms,

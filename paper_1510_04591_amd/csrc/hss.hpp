@@ -70,8 +70,10 @@ __global__ void k_sample_sum(const double* __restrict__ part, int nseg, int64_t 
 struct NodeJob {
   int32_t merge;
   int32_t node;  // heap index
-  int32_t root;  // 1: only generate the children's B blocks
+  int32_t side;  // compression: 0 row ID (U, Zhat), 1 column ID (V, Yhat)
+  int32_t pad;
 };
+__global__ void k_hss_bblocks(const HssMerge* __restrict__ ms, const NodeJob* __restrict__ jobs);
 __global__ void k_hss_compress(const HssMerge* __restrict__ ms, const NodeJob* __restrict__ jobs, int lds_doubles);
 __global__ void k_probe_qt(const HssMerge* __restrict__ ms, int g, const double* __restrict__ W, int ldw, int c0,
                            int nc, int nseg, double* __restrict__ part);

@@ -12,12 +12,15 @@
 //                  16 x 4 operand fragment of v_mfma_f64_16x16x4f64 is generated
 //                  in registers from the generators (eq. Ev-Q, differences by
 //                  eq. d-lambda), Omega tiles are staged in LDS.
-// k_hss_compress   one workgroup per tree node and level: the compressed block
-//                  row Phi_i and column Theta_i (leaves from the samples,
-//                  parents from the children as in Algorithm 2), their
-//                  interpolative decompositions by column-pivoted Householder
-//                  QR truncated at |R_kk| <= tol |R_11|, the generators U_i,
-//                  V_i, B of the children, and Yhat_i, Zhat_i.
+// k_hss_bblocks    the B blocks of a parent's children from the generators
+//                  (one workgroup per parent, before the parent's level).
+// k_hss_compress   one workgroup per tree node, level and side (row ID and
+//                  column ID run side by side): the compressed block row
+//                  Phi_i or column Theta_i (leaves from the samples, parents
+//                  from the children as in Algorithm 2), its interpolative
+//                  decomposition by column-pivoted Householder QR truncated
+//                  at |R_kk| <= tol |R_11|, the generator U_i or V_i, and
+//                  Zhat_i or Yhat_i.
 // k_hss_dmat       the leaf diagonal blocks D_i = A(t_i, t_i) for Algorithm 3.
 #include "hss.hpp"
 
@@ -474,31 +477,12 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
   double* ar = M.arena;
   int* ia = M.iarena;
 
-  // B blocks of the children: B_{i1} = A(skel_r(i1), skel_c(i2)), B_{i2} likewise
-  if (!nd.leaf) {
-    HssNode& a = nodes[2 * jb.node + 1];
-    HssNode& b = nodes[2 * jb.node + 2];
-    const int* sra = ia + a.offSr;
-    const int* sca = ia + a.offSc;
-    const int* srb = ia + b.offSr;
-    const int* scb = ia + b.offSc;
-    double* Ba = ar + a.offB;
-    double* Bb = ar + b.offB;
-    for (int e = tid; e < a.kr * b.kc; e += blockDim.x) {
-      const int r = e % a.kr, q = e / a.kr;
-      Ba[e] = gen_entry(M, sra[r], scb[q]);
-    }
-    for (int e = tid; e < b.kr * a.kc; e += blockDim.x) {
-      const int r = e % b.kr, q = e / b.kr;
-      Bb[e] = gen_entry(M, srb[r], sca[q]);
-    }
-    __syncthreads();
-  }
-  if (jb.root) return;
-
-  for (int side = 0; side < 2; ++side) {  // 0: rows (Phi, U), 1: columns (Theta, V)
-    // candidates and the compressed block (cand x sp, row-major) in the work area
-    double* W0 = ar + nd.offWork;
+  {
+    const int side = jb.side;  // 0: rows (Phi, U), 1: columns (Theta, V)
+    // candidates and the compressed block (cand x sp, row-major) in this
+    // side's half of the work area
+    const int cand_alloc = nd.leaf ? (nd.hi - nd.lo) : min(2 * s, nd.hi - nd.lo);
+    double* W0 = ar + nd.offWork + (int64_t)side * 2 * cand_alloc * sp;
     int nc;
     if (nd.leaf) {
       nc = nd.hi - nd.lo;
@@ -562,25 +546,64 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     __syncthreads();
   }
 
-  // Yhat_i = V_i^T Om_c and Zhat_i = U_i^T Om_r with Om = Omega(t_i) for a
-  // leaf, the children's stacked Yhat / Zhat for a parent.
-  const int kr = nd.kr, kc = nd.kc, nr = nd.nr, ncc = nd.nc;
-  const double* U = ar + nd.offU;  // nr x kr
-  const double* V = ar + nd.offV;  // ncc x kc
-  double* Yh = ar + nd.offYh;
-  double* Zh = ar + nd.offZh;
+  // Yhat_i = V_i^T Om_c (the column side) and Zhat_i = U_i^T Om_r (the row
+  // side) with Om = Omega(t_i) for a leaf, the children's stacked Yhat / Zhat
+  // for a parent.  Each side reads only its own ID's results.
   // U^T(j, c) = U[c + j nr]: row stride nr, column stride 1
-  if (nd.leaf) {
-    const double* Om = M.omega + (int64_t)nd.lo * sp;
-    block_small_gemm(Yh, sp, nullptr, 0, 1.0, V, ncc, 1, Om, sp, kc, ncc, s, dyn, lds_doubles);
-    block_small_gemm(Zh, sp, nullptr, 0, 1.0, U, nr, 1, Om, sp, kr, nr, s, dyn, lds_doubles);
+  if (jb.side == 1) {
+    const int kc = nd.kc, ncc = nd.nc;
+    const double* V = ar + nd.offV;  // ncc x kc
+    double* Yh = ar + nd.offYh;
+    if (nd.leaf) {
+      const double* Om = M.omega + (int64_t)nd.lo * sp;
+      block_small_gemm(Yh, sp, nullptr, 0, 1.0, V, ncc, 1, Om, sp, kc, ncc, s, dyn, lds_doubles);
+    } else {
+      const HssNode& a = nodes[2 * jb.node + 1];
+      const HssNode& b = nodes[2 * jb.node + 2];
+      block_small_gemm(Yh, sp, nullptr, 0, 1.0, V, ncc, 1, ar + a.offYh, sp, kc, a.kc, s, dyn, lds_doubles);
+      block_small_gemm(Yh, sp, Yh, sp, 1.0, V + a.kc, ncc, 1, ar + b.offYh, sp, kc, b.kc, s, dyn, lds_doubles);
+    }
   } else {
-    const HssNode& a = nodes[2 * jb.node + 1];
-    const HssNode& b = nodes[2 * jb.node + 2];
-    block_small_gemm(Yh, sp, nullptr, 0, 1.0, V, ncc, 1, ar + a.offYh, sp, kc, a.kc, s, dyn, lds_doubles);
-    block_small_gemm(Yh, sp, Yh, sp, 1.0, V + a.kc, ncc, 1, ar + b.offYh, sp, kc, b.kc, s, dyn, lds_doubles);
-    block_small_gemm(Zh, sp, nullptr, 0, 1.0, U, nr, 1, ar + a.offZh, sp, kr, a.kr, s, dyn, lds_doubles);
-    block_small_gemm(Zh, sp, Zh, sp, 1.0, U + a.kr, nr, 1, ar + b.offZh, sp, kr, b.kr, s, dyn, lds_doubles);
+    const int kr = nd.kr, nr = nd.nr;
+    const double* U = ar + nd.offU;  // nr x kr
+    double* Zh = ar + nd.offZh;
+    if (nd.leaf) {
+      const double* Om = M.omega + (int64_t)nd.lo * sp;
+      block_small_gemm(Zh, sp, nullptr, 0, 1.0, U, nr, 1, Om, sp, kr, nr, s, dyn, lds_doubles);
+    } else {
+      const HssNode& a = nodes[2 * jb.node + 1];
+      const HssNode& b = nodes[2 * jb.node + 2];
+      block_small_gemm(Zh, sp, nullptr, 0, 1.0, U, nr, 1, ar + a.offZh, sp, kr, a.kr, s, dyn, lds_doubles);
+      block_small_gemm(Zh, sp, Zh, sp, 1.0, U + a.kr, nr, 1, ar + b.offZh, sp, kr, b.kr, s, dyn, lds_doubles);
+    }
+  }
+}
+
+// B blocks of a parent's children from the generators: B_{i1} =
+// A(skel_r(i1), skel_c(i2)) and B_{i2} = A(skel_r(i2), skel_c(i1)) (one
+// workgroup per parent, run before the parent's level is compressed).
+__global__ void __launch_bounds__(256) k_hss_bblocks(const HssMerge* __restrict__ ms,
+                                                     const NodeJob* __restrict__ jobs) {
+  const NodeJob jb = jobs[blockIdx.x];
+  const HssMerge& M = ms[jb.merge];
+  const HssNode* nodes = M.nodes;
+  const HssNode& a = nodes[2 * jb.node + 1];
+  const HssNode& b = nodes[2 * jb.node + 2];
+  const int* ia = M.iarena;
+  double* ar = M.arena;
+  const int* sra = ia + a.offSr;
+  const int* sca = ia + a.offSc;
+  const int* srb = ia + b.offSr;
+  const int* scb = ia + b.offSc;
+  double* Ba = ar + a.offB;
+  double* Bb = ar + b.offB;
+  for (int e = threadIdx.x; e < a.kr * b.kc; e += blockDim.x) {
+    const int r = e % a.kr, q = e / a.kr;
+    Ba[e] = gen_entry(M, sra[r], scb[q]);
+  }
+  for (int e = threadIdx.x; e < b.kr * a.kc; e += blockDim.x) {
+    const int r = e % b.kr, q = e / b.kr;
+    Bb[e] = gen_entry(M, srb[r], sca[q]);
   }
 }
 
