@@ -1,8 +1,9 @@
 """Benchmark: full symmetric tridiagonal eigendecomposition on one MI355X.
 
 Workload (the headline configuration): N = 32768 tridiagonal Toeplitz
-(diagonal 2, off-diagonal 1), DC leaf 32, randomized HSS update at the top
-three merge levels (HSS leaf 128, p = 10, adaptive oversampling), compared
+(diagonal 2, off-diagonal 1), DC leaf 32, randomized HSS update at the
+merges whose dense update would cost at least 1e11 flops (the top three
+levels here; HSS leaf 128, p = 16, adaptive oversampling), compared
 with the plain dense FP64 MFMA update on the same GPU.
 
 A step is one complete eigendecomposition (all eigenvalues and eigenvectors)
@@ -70,6 +71,9 @@ def parse():
     p.add_argument("--batched-only", action="store_true")
     p.add_argument("--c5", action="store_true",
                    help="only the learned rank predictor at N = 32768 on prescribed spectra (trains first)")
+    p.add_argument("--families", action="store_true",
+                   help="only the five matrix families of Example 3 at 5k..25k: HSS-ADC against dense DC")
+    p.add_argument("--family-sizes", default="5000,10000,15000,20000,25000")
     return p.parse_args()
 
 
@@ -208,7 +212,7 @@ def run_c5(torch, adc, ctx, steps):
         w = torch.empty(n, dtype=torch.float64, device="cuda")
         Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
         for leaf in ((32, 64, 128) if n <= 8192 else (128,)):
-            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=max(2 * leaf, 256 if n > 8192 else 0), hss_levels=-1)
+            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=max(2 * leaf, 256 if n > 8192 else 0), hss_levels=-1, hss_min_flops=0)
             cap = 1 << 17
             X = torch.empty((cap, 16), dtype=torch.float32, device="cuda")
             y = torch.empty(cap, dtype=torch.float32, device="cuda")
@@ -239,7 +243,7 @@ def run_c5(torch, adc, ctx, steps):
         ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
         res = {}
         for name, mode in (("bound", adc.ADC_RANK_BOUND), ("mlp", adc.ADC_RANK_MLP)):
-            o = adc.opts(dc_leaf=32, hss_leaf=128, hss_min_k=2048, hss_levels=-1, rank_mode=mode)
+            o = adc.opts(dc_leaf=32, hss_leaf=128, hss_min_k=2048, hss_levels=-1, hss_min_flops=0, rank_mode=mode)
             times = []
             for it in range(steps + 1):
                 rep = adc.adc_report()
@@ -259,6 +263,67 @@ def run_c5(torch, adc, ctx, steps):
         out["spectra"][kind] = res
         print(f"# C5 {kind}: bound {res['bound']['s']:.4f} s (s={res['bound']['samples']}), "
               f"mlp {res['mlp']['s']:.4f} s (s={res['mlp']['samples']})", flush=True)
+    return out
+
+
+FAMILIES = ("clement", "legendre", "laguerre", "hermite", "toeplitz")
+
+
+def family_matrix(kind, n):
+    """Order-n matrix of one of the five families of Example 3 and its exact
+    eigenvalues where a closed form is known (else None)."""
+    from paper_1510_04591_amd import workloads
+    if kind == "clement":
+        a, b = workloads.clement(n - 1)
+        return a, b, np.arange(-(n - 1), n, 2, dtype=np.float64)
+    if kind == "toeplitz":
+        a, b = workloads.toeplitz(n)
+        return a, b, np.sort(2 + 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    a, b = getattr(workloads, kind)(n)
+    return a, b, None
+
+
+def run_families(torch, adc, ctx, sizes, steps):
+    """Example 3 / Table 5 setting: each family at each size solved with the
+    headline HSS options and with the dense update; median seconds of
+    `steps` timed solves after one untimed one, residual and orthogonality of
+    the HSS result, eigenvalue error where the spectrum has a closed form."""
+    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=1e11, oversample=16)
+    dense_opts = adc.opts(dc_leaf=32, force_dense=1)
+    out = {}
+    for kind in FAMILIES:
+        out[kind] = {}
+        for n in sizes:
+            a, b, exact = family_matrix(kind, n)
+            ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+            w = torch.empty(n, dtype=torch.float64, device="cuda")
+            Zt = torch.empty((n, n), dtype=torch.float64, device="cuda")
+            row = {}
+            for name, o in (("dense", dense_opts), ("hss", hss_opts)):
+                times = []
+                for it in range(steps + 1):
+                    rep = adc.adc_report()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = adc.adc_stedc(ctx.h, n, ad, bd, w, Zt, n, None, 0, o, rep)
+                    torch.cuda.synchronize()
+                    if st != adc.ADC_OK:
+                        raise adc.AdcError(st, "adc_stedc", rep.as_dict())
+                    if it > 0:
+                        times.append(time.perf_counter() - t0)
+                row[name] = float(np.median(times))
+            r = rep.as_dict()
+            v = validate(torch, a, b, w, Zt.t(), exact if exact is not None else w.cpu().numpy())
+            if exact is None:
+                v.pop("eig_err_rel")
+            row.update(speedup=row["dense"] / row["hss"], hss_merges=r["hss_merges"], samples=r["samples"],
+                       max_rank=r["max_rank"], fallbacks=r["hss_fallbacks"], K_top=r["K_per_level"][0],
+                       validation=v)
+            out[kind][str(n)] = row
+            print(f"# {kind} n={n}: dense {row['dense']:.4f} s, HSS {row['hss']:.4f} s, "
+                  f"x{row['speedup']:.2f}, K top {row['K_top']}, rank {row['max_rank']}, "
+                  f"resid {v['resid']:.1e} orth {v['orth']:.1e}", flush=True)
+            del Zt
     return out
 
 
@@ -285,6 +350,12 @@ def main():
         print(json.dumps({"c5": run_c5(torch, adc, ctx, args.steps)}), flush=True)
         ctx.close()
         return
+    if args.families:
+        ctx = adc.Context(0)
+        sizes = [int(x) for x in args.family_sizes.split(",")]
+        print(json.dumps({"families": run_families(torch, adc, ctx, sizes, max(args.steps, 1))}), flush=True)
+        ctx.close()
+        return
     if args.batched_only:
         ctx = adc.Context(0)
         print(json.dumps({"batched": run_batched(torch, adc, ctx, args.steps, args.warmup)}), flush=True)
@@ -300,7 +371,7 @@ def main():
     ctx = adc.Context(0)
     w = torch.empty(N, dtype=torch.float64, device="cuda")
     Zt = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=3, hss_min_k=2048, oversample=10)
+    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=1e11, oversample=16)
     dense_opts = adc.opts(dc_leaf=32, force_dense=1)
 
     def run(o, steps, warm):
@@ -385,7 +456,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS top 3 levels, HSS leaf 128, p=10",
+        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=1e11 flops, HSS leaf 128, p=16",
                    "update": head, "n": N, "K_per_level": r0["K_per_level"],
                    "hss_per_level": r0["hss_per_level"], "max_rank": r0["max_rank"],
                    "samples": r0["samples"], "retries": r0["retries"], "fallbacks": r0["hss_fallbacks"]},

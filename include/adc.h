@@ -63,11 +63,14 @@ typedef struct adc_opts {
   int32_t dc_leaf;       /* [32] DC leaf size m (Algorithm 1); 2..64            */
   int32_t hss_min_k;     /* [2048] HSS update only if the deflated size K >= this
                             (Section 4.3 uses "larger than 2000")             */
-  int32_t hss_levels;    /* [3] only the top hss_levels merge levels may use HSS;
-                            <0 means every level                              */
+  int32_t hss_levels;    /* [-1] only the top hss_levels merge levels may use
+                            HSS; <0 means every level                         */
   int32_t hss_leaf;      /* [128] HSS leaf size (rows per leaf node)          */
   double  id_tol;        /* [1e-14] ID truncation |R_kk| <= id_tol |R_11|       */
-  int32_t oversample;    /* [10] p (Section 3: "p = 10")                       */
+  int32_t oversample;    /* [16] p, samples beyond the rank estimate (Section 3
+                            takes 10; 16 keeps the check at 1e-13 from
+                            failing at the top merges, whose retries cost
+                            more than the extra columns)                  */
   int32_t rank_mode;     /* [ADC_RANK_BOUND] adc_rank_mode                      */
   int32_t fixed_rank;    /* [0] r for ADC_RANK_FIXED                            */
   int32_t max_retries;   /* [2] sample doublings before the dense fallback     */
@@ -81,6 +84,14 @@ typedef struct adc_opts {
   double  shift_thresh;  /* [1e-10] move a boundary when its distance is below  */
   int32_t r_cap;         /* [100] cap of the estimated rank                     */
   double  rank_eps;      /* [1e-16] epsilon of eq. (bounds)                     */
+  double  hss_min_flops; /* [1e11] HSS update only if the merge's dense update,
+                            2 n1 K (k1+k2) + 2 n2 K (k2+k3) flops with the
+                            column classes of the deflated Q (Section 2.1),
+                            reaches this (about 2 ms of FP64 MFMA GEMM; the
+                            HSS route's fixed costs outweigh smaller
+                            updates); once one merge of a level qualifies,
+                            merges of the level reaching a quarter of it
+                            (and hss_min_k) join; 0 disables the test     */
 } adc_opts;
 
 /* Report of one solve (host struct, optional). */

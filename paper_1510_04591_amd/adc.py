@@ -34,7 +34,7 @@ class adc_opts(C.Structure):
         ("max_iter", C.c_int32), ("seed", C.c_uint64), ("force_dense", C.c_int32),
         ("strict", C.c_int32), ("check_tol", C.c_double), ("nprobe", C.c_int32),
         ("shift_max", C.c_int32), ("shift_thresh", C.c_double), ("r_cap", C.c_int32),
-        ("rank_eps", C.c_double),
+        ("rank_eps", C.c_double), ("hss_min_flops", C.c_double),
     ]
 
 

@@ -27,10 +27,10 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->dc_leaf = 32;
   o->hss_min_k = 2048;
-  o->hss_levels = 3;
+  o->hss_levels = -1;
   o->hss_leaf = 128;
   o->id_tol = 1e-14;
-  o->oversample = 10;
+  o->oversample = 16;
   o->rank_mode = ADC_RANK_BOUND;
   o->fixed_rank = 0;
   o->max_retries = 2;
@@ -44,6 +44,7 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   o->shift_thresh = 1e-10;
   o->r_cap = 100;
   o->rank_eps = 1e-16;
+  o->hss_min_flops = 1e11;
   return ADC_OK;
 }
 
@@ -51,7 +52,9 @@ adc_status validate_opts_ext(const adc_opts& o) {
   if (o.dc_leaf < 2 || o.dc_leaf > 64) return ADC_ERR_ARG;
   if (o.hss_leaf < 16 || o.hss_leaf > 256) return ADC_ERR_ARG;
   if (!(o.id_tol >= 0.0) || o.oversample < 0 || o.max_retries < 0 || o.max_iter < 1) return ADC_ERR_ARG;
-  if (o.nprobe < 1 || o.nprobe > 32 || o.r_cap < 1 || !(o.rank_eps > 0.0)) return ADC_ERR_ARG;
+  if (o.nprobe < 1 || o.nprobe > 32 || o.r_cap < 1 || !(o.rank_eps > 0.0) ||
+      !(o.hss_min_flops >= 0.0))
+    return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
   return ADC_OK;
 }

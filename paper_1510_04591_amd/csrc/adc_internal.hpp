@@ -11,6 +11,7 @@ enum Slot {
   SLOT_QC,         // standalone Cauchy matrix
   SLOT_HSS,        // HSS workspace of the solver
   SLOT_HSS2,       // HSS work arrays of the solver (second arena)
+  SLOT_HSS_RETRY,  // HSS workspace of the merges rebuilt with more samples
   SLOT_BATCH,      // batched solver workspace
   SLOT_BATCH_DESC, // batched solver descriptors
   SLOT_MLP,        // MLP scratch

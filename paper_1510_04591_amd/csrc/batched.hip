@@ -594,7 +594,10 @@ extern "C" adc_status adc_stedc_batched(adc_ctx c, int32_t count, const int64_t*
   std::vector<int> solo, batch;
   for (int i = 0; i < count; ++i) {
     if (n[i] == 0) continue;
-    if (hss_possible && n[i] >= o.hss_min_k) solo.push_back(i);
+    // the top merge's dense update is at most 2 n (n1^2 + n2^2) flops
+    const double n1 = (double)(n[i] / 2), n2 = (double)(n[i] - n[i] / 2);
+    const double top_f = 2.0 * n[i] * (n1 * n1 + n2 * n2);
+    if (hss_possible && n[i] >= o.hss_min_k && top_f >= o.hss_min_flops) solo.push_back(i);
     else batch.push_back(i);
   }
   for (int i : solo) {

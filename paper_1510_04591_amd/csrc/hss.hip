@@ -712,50 +712,89 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
   return ADC_OK;
 }
 
+// One attempt for every merge of the batch with its current s: storage,
+// Omega, sampling, compression and (if asked) the accuracy check.
+static adc_status batch_attempt(adc_ctx c, HssBatch& hb, const adc_opts& o, int slot, bool check, adc_report* rep,
+                                double* flops, const std::vector<const double*>* omega_given) {
+  ADC_TRY(batch_alloc(c, hb, slot));
+  ADC_TRY(batch_upload(c, hb));
+  for (size_t g = 0; g < hb.ms.size(); ++g) {
+    auto& m = hb.ms[g];
+    if (omega_given && (*omega_given)[g]) {
+      // caller's K x s row-major Omega into the padded layout
+      HIP_OK(hipMemset2DAsync(m.dev.omega, m.sp * 8, 0, m.sp * 8, m.K, c->stream));
+      HIP_OK(hipMemcpy2DAsync(m.dev.omega, m.sp * 8, (*omega_given)[g], m.s * 8, m.s * 8, m.K,
+                              hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      draw_omega(c, m, o.seed);
+    }
+  }
+  HIP_OK(hipGetLastError());
+  ADC_TRY(batch_construct(c, hb, rep));
+  if (!check) {
+    for (auto& m : hb.ms) m.pass = true;
+    return ADC_OK;
+  }
+  ADC_TRY(batch_check(c, hb, o, flops));
+  c->timer.mark(c->stream, 7);
+  return ADC_OK;
+}
+
+// Double the samples of the failing merges; false when none can grow.
+static bool grow_failing(HssBatch& hb) {
+  bool any = false;
+  for (auto& m : hb.ms) {
+    if (!m.pass && m.s < std::min(m.K, S_MAX)) {
+      m.s = std::min({2 * m.s, m.K, S_MAX});
+      m.sp = (m.s + 31) / 32 * 32;
+      m.retries++;
+      any = true;
+    }
+  }
+  return any;
+}
+
 // Build (construct + check + retries) for a batch whose merges have K, L,
-// bounds, r and stream set.  gens[g] = device generators (d, gam, mu, uh, v).
+// bounds, r and stream set.  Without `rb` a retry rebuilds the whole batch
+// in place.  With `rb`, the merges that pass the first check keep their HSS
+// forms in `hb`; the ones that fail move to `rb` (own storage) and only they
+// are rebuilt with doubled samples; rb_of[g] is the merge's index in `rb`,
+// -1 for the merges that stay in `hb`.
 static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool check, adc_report* rep,
-                              double* flops, const std::vector<const double*>* omega_given) {
+                              double* flops, const std::vector<const double*>* omega_given,
+                              HssBatch* rb = nullptr, std::vector<int>* rb_of = nullptr) {
   for (auto& m : hb.ms) {
     m.s = std::min({m.K, m.r + o.oversample, S_MAX});
     m.s = std::max(m.s, 1);
     m.sp = (m.s + 31) / 32 * 32;
     m.retries = 0;
   }
-  for (int attempt = 0;; ++attempt) {
-    ADC_TRY(batch_alloc(c, hb, SLOT_HSS));
-    ADC_TRY(batch_upload(c, hb));
-    for (size_t g = 0; g < hb.ms.size(); ++g) {
-      auto& m = hb.ms[g];
-      if (omega_given && (*omega_given)[g]) {
-        // caller's K x s row-major Omega into the padded layout
-        HIP_OK(hipMemset2DAsync(m.dev.omega, m.sp * 8, 0, m.sp * 8, m.K, c->stream));
-        HIP_OK(hipMemcpy2DAsync(m.dev.omega, m.sp * 8, (*omega_given)[g], m.s * 8, m.s * 8, m.K,
-                                hipMemcpyDeviceToDevice, c->stream));
-      } else {
-        draw_omega(c, m, o.seed);
+  if (rb_of) rb_of->assign(hb.ms.size(), -1);
+  if (rb) rb->ms.clear();
+  ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, check, rep, flops, omega_given));
+  if (!check) return ADC_OK;
+  for (int attempt = 1; attempt <= o.max_retries; ++attempt) {
+    if (!rb || attempt == 1) {
+      // first retry (or every retry in place): the failing merges of hb
+      if (!grow_failing(hb)) return ADC_OK;
+      if (!rb) {
+        ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, true, rep, flops, omega_given));
+        continue;
       }
-    }
-    HIP_OK(hipGetLastError());
-    ADC_TRY(batch_construct(c, hb, rep));
-    if (!check) {
-      for (auto& m : hb.ms) m.pass = true;
+      for (size_t g = 0; g < hb.ms.size(); ++g) {
+        if (hb.ms[g].pass) continue;
+        (*rb_of)[g] = (int)rb->ms.size();
+        rb->ms.push_back(hb.ms[g]);
+      }
+    } else if (!grow_failing(*rb)) {
       return ADC_OK;
     }
-    ADC_TRY(batch_check(c, hb, o, flops));
-    c->timer.mark(c->stream, 7);
+    ADC_TRY(batch_attempt(c, *rb, o, SLOT_HSS_RETRY, true, rep, flops, nullptr));
     bool all = true;
-    for (auto& m : hb.ms) all = all && m.pass;
-    if (all || attempt >= o.max_retries) return ADC_OK;
-    // double the samples of the failing merges and rebuild the batch
-    for (auto& m : hb.ms) {
-      if (!m.pass && m.s < std::min(m.K, S_MAX)) {
-        m.s = std::min({2 * m.s, m.K, S_MAX});
-        m.sp = (m.s + 31) / 32 * 32;
-        m.retries++;
-      }
-    }
+    for (auto& m : rb->ms) all = all && m.pass;
+    if (all) return ADC_OK;
   }
+  return ADC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -792,12 +831,15 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     m.dev.id_tol = o.id_tol;
     hb.ms.push_back(m);
   }
-  ADC_TRY(batch_build(c, hb, o, true, rep, flops, nullptr));
-  std::vector<ApplyJob> aj;
+  HssBatch rb;
+  std::vector<int> rb_of;
+  ADC_TRY(batch_build(c, hb, o, true, rep, flops, nullptr, &rb, &rb_of));
+  std::vector<ApplyJob> aj, ajr;
   std::vector<int> dense_fb;
   for (size_t t = 0; t < which.size(); ++t) {
     const MergeDev& M = h_m[which[t]];
-    auto& m = hb.ms[t];
+    const bool moved = rb_of[t] >= 0;
+    auto& m = moved ? rb.ms[rb_of[t]] : hb.ms[t];
     if (rep) {
       rep->retries += m.retries;
       rep->max_rank = std::max(rep->max_rank, m.max_rank);
@@ -815,8 +857,9 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
       ADC_TRY(mlp_collect_merge(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, lo, hi, kr, kc));
     }
     if (m.pass) {
-      aj.push_back(ApplyJob{(int)t, B.pk + M.zoff, (int64_t)M.n, M.n, M.zn, M.ldn,
-                            B.posR + M.s0});
+      (moved ? ajr : aj)
+          .push_back(ApplyJob{moved ? rb_of[t] : (int)t, B.pk + M.zoff, (int64_t)M.n, M.n, M.zn, M.ldn,
+                              B.posR + M.s0});
     } else {
       dense_fb.push_back(which[t]);
       if (rep) rep->hss_fallbacks++;
@@ -824,7 +867,8 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
   }
   if (!dense_fb.empty() && o.strict) return ADC_ERR_ACCURACY;
   double fm = 0.0;
-  ADC_TRY(batch_apply(c, hb, aj, &fm));
+  if (!aj.empty()) ADC_TRY(batch_apply(c, hb, aj, &fm));
+  if (!ajr.empty()) ADC_TRY(batch_apply(c, rb, ajr, &fm));
   c->timer.mark(st, 8);
   if (flops) *flops += fm;
   if (rep) {

@@ -43,8 +43,9 @@ def test_status_strings_and_defaults():
     assert adc.status_string(0) == "ADC_OK"
     assert "NOCONV" in adc.status_string(adc.ADC_ERR_NOCONV)
     o = adc.opts()
-    assert (o.dc_leaf, o.hss_min_k, o.hss_leaf, o.oversample, o.r_cap) == (32, 2048, 128, 10, 100)
+    assert (o.dc_leaf, o.hss_min_k, o.hss_leaf, o.oversample, o.r_cap) == (32, 2048, 128, 16, 100)
     assert o.id_tol == 1e-14 and o.rank_eps == 1e-16
+    assert o.hss_levels == -1 and o.hss_min_flops == 1e11
 
 
 def test_product_does_not_use_the_oracle():

@@ -101,7 +101,7 @@ def solve(ctx, a, b, **kw):
 def test_stedc_hss_toeplitz(ctx, N, leaf, minK):
     print(f"stedc hss toeplitz N={N}", flush=True)
     a, b = workloads.toeplitz(N)
-    w, Z, rep = solve(ctx, a, b, hss_leaf=leaf, hss_min_k=minK, hss_levels=-1)
+    w, Z, rep = solve(ctx, a, b, hss_leaf=leaf, hss_min_k=minK, hss_levels=-1, hss_min_flops=0)
     assert rep["hss_merges"] >= 1 and rep["hss_fallbacks"] == 0
     k = np.arange(1, N + 1)
     exact = np.sort(2 + 2 * np.cos(k * np.pi / (N + 1)))
@@ -113,7 +113,28 @@ def test_stedc_hss_toeplitz(ctx, N, leaf, minK):
 def test_stedc_hss_random_matches_oracle(ctx):
     print("stedc hss random", flush=True)
     a, b = workloads.random_uniform(3000, 9)
-    w, Z, rep = solve(ctx, a, b, hss_leaf=32, hss_min_k=16, hss_levels=-1)
+    w, Z, rep = solve(ctx, a, b, hss_leaf=32, hss_min_k=16, hss_levels=-1, hss_min_flops=0)
     w_o, _ = odc.stedc(a, b, leaf=32)
     assert np.max(np.abs(w - w_o)) <= 1e-13 * odc.tnorm1(a, b)
     assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
+
+
+@pytest.mark.parametrize("rank", [4, 48, 64])
+def test_stedc_hss_retries_rebuild_failing_merges(ctx, rank):
+    """Too few samples on purpose (fixed rank, no oversampling): merges that
+    fail the check are rebuilt with doubled samples while the ones that
+    passed keep their first HSS form; the result must still be exact."""
+    print(f"stedc hss retries rank={rank}", flush=True)
+    N = 8192
+    a, b = workloads.toeplitz(N)
+    w, Z, rep = solve(ctx, a, b, hss_leaf=128, hss_min_k=1024, hss_levels=-1, hss_min_flops=0,
+                      rank_mode=adc.ADC_RANK_FIXED, fixed_rank=rank, oversample=0, max_retries=6)
+    print(f"  hss merges {rep['hss_merges']} retries {rep['retries']} samples {rep['samples']}", flush=True)
+    assert rep["hss_merges"] >= 3 and rep["hss_fallbacks"] == 0
+    if rank == 4:
+        assert rep["retries"] >= rep["hss_merges"]
+    k = np.arange(1, N + 1)
+    exact = np.sort(2 + 2 * np.cos(k * np.pi / (N + 1)))
+    assert np.max(np.abs(w - exact)) <= 1e-13 * 4
+    assert odc.residual(a, b, w, Z) <= 1e-13
+    assert odc.orthogonality(Z) <= 1e-12

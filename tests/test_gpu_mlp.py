@@ -116,7 +116,7 @@ def test_collection_rows_match_oracle_features(ctx):
     """Collected rows are finite, scale-free features and targets log2 of
     ranks >= 1, and the solve that produced them stays exact."""
     a, b = workloads.toeplitz(1024)
-    o = adc.opts(dc_leaf=32, hss_leaf=64, hss_min_k=128, hss_levels=-1)
+    o = adc.opts(dc_leaf=32, hss_leaf=64, hss_min_k=128, hss_levels=-1, hss_min_flops=0)
     X, y, w, Z = collect(ctx, a, b, o)
     assert X.shape[0] > 0
     yy = y.cpu().numpy()
@@ -142,7 +142,7 @@ def trained_model(ctx):
     for a, b in mats:
         print(f"collect N={len(a)}", flush=True)
         for leaf in (32, 64, 128):
-            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=2 * leaf, hss_levels=-1)
+            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=2 * leaf, hss_levels=-1, hss_min_flops=0)
             X, y, _, _ = collect(ctx, a, b, o)
             Xs.append(X)
             ys.append(y)
@@ -180,7 +180,7 @@ def test_gain_over_the_bound(ctx):
         res = {}
         for mode in (adc.ADC_RANK_BOUND, adc.ADC_RANK_MLP):
             w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), dc_leaf=32, hss_leaf=128, hss_min_k=2048,
-                                             hss_levels=-1, rank_mode=mode)
+                                             hss_levels=-1, hss_min_flops=0, rank_mode=mode)
             torch.cuda.synchronize()
             w, Z = w.cpu().numpy(), Z.cpu().numpy()
             tn = odc.tnorm1(a, b)
