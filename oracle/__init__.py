@@ -23,4 +23,6 @@ hss       interpolative decomposition, the randomized HSS construction of
 sturm     Sturm-sequence eigenvalue counts of a tridiagonal matrix (textbook),
           used to check single eigenvalues at any size.
 mlp       fp64 forward/backward/Adam of the 16-64-64-1 rank-predictor MLP.
+fmm       fast sampling for Algorithm 2: a one-dimensional Chebyshev FMM for
+          the off-diagonal Cauchy sums, and the same samples by definition.
 """
