@@ -58,6 +58,21 @@ typedef struct adc_hss_s* adc_hss;
  * FIXED: r = opts.fixed_rank. */
 typedef enum adc_rank_mode { ADC_RANK_BOUND = 0, ADC_RANK_MLP = 1, ADC_RANK_FIXED = 2 } adc_rank_mode;
 
+/* Sampling of Algorithm 2, i.e. Phi = the block rows of the Cauchy-like matrix
+ * without their diagonal blocks times Omega, and Theta likewise for the
+ * block columns.
+ * DIRECT: every entry generated from (d, gam, mu, uh, v) and summed, O(K^2 s).
+ * FMM:    the off-diagonal Cauchy sums by a one-dimensional fast multipole
+ *         method (the acceleration the paper names for this step, Sections 1,
+ *         3 and 5): Chebyshev interpolation with fmm_order points per node of
+ *         the HSS tree, nodes in coordinates local to their first pole, two
+ *         nodes well separated when their gap (eq. d-lambda) is at least the
+ *         larger width; pairs of leaves that are not are summed entry by
+ *         entry with the differences of eq. (d-lambda).  O(K s (P + m)) for
+ *         well-spread spectra; agrees with DIRECT to about 1e-15 relative at
+ *         fmm_order 20. */
+typedef enum adc_sample_mode { ADC_SAMPLE_DIRECT = 0, ADC_SAMPLE_FMM = 1 } adc_sample_mode;
+
 /* Options.  adc_opts_default() fills the values in brackets. */
 typedef struct adc_opts {
   int32_t dc_leaf;       /* [32] DC leaf size m (Algorithm 1); 2..64            */
@@ -92,6 +107,10 @@ typedef struct adc_opts {
                             updates); once one merge of a level qualifies,
                             merges of the level reaching a quarter of it
                             (and hss_min_k) join; 0 disables the test     */
+  int32_t sample_mode;   /* [ADC_SAMPLE_FMM] adc_sample_mode: how Algorithm 2
+                            takes its samples                                */
+  int32_t fmm_order;     /* [20] Chebyshev points per tree node of the fast
+                            sampling, 4..32                                  */
 } adc_opts;
 
 /* Report of one solve (host struct, optional). */
@@ -125,13 +144,15 @@ typedef struct adc_report {
    * stream: 0 k_gemm_f64 (128 x 128 FP64 MFMA GEMM tiles), 1 k_gemm_f64_n64
    * (128 x 64), 2 k_hss_sample, 3 k_pack_rot, 4 k_secular, 5 k_hss_compress,
    * 6 k_gemm_f64_big (256 x 128, the dense update), 7 k_gemm_f64_n96
-   * (128 x 96).
+   * (128 x 96), 8 k_fmm_leaf (fast sampling: near field and local
+   * expansions), 9 k_fmm_m2l (fast sampling: far-field translations),
+   * 10-11 unused.
    * Times in seconds; flops and bytes are the algorithmic counts of the
    * launches (operands read once, results written once). */
-  double  kern_time[8];
-  double  kern_flops[8];
-  double  kern_bytes[8];
-  int32_t kern_launches[8];
+  double  kern_time[12];
+  double  kern_flops[12];
+  double  kern_bytes[12];
+  int32_t kern_launches[12];
 } adc_report;
 
 /* ---------------------------------------------------------------- context */
@@ -211,6 +232,18 @@ adc_status adc_cauchy_gemm(adc_ctx ctx, int64_t P, int64_t K, const double* d, c
 adc_status adc_hss_build(adc_ctx ctx, int64_t K, const double* d, const double* gam,
                          const double* mu, const double* uh, const double* v,
                          const double* omega, int32_t s, const adc_opts* opts, adc_hss* out);
+
+/* The samples of Algorithm 2 alone: phi = Phi and theta = Theta (K x s,
+ * row-major, device), row i of Phi being block row t(i) of the Cauchy-like
+ * matrix with generators (d, gam, mu, uh, v) without its diagonal block,
+ * times omega (K x s row-major, device), and Theta the same for block
+ * columns.  The leaves are those of adc_hss_build for opts->hss_leaf
+ * (balanced, L = ceil(log2(K / hss_leaf)) levels, at least one); the method
+ * is opts->sample_mode with opts->fmm_order points per node.  1 <= s <= 256.
+ * Blocking. */
+adc_status adc_hss_sample(adc_ctx ctx, int64_t K, const double* d, const double* gam, const double* mu,
+                          const double* uh, const double* v, const double* omega, int32_t s,
+                          const adc_opts* opts, double* phi, double* theta);
 
 /* Y[P x K] = X[P x K] * H (Algorithm 3, HSS times a general matrix from the
  * right).  Y must not overlap X.  Asynchronous. */

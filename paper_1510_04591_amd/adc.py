@@ -22,6 +22,8 @@ ADC_ERR_UNSUPPORTED = 6
 ADC_RANK_BOUND = 0
 ADC_RANK_MLP = 1
 ADC_RANK_FIXED = 2
+ADC_SAMPLE_DIRECT = 0
+ADC_SAMPLE_FMM = 1
 
 MLP_NPARAM = 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -34,7 +36,8 @@ class adc_opts(C.Structure):
         ("max_iter", C.c_int32), ("seed", C.c_uint64), ("force_dense", C.c_int32),
         ("strict", C.c_int32), ("check_tol", C.c_double), ("nprobe", C.c_int32),
         ("shift_max", C.c_int32), ("shift_thresh", C.c_double), ("r_cap", C.c_int32),
-        ("rank_eps", C.c_double), ("hss_min_flops", C.c_double),
+        ("rank_eps", C.c_double), ("hss_min_flops", C.c_double), ("sample_mode", C.c_int32),
+        ("fmm_order", C.c_int32),
     ]
 
 
@@ -47,12 +50,12 @@ class adc_report(C.Structure):
         ("t_phase", C.c_double * 12), ("phase_flops", C.c_double * 12), ("phase_bytes", C.c_double * 12),
         ("phase_launches", C.c_int32 * 12), ("flops_model", C.c_double), ("bytes_model", C.c_double),
         ("check_err_max", C.c_double),
-        ("kern_time", C.c_double * 8), ("kern_flops", C.c_double * 8), ("kern_bytes", C.c_double * 8),
-        ("kern_launches", C.c_int32 * 8),
+        ("kern_time", C.c_double * 12), ("kern_flops", C.c_double * 12), ("kern_bytes", C.c_double * 12),
+        ("kern_launches", C.c_int32 * 12),
     ]
 
     KERNELS = ("k_gemm_f64", "k_gemm_f64_n64", "k_hss_sample", "k_pack_rot", "k_secular", "k_hss_compress",
-               "k_gemm_f64_big", "k_gemm_f64_n96")
+               "k_gemm_f64_big", "k_gemm_f64_n96", "k_fmm_leaf", "k_fmm_m2l", "unused10", "unused11")
 
     def as_dict(self):
         L = self.levels
@@ -94,6 +97,7 @@ _SIGS = {
     "adc_cauchy_gemm": (_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _I64),
     "adc_hss_build": (_P, _I64, _P, _P, _P, _P, _P, _P, _I32, C.POINTER(adc_opts), C.POINTER(_P)),
     "adc_hss_apply": (_P, _P, _I64, _P, _I64, _P, _I64),
+    "adc_hss_sample": (_P, _I64, _P, _P, _P, _P, _P, _P, _I32, C.POINTER(adc_opts), _P, _P),
     "adc_hss_info": (_P, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                      C.POINTER(_I32), C.POINTER(_D)),
     "adc_hss_free": (_P,),
@@ -206,6 +210,11 @@ def adc_hss_build(ctx, K, d, gam, mu, uh, v, omega, s, o=None):
     st = lib().adc_hss_build(ctx, int(K), _ptr(d), _ptr(gam), _ptr(mu), _ptr(uh), _ptr(v), _ptr(omega), int(s),
                              C.byref(o) if o is not None else None, C.byref(h))
     return st, h
+
+
+def adc_hss_sample(ctx, K, d, gam, mu, uh, v, omega, s, o, phi, theta):
+    return lib().adc_hss_sample(ctx, int(K), _ptr(d), _ptr(gam), _ptr(mu), _ptr(uh), _ptr(v), _ptr(omega), int(s),
+                                C.byref(o) if o is not None else None, _ptr(phi), _ptr(theta))
 
 
 def adc_hss_apply(ctx, h, P, X, ldx, Y, ldy):

@@ -45,6 +45,8 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   o->r_cap = 100;
   o->rank_eps = 1e-16;
   o->hss_min_flops = 1e11;
+  o->sample_mode = ADC_SAMPLE_FMM;
+  o->fmm_order = 20;
   return ADC_OK;
 }
 
@@ -55,6 +57,7 @@ adc_status validate_opts_ext(const adc_opts& o) {
   if (o.nprobe < 1 || o.nprobe > 32 || o.r_cap < 1 || !(o.rank_eps > 0.0) ||
       !(o.hss_min_flops >= 0.0))
     return ADC_ERR_ARG;
+  if (o.sample_mode < 0 || o.sample_mode > 1 || o.fmm_order < 4 || o.fmm_order > 32) return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
   return ADC_OK;
 }

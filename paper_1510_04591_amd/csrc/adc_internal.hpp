@@ -12,6 +12,8 @@ enum Slot {
   SLOT_HSS,        // HSS workspace of the solver
   SLOT_HSS2,       // HSS work arrays of the solver (second arena)
   SLOT_HSS_RETRY,  // HSS workspace of the merges rebuilt with more samples
+  SLOT_FMM,        // fast-sampling coefficients (multipole and local)
+  SLOT_SAMPLE_JOBS, // sampling launch lists (direct or fast)
   SLOT_BATCH,      // batched solver workspace
   SLOT_BATCH_DESC, // batched solver descriptors
   SLOT_MLP,        // MLP scratch
@@ -78,7 +80,9 @@ enum KernId {
   KT_SECULAR = 4,
   KT_COMPRESS = 5,
   KT_GEMMBIG = 6,
-  KT_GEMM96 = 7
+  KT_GEMM96 = 7,
+  KT_FMMLEAF = 8,
+  KT_FMMM2L = 9
 };
 struct KernTimer {
   std::vector<hipEvent_t> ev;

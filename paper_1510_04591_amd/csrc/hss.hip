@@ -97,10 +97,13 @@ struct HssBatch {
     double err = 0.0;
     int retries = 0;
     int max_rank = 0;
+    std::vector<double> hd, hg, hmu;  // host copies of d, gam, mu (fast sampling lists)
   };
   std::vector<One> ms;
   char* mem = nullptr;
   HssMerge* d_ms = nullptr;
+  int fmm_p = 0;                   // Chebyshev points per node; 0: direct sampling
+  std::vector<char> sample_host;   // launch lists of the last sampling pass
 };
 
 namespace {
@@ -213,12 +216,13 @@ static adc_status batch_upload(adc_ctx c, HssBatch& hb) {
 }
 
 // Sampling and compression of every merge in the batch (omega already drawn).
-static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
+// Direct sampling: every entry of the off-diagonal blocks generated and
+// summed; Y and Z in one launch, the inner dimension split into segments
+// until about six waves per SIMD are resident (each 64-row job is four
+// waves), the segment partial sums added afterwards.
+static adc_status sample_direct(adc_ctx c, HssBatch& hb) {
   hipStream_t st = c->stream;
   const int nm = (int)hb.ms.size();
-  // sampling jobs: Y and Z in one launch, the inner dimension split into
-  // segments until about six waves per SIMD are resident (each 64-row job is
-  // four waves); segment partial sums are added afterwards
   int64_t Ksum = 0;
   for (auto& m : hb.ms) Ksum += m.K;
   const int64_t waves = 2 * ((Ksum + 15) / 16);
@@ -238,6 +242,147 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   }
   double* part = nullptr;
   if (nseg > 1) ADC_TRY(c->buffer(SLOT_HSS2, (size_t)ptot * 8 + 256, (void**)&part));
+  void* dj;
+  ADC_TRY(c->buffer(SLOT_SAMPLE_JOBS, sj.size() * sizeof(SampleJob) + 256, &dj));
+  hb.sample_host.assign((const char*)sj.data(), (const char*)(sj.data() + sj.size()));
+  HIP_OK(hipMemcpyAsync(dj, hb.sample_host.data(), hb.sample_host.size(), hipMemcpyHostToDevice, st));
+  // algorithmic flops of one sampling pass: the off-diagonal-block part of
+  // Q' times s columns; bytes: Omega read, the samples written
+  double sfl = 0.0, sby = 0.0;
+  for (auto& m : hb.ms) {
+    double dsq = 0.0;
+    for (size_t i = 0; i + 1 < m.bounds.size(); ++i) dsq += (double)(m.bounds[i + 1] - m.bounds[i]) * (m.bounds[i + 1] - m.bounds[i]);
+    sfl += 2.0 * m.s * ((double)m.K * m.K - dsq);
+    sby += 16.0 * m.K * m.s;
+  }
+  c->ktimer.pre(st);
+  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms, (const SampleJob*)dj, 1,
+                     part);
+  c->ktimer.post(st, KT_SAMPLE, 2.0 * sfl, 2.0 * sby);
+  if (nseg > 1) {
+    for (int g = 0; g < nm; ++g) {
+      const auto& m = hb.ms[g];
+      const int64_t n = (int64_t)m.K * m.sp;
+      for (int tr = 0; tr < 2; ++tr)
+        hipLaunchKernelGGL(k_sample_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (const double*)(part + pb[g] + (int64_t)tr * nseg * n), nseg, n,
+                           tr ? m.dev.theta : m.dev.phi);
+    }
+  }
+  HIP_OK(hipGetLastError());
+  return ADC_OK;
+}
+
+// Fast sampling (one-dimensional Chebyshev FMM over each merge's HSS tree):
+// P2M at the leaves, M2M by height, M2L over the far lists, L2L by depth,
+// then the leaves' local expansions and near fields.  Every job covers one
+// (node, side, 32-column chunk).
+static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
+  hipStream_t st = c->stream;
+  const int P = hb.fmm_p;
+  const int nm = (int)hb.ms.size();
+  std::vector<int64_t> off(nm);
+  int64_t tot = 0;
+  int Lmax = 0;
+  for (int g = 0; g < nm; ++g) {
+    off[g] = tot;
+    tot += (int64_t)hb.ms[g].nodes.size() * 2 * P * hb.ms[g].sp;
+    Lmax = std::max(Lmax, hb.ms[g].L);
+  }
+  double* W;
+  ADC_TRY(c->buffer(SLOT_FMM, (size_t)(2 * tot) * 8 + 256, (void**)&W));
+  double* F = W + tot;
+  std::vector<int32_t> lists;
+  std::vector<FmmJob> p2m, m2l, leaf;
+  std::vector<std::vector<FmmJob>> m2m(Lmax + 1), l2l(Lmax + 1);
+  double near_fl = 0.0, m2l_fl = 0.0;
+  std::vector<std::vector<int32_t>> far, near;
+  for (int g = 0; g < nm; ++g) {
+    const auto& m = hb.ms[g];
+    if ((int64_t)m.hd.size() != m.K || (int64_t)m.hg.size() != m.K || (int64_t)m.hmu.size() != m.K)
+      return ADC_ERR_ARG;
+    fmm_lists(m.hd.data(), m.hg.data(), m.hmu.data(), m.nodes, far, near);
+    for (int q = 0; q < (int)m.nodes.size(); ++q) {
+      const HssNode& nd = m.nodes[q];
+      int l = 0;
+      while ((2 << l) - 1 <= q) ++l;  // level of heap node q
+      const int foff = (int)lists.size();
+      lists.insert(lists.end(), far[q].begin(), far[q].end());
+      const int noff = (int)lists.size();
+      lists.insert(lists.end(), near[q].begin(), near[q].end());
+      for (int side = 0; side < 2; ++side)
+        for (int c0 = 0; c0 < m.sp; c0 += 32) {
+          if (nd.leaf) {
+            p2m.push_back(FmmJob{g, q, side, c0, 0, 0});
+            leaf.push_back(FmmJob{g, q, side, c0, noff, (int)near[q].size()});
+          } else if (l >= 1) {
+            m2m[m.L - l].push_back(FmmJob{g, q, side, c0, 0, 0});
+          }
+          if (l >= 1) m2l.push_back(FmmJob{g, q, side, c0, foff, (int)far[q].size()});
+          if (l >= 2) l2l[l].push_back(FmmJob{g, q, side, c0, 0, 0});
+        }
+      for (int32_t sn : near[q]) near_fl += 2.0 * 2.0 * m.s * (double)(nd.hi - nd.lo) * (m.nodes[sn].hi - m.nodes[sn].lo);
+      m2l_fl += 2.0 * 2.0 * m.s * (double)P * P * far[q].size();
+    }
+  }
+  // one upload: offsets, lists and every job array
+  std::vector<char>& hj = hb.sample_host;
+  hj.clear();
+  auto put = [&](const void* src, size_t n) {
+    const size_t o = hj.size();
+    hj.resize((o + n + 255) & ~(size_t)255);
+    if (n) std::memcpy(hj.data() + o, src, n);
+    return o;
+  };
+  const size_t o_off = put(off.data(), off.size() * sizeof(int64_t));
+  const size_t o_lists = put(lists.data(), lists.size() * sizeof(int32_t));
+  const size_t o_p2m = put(p2m.data(), p2m.size() * sizeof(FmmJob));
+  const size_t o_m2l = put(m2l.data(), m2l.size() * sizeof(FmmJob));
+  const size_t o_leaf = put(leaf.data(), leaf.size() * sizeof(FmmJob));
+  std::vector<size_t> o_m2m(Lmax + 1), o_l2l(Lmax + 1);
+  for (int h = 0; h <= Lmax; ++h) o_m2m[h] = put(m2m[h].data(), m2m[h].size() * sizeof(FmmJob));
+  for (int l = 0; l <= Lmax; ++l) o_l2l[l] = put(l2l[l].data(), l2l[l].size() * sizeof(FmmJob));
+  void* dp;
+  ADC_TRY(c->buffer(SLOT_SAMPLE_JOBS, hj.size() + 256, &dp));
+  char* dj = (char*)dp;
+  HIP_OK(hipMemcpyAsync(dj, hj.data(), hj.size(), hipMemcpyHostToDevice, st));
+  const int64_t* d_off = (const int64_t*)(dj + o_off);
+  const int32_t* d_lists = (const int32_t*)(dj + o_lists);
+  if (!p2m.empty())
+    hipLaunchKernelGGL(k_fmm_p2m, dim3((unsigned)p2m.size()), dim3(256), 0, st, hb.d_ms,
+                       (const FmmJob*)(dj + o_p2m), P, W, d_off);
+  for (int h = 1; h <= Lmax; ++h)
+    if (!m2m[h].empty())
+      hipLaunchKernelGGL(k_fmm_m2m, dim3((unsigned)m2m[h].size()), dim3(256), 0, st, hb.d_ms,
+                         (const FmmJob*)(dj + o_m2m[h]), P, W, d_off);
+  if (!m2l.empty()) {
+    c->ktimer.pre(st);
+    hipLaunchKernelGGL(k_fmm_m2l, dim3((unsigned)m2l.size()), dim3(256), 0, st, hb.d_ms,
+                       (const FmmJob*)(dj + o_m2l), d_lists, P, (const double*)W, F, d_off);
+    c->ktimer.post(st, KT_FMMM2L, m2l_fl, 0.0);
+  }
+  for (int l = 2; l <= Lmax; ++l)
+    if (!l2l[l].empty())
+      hipLaunchKernelGGL(k_fmm_l2l, dim3((unsigned)l2l[l].size()), dim3(256), 0, st, hb.d_ms,
+                         (const FmmJob*)(dj + o_l2l[l]), P, F, d_off);
+  c->ktimer.pre(st);
+  hipLaunchKernelGGL(k_fmm_leaf, dim3((unsigned)leaf.size()), dim3(128), 0, st, hb.d_ms,
+                     (const FmmJob*)(dj + o_leaf), d_lists, P, (const double*)F, d_off);
+  c->ktimer.post(st, KT_FMMLEAF, near_fl, 0.0);
+  HIP_OK(hipGetLastError());
+  return ADC_OK;
+}
+
+static adc_status batch_sample(adc_ctx c, HssBatch& hb) {
+  return hb.fmm_p > 0 ? sample_fmm(c, hb) : sample_direct(c, hb);
+}
+
+// Sampling and compression of every merge in the batch (omega already drawn).
+static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
+  hipStream_t st = c->stream;
+  const int nm = (int)hb.ms.size();
+  ADC_TRY(batch_sample(c, hb));
+  c->timer.mark(st, 5);
   // compression jobs per level
   int Lmax = 0;
   for (auto& m : hb.ms) Lmax = std::max(Lmax, m.L);
@@ -262,7 +407,7 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
       }
     }
   }
-  size_t jbytes = sj.size() * sizeof(SampleJob) + 256 * (2 * Lmax + 3);
+  size_t jbytes = 256 * (2 * Lmax + 3);
   for (auto& v : lj) jbytes += v.size() * sizeof(NodeJob);
   for (auto& v : bj) jbytes += v.size() * sizeof(NodeJob);
   void* dp;
@@ -276,37 +421,10 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
     off = (off + n + 255) & ~(size_t)255;
     return o;
   };
-  const size_t o_sj = put(sj.data(), sj.size() * sizeof(SampleJob));
   std::vector<size_t> o_lj(Lmax + 1), o_bj(Lmax + 1);
   for (int l = 0; l <= Lmax; ++l) o_lj[l] = put(lj[l].data(), lj[l].size() * sizeof(NodeJob));
   for (int l = 0; l <= Lmax; ++l) o_bj[l] = put(bj[l].data(), bj[l].size() * sizeof(NodeJob));
   HIP_OK(hipMemcpyAsync(dj, hj.data(), off, hipMemcpyHostToDevice, st));
-
-  // algorithmic flops of one sampling pass: the off-diagonal-block part of
-  // Q' times s columns; bytes: Omega read, the samples written
-  double sfl = 0.0, sby = 0.0;
-  for (auto& m : hb.ms) {
-    double dsq = 0.0;
-    for (size_t i = 0; i + 1 < m.bounds.size(); ++i) dsq += (double)(m.bounds[i + 1] - m.bounds[i]) * (m.bounds[i + 1] - m.bounds[i]);
-    sfl += 2.0 * m.s * ((double)m.K * m.K - dsq);
-    sby += 16.0 * m.K * m.s;
-  }
-  c->ktimer.pre(st);
-  hipLaunchKernelGGL(k_hss_sample, dim3((unsigned)sj.size()), dim3(256), 0, st, hb.d_ms, (const SampleJob*)(dj + o_sj),
-                     1, part);
-  c->ktimer.post(st, KT_SAMPLE, 2.0 * sfl, 2.0 * sby);
-  if (nseg > 1) {
-    for (int g = 0; g < nm; ++g) {
-      const auto& m = hb.ms[g];
-      const int64_t n = (int64_t)m.K * m.sp;
-      for (int tr = 0; tr < 2; ++tr)
-        hipLaunchKernelGGL(k_sample_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                           (const double*)(part + pb[g] + (int64_t)tr * nseg * n), nseg, n,
-                           tr ? m.dev.theta : m.dev.phi);
-    }
-  }
-  HIP_OK(hipGetLastError());
-  c->timer.mark(st, 5);
   // dynamic LDS of every node job: its ID matrix when it fits (odd leading
   // dimension sp + 1), else the staging of its small products
   (void)ncand_max;
@@ -770,7 +888,10 @@ static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool c
     m.retries = 0;
   }
   if (rb_of) rb_of->assign(hb.ms.size(), -1);
-  if (rb) rb->ms.clear();
+  if (rb) {
+    rb->ms.clear();
+    rb->fmm_p = hb.fmm_p;
+  }
   ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, check, rep, flops, omega_given));
   if (!check) return ADC_OK;
   for (int attempt = 1; attempt <= o.max_retries; ++attempt) {
@@ -829,8 +950,12 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     m.dev.uh = B.uh + M.s0;
     m.dev.v = B.v + M.s0;
     m.dev.id_tol = o.id_tol;
-    hb.ms.push_back(m);
+    m.hd = std::move(d);
+    m.hg = std::move(g2);
+    m.hmu = std::move(mu);
+    hb.ms.push_back(std::move(m));
   }
+  hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
   HssBatch rb;
   std::vector<int> rb_of;
   ADC_TRY(batch_build(c, hb, o, true, rep, flops, nullptr, &rb, &rb_of));
@@ -928,7 +1053,11 @@ extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const
   m.dev.uh = h->gen + 3 * K;
   m.dev.v = h->gen + 4 * K;
   m.dev.id_tol = o.id_tol;
-  hb.ms.push_back(m);
+  m.hd = std::move(hd);
+  m.hg = std::move(hg);
+  m.hmu = std::move(hm);
+  hb.ms.push_back(std::move(m));
+  hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
   std::vector<const double*> om{omega};
   adc_status sres = batch_build(c, hb, o, omega == nullptr, nullptr, nullptr, omega ? &om : nullptr);
   if (sres != ADC_OK) {
@@ -971,6 +1100,56 @@ extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const
   h->dense_fallback = !mm.pass;
   h->bounds = mm.bounds;
   *out = h;
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_hss_sample(adc_ctx c, int64_t K, const double* d, const double* gam, const double* mu,
+                                     const double* uh, const double* v, const double* omega, int32_t s,
+                                     const adc_opts* opts_in, double* phi, double* theta) {
+  if (!c || K < 2 || K > (1 << 24) || !d || !gam || !mu || !uh || !v || !omega || !phi || !theta || s < 1 ||
+      s > S_MAX)
+    return ADC_ERR_ARG;
+  c->ktimer.begin(false);
+  adc_opts o;
+  if (opts_in) o = *opts_in;
+  else adc_opts_default(&o);
+  ADC_TRY(validate_opts_ext(o));
+  DeviceGuard gd(c->device);
+  hipStream_t st = c->stream;
+  HssBatch hb;
+  HssBatch::One m;
+  m.K = (int)K;
+  m.L = std::max(1, ceil_log2_ratio((int)K, o.hss_leaf));
+  m.bounds = balanced_bounds((int)K, m.L);
+  m.s = s;
+  m.sp = (s + 31) / 32 * 32;
+  m.hd.resize(K);
+  m.hg.resize(K);
+  m.hmu.resize(K);
+  HIP_OK(hipMemcpyAsync(m.hd.data(), d, K * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(m.hg.data(), gam, K * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(m.hmu.data(), mu, K * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  m.dev.d = d;
+  m.dev.gam = gam;
+  m.dev.mu = mu;
+  m.dev.uh = uh;
+  m.dev.v = v;
+  m.dev.id_tol = o.id_tol;
+  hb.ms.push_back(std::move(m));
+  hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
+  ADC_TRY(batch_alloc(c, hb, SLOT_HSS));
+  ADC_TRY(batch_upload(c, hb));
+  HssBatch::One& mm = hb.ms[0];
+  HIP_OK(hipMemset2DAsync(mm.dev.omega, mm.sp * 8, 0, mm.sp * 8, mm.K, st));
+  HIP_OK(hipMemcpy2DAsync(mm.dev.omega, mm.sp * 8, omega, (size_t)s * 8, (size_t)s * 8, mm.K,
+                          hipMemcpyDeviceToDevice, st));
+  ADC_TRY(batch_sample(c, hb));
+  HIP_OK(hipMemcpy2DAsync(phi, (size_t)s * 8, mm.dev.phi, mm.sp * 8, (size_t)s * 8, mm.K, hipMemcpyDeviceToDevice,
+                          st));
+  HIP_OK(hipMemcpy2DAsync(theta, (size_t)s * 8, mm.dev.theta, mm.sp * 8, (size_t)s * 8, mm.K,
+                          hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
   return ADC_OK;
 }
 

@@ -85,5 +85,29 @@ __global__ void k_diff_norms(const double* __restrict__ a, const double* __restr
                              double* __restrict__ part);
 __global__ void k_sum_pairs(const double* __restrict__ part, int nblk, double* __restrict__ out2);
 
+// Fast sampling (one-dimensional Chebyshev FMM over the HSS tree)
+struct FmmJob {
+  int32_t merge;
+  int32_t node;  // heap index
+  int32_t side;  // 0: Phi (targets d, sources lam), 1: Theta (targets lam, sources d)
+  int32_t c0;    // first sample column of the job's 32-column chunk
+  int32_t loff;  // offset of the node's far (M2L) or near (leaf) list
+  int32_t lcnt;  // its length
+};
+__global__ void k_fmm_p2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs, int P,
+                          double* __restrict__ W, const int64_t* __restrict__ off);
+__global__ void k_fmm_m2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs, int P,
+                          double* __restrict__ W, const int64_t* __restrict__ off);
+__global__ void k_fmm_m2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
+                          const int32_t* __restrict__ lists, int P, const double* __restrict__ W,
+                          double* __restrict__ F, const int64_t* __restrict__ off);
+__global__ void k_fmm_l2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs, int P,
+                          double* __restrict__ F, const int64_t* __restrict__ off);
+__global__ void k_fmm_leaf(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
+                           const int32_t* __restrict__ lists, int P, const double* __restrict__ F,
+                           const int64_t* __restrict__ off);
+void fmm_lists(const double* d, const double* gam, const double* mu, const std::vector<HssNode>& nodes,
+               std::vector<std::vector<int32_t>>& far, std::vector<std::vector<int32_t>>& near);
+
 adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
                             const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes);
