@@ -95,7 +95,7 @@ typedef struct adc_opts {
   int32_t strict;        /* [0] 1: a failed HSS check is ADC_ERR_ACCURACY       */
   double  check_tol;     /* [1e-13] relative error allowed by the HSS check     */
   int32_t nprobe;        /* [4] Gaussian probe vectors of the HSS check, 1..32  */
-  int32_t shift_max;     /* [5] max boundary move of the rank estimate          */
+  int32_t shift_max;     /* [5] max boundary move of the rank estimate, 0..64   */
   double  shift_thresh;  /* [1e-10] move a boundary when its distance is below  */
   int32_t r_cap;         /* [100] cap of the estimated rank                     */
   double  rank_eps;      /* [1e-16] epsilon of eq. (bounds)                     */

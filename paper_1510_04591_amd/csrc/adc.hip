@@ -58,6 +58,7 @@ adc_status validate_opts_ext(const adc_opts& o) {
       !(o.hss_min_flops >= 0.0))
     return ADC_ERR_ARG;
   if (o.sample_mode < 0 || o.sample_mode > 1 || o.fmm_order < 4 || o.fmm_order > 32) return ADC_ERR_ARG;
+  if (o.shift_max < 0 || o.shift_max > 64) return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
   return ADC_OK;
 }

@@ -211,6 +211,7 @@ bool mlp_collecting(adc_ctx c);
 adc_status mlp_collect_merge(adc_ctx c, const double* d, const double* gam, const double* mu, int K,
                              const std::vector<int>& bounds, const std::vector<int>& lo, const std::vector<int>& hi,
                              const std::vector<int>& kr, const std::vector<int>& kc);
-// Rank estimate of eq. (bounds) over leaf boundaries (may move boundaries).
+// Rank estimate of eq. (bounds) over leaf boundaries (moves boundaries closer
+// than shift_thresh unless shift is false).
 int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
-                      const adc_opts& o);
+                      const adc_opts& o, bool shift = true);

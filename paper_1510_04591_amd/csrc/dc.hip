@@ -94,7 +94,7 @@ struct WsLayout {
   double *a, *win, *Zb;
   double *dsort, *zsort, *dS, *zS, *lam, *gam, *mu, *uh, *v, *rot_c, *rot_s;
   int32_t *src, *supp, *surv, *defl, *gorder, *rot_i, *rot_j, *rot_f, *posR, *posD, *colmerge;
-  int32_t *pidx, *ginv, *rot_i_of, *rot_j_of;
+  int32_t *pidx, *ginv, *rot_i_of, *rot_j_of, *lcnt;
   double *pk, *qc;
   int* noconv;
   size_t bytes;
@@ -131,6 +131,7 @@ WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
   L.ginv = ar.take<int32_t>(N);
   L.rot_i_of = ar.take<int32_t>(N);
   L.rot_j_of = ar.take<int32_t>(N);
+  L.lcnt = ar.take<int32_t>(N);
   L.noconv = ar.take<int>(64);
   L.Zb = need_zb ? ar.take<double>((size_t)N * N) : nullptr;
   L.pk = ar.take<double>((size_t)N * N);
@@ -175,7 +176,8 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   HIP_OK(hipMemcpyAsync(dg, &P, sizeof(P), hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(dtm, tm.data(), nt * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(dtc, tc.data(), nt * 4, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_cauchy, dim3((unsigned)nt), dim3(256), 0, st, d_m, dtm, dtc, B, ncols, 0);
+  // rows of qc in the packed order of the merge's columns
+  hipLaunchKernelGGL(k_cauchy, dim3((unsigned)nt), dim3(256), 0, st, d_m, dtm, dtc, B, ncols, 1);
   hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, st, dg, 1);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(st));
@@ -237,7 +239,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
   const size_t blocks64 = (size_t)(n / 64 + 2 * max_merges + 8);
   const size_t desc_bytes = 4096 + nleaf * 32 + plan.splits.size() * 8 + max_merges * sizeof(MergeDev) +
                             3 * blocks64 * sizeof(RootBlock) + 2 * max_merges * sizeof(GemmProb) +
-                            (size_t)n * 8 + 2 * ((size_t)n / 8 + max_merges + 8) * 4 + 32 * 256;
+                            (size_t)n * 8 + 2 * ((size_t)n / 8 + max_merges + 8) * 4 + 32 * 256 +
+                            12 * ((size_t)n / 8 + 2 * max_merges) + 256 * (max_merges + 4);
   char* hs;
   ADC_TRY(c->stage(desc_bytes * 2, (void**)&hs));
   char* dd;
@@ -329,6 +332,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     B.ginv = L.ginv;
     B.rot_i_of = L.rot_i_of;
     B.rot_j_of = L.rot_j_of;
+    B.lcnt = L.lcnt;
 
     Arena ha{hs, 0, 0}, da{dd, 0, 0};
     MergeDev* h_m = ha.take<MergeDev>(nm);
@@ -380,6 +384,30 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       Ksum += M.K;
       nsum += M.n;
     }
+    // HSS merges: the leaf boundaries of their HSS trees (leaves of at most
+    // hss_leaf <= 256 survivors) and one column-grouping job per leaf
+    std::vector<int2> lg_jobs;
+    std::vector<int32_t> lg_merges;
+    for (int g2 = 0; g2 < nm; ++g2) {
+      MergeDev& M = h_m[g2];
+      M.lbounds = nullptr;
+      M.nleaf = 0;
+      if (M.mode != 1) continue;
+      const std::vector<int> bd = hss_leaf_bounds(M.K, o.hss_leaf);
+      int32_t* hbd = ha.take<int32_t>(bd.size());
+      int32_t* dbd = da.take<int32_t>(bd.size());
+      std::copy(bd.begin(), bd.end(), hbd);
+      M.lbounds = dbd;
+      M.nleaf = (int)bd.size() - 1;
+      lg_merges.push_back(g2);
+      for (int i = 0; i < M.nleaf; ++i) lg_jobs.push_back(int2{g2, i});
+    }
+    int2* h_lg = ha.take<int2>(lg_jobs.size() + 1);
+    int2* d_lg = da.take<int2>(lg_jobs.size() + 1);
+    std::copy(lg_jobs.begin(), lg_jobs.end(), h_lg);
+    int32_t* h_lgm = ha.take<int32_t>(lg_merges.size() + 1);
+    int32_t* d_lgm = da.take<int32_t>(lg_merges.size() + 1);
+    std::copy(lg_merges.begin(), lg_merges.end(), h_lgm);
     RootBlock* h_rb = ha.take<RootBlock>(blocks64);
     RootBlock* d_rb = da.take<RootBlock>(blocks64);
     int nrb = 0;
@@ -452,6 +480,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       }
     }
     if (rep && gtiles) rep->phase_launches[4] += 1;
+    if (ha.off > desc_bytes) return ADC_ERR_UNSUPPORTED;  // descriptor space sized too small
     HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
 
     // --- secular, Loewner, v
@@ -471,6 +500,11 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     // packing: every column's support rows read once, all n rows written
     double pack_by = 0.0;
     for (int g2 = 0; g2 < nm; ++g2) pack_by += 12.0 * (double)h_m[g2].n * h_m[g2].n;
+    if (!lg_jobs.empty()) {
+      hipLaunchKernelGGL(k_leaf_bounds, dim3((unsigned)lg_merges.size()), dim3(64), 0, st, d_m, d_lgm, B,
+                         o.shift_thresh, o.shift_max);
+      hipLaunchKernelGGL(k_leaf_group, dim3((unsigned)lg_jobs.size()), dim3(512), 0, st, d_m, d_lg, B);
+    }
     c->ktimer.pre(st);
     hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B);
     c->ktimer.post(st, KT_PACK, 0.0, pack_by);

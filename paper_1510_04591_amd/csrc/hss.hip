@@ -50,17 +50,21 @@ double boundary_dist(const double* d, const double* gam, const double* mu, int K
 
 }  // namespace
 
+std::vector<int> hss_leaf_bounds(int K, int leaf) {
+  return balanced_bounds(K, std::max(1, ceil_log2_ratio(K, leaf)));
+}
+
 // Rank estimate over the leaf boundaries (Section 4.1): every boundary closer
 // than shift_thresh is moved by up to shift_max indices to the largest
 // distance; r = min(r_cap, max_b rank_bound((lam_K - d_1)/dist_b)).
 int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
-                      const adc_opts& o) {
+                      const adc_opts& o, bool shift) {
   const double span = (d[K - 1] + gam[K - 1]) - d[0];
   int r = 0;
   for (size_t t = 1; t + 1 < bounds.size(); ++t) {
     int b = bounds[t];
     double dist = boundary_dist(d, gam, mu, K, b);
-    if (dist < o.shift_thresh) {
+    if (shift && dist < o.shift_thresh) {
       int best = b;
       double bd = dist;
       const int lo = std::max(bounds[t - 1] + 1, b - o.shift_max);
@@ -98,6 +102,7 @@ struct HssBatch {
     int retries = 0;
     int max_rank = 0;
     std::vector<double> hd, hg, hmu;  // host copies of d, gam, mu (fast sampling lists)
+    std::vector<int32_t> grp;         // per leaf: top-only, both, bottom-only columns (solver)
   };
   std::vector<One> ms;
   char* mem = nullptr;
@@ -469,6 +474,9 @@ struct ApplyJob {
   double* C;          // output columns: C + colmap[j] * ldc (colmap may be null)
   int64_t ldc;
   const int32_t* colmap;
+  // -1: X's columns in index order; 0 / 1: X holds the top / bottom rows of a
+  // solver merge's packed operand, columns leaf-grouped (HssMerge::perm)
+  int half = -1;
 };
 
 static void push_prob(std::vector<GemmProb>& v, const GemmProb& p) { v.push_back(p); }
@@ -555,10 +563,13 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
   std::vector<Lay> lays(jobs.size());
   int64_t total = 0;
   std::vector<int2> leafjobs;
-  std::vector<int64_t> doff;
-  std::vector<int64_t> leaf_base(jobs.size());
-  int64_t dtotal = 0;
+  std::vector<int64_t> doff, uoff;
+  // leaf data (D_i, and U_i in leaf-grouped row order) once per merge
+  std::vector<int64_t> leaf_base(hb.ms.size(), -1);
+  int64_t dtotal = 0, utotal = 0;
+  const bool grouped = !jobs.empty() && jobs[0].half >= 0;
   for (size_t t = 0; t < jobs.size(); ++t) {
+    if ((jobs[t].half >= 0) != grouped) return ADC_ERR_ARG;
     const auto& m = hb.ms[jobs[t].g];
     Lay& ly = lays[t];
     const int nn = (int)m.nodes.size();
@@ -579,25 +590,46 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       ly.lev_f[l] = total;
       total += sf * jobs[t].P;
     }
-    leaf_base[t] = (int64_t)leafjobs.size();
+    if (leaf_base[jobs[t].g] >= 0) continue;
+    leaf_base[jobs[t].g] = (int64_t)leafjobs.size();
+    if (grouped && (int)m.grp.size() != 3 * (1 << m.L)) return ADC_ERR_ARG;
     for (int q = (1 << m.L) - 1; q < (1 << (m.L + 1)) - 1; ++q) {
       const int mm = m.nodes[q].hi - m.nodes[q].lo;
       leafjobs.push_back(int2{jobs[t].g, q});
       doff.push_back(dtotal);
       dtotal += (int64_t)mm * mm;
+      uoff.push_back(utotal);
+      if (grouped) utotal += (int64_t)mm * m.nodes[q].kr;
     }
   }
   void* wp;
-  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal) * 8 + leafjobs.size() * 16 + 1024, &wp));
+  const size_t lj_bytes = (leafjobs.size() * sizeof(int2) + 255) & ~(size_t)255;
+  const size_t of_bytes = (doff.size() * 8 + 255) & ~(size_t)255;
+  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal + utotal) * 8 + lj_bytes + 2 * of_bytes + 1024, &wp));
   double* work = (double*)wp;
   double* dmat = work + total;
-  char* tail = (char*)(dmat + dtotal);
+  double* uperm = dmat + dtotal;
+  char* tail = (char*)(uperm + utotal);
   int2* d_lj = (int2*)tail;
-  int64_t* d_doff = (int64_t*)(tail + ((leafjobs.size() * sizeof(int2) + 255) & ~(size_t)255));
+  int64_t* d_doff = (int64_t*)(tail + lj_bytes);
+  int64_t* d_uoff = (int64_t*)(tail + lj_bytes + of_bytes);
   HIP_OK(hipMemcpyAsync(d_lj, leafjobs.data(), leafjobs.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(d_doff, doff.data(), doff.size() * 8, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_hss_dmat, dim3((unsigned)leafjobs.size()), dim3(256), 0, st, hb.d_ms, d_lj, dmat, d_doff);
+  if (grouped) HIP_OK(hipMemcpyAsync(d_uoff, uoff.data(), uoff.size() * 8, hipMemcpyHostToDevice, st));
+  // D_i (rows in the packed order for grouped jobs) and the grouped U_i
+  hipLaunchKernelGGL(k_hss_dmat, dim3((unsigned)leafjobs.size()), dim3(256), 0, st, hb.d_ms, d_lj, dmat, d_doff,
+                     grouped ? 1 : 0);
+  if (grouped)
+    hipLaunchKernelGGL(k_hss_urows, dim3((unsigned)leafjobs.size()), dim3(256), 0, st, hb.d_ms, d_lj, uperm,
+                       d_uoff);
   HIP_OK(hipGetLastError());
+  // the leaf column range of a grouped job: top rows meet top-only and both,
+  // bottom rows both and bottom-only
+  auto leaf_range = [&](const ApplyJob& J, int li, int& kb, int& kl) {
+    const int32_t* gc = hb.ms[J.g].grp.data() + 3 * li;
+    kb = J.half == 0 ? 0 : gc[0];
+    kl = J.half == 0 ? gc[0] + gc[1] : gc[1] + gc[2];
+  };
 
   int Lmax = 0;
   size_t nodes_all = 0;
@@ -646,7 +678,16 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         p.ldc = J.P;
         p.B = m.dev.arena + nd.offU;
         p.ldb = nd.nr;
-        if (nd.leaf) {
+        if (nd.leaf && grouped) {
+          const int li = q - ((1 << m.L) - 1);
+          int kb, kl;
+          leaf_range(J, li, kb, kl);
+          p.A = J.X + (int64_t)(nd.lo + kb) * J.ldx;
+          p.lda = J.ldx;
+          p.K = kl;
+          p.B = uperm + uoff[leaf_base[J.g] + li] + kb;
+          p.ldb = nd.hi - nd.lo;
+        } else if (nd.leaf) {
           p.A = J.X + (int64_t)nd.lo * J.ldx;
           p.lda = J.ldx;
           p.K = nd.hi - nd.lo;
@@ -724,8 +765,15 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       p.K = mm;
       p.A = J.X + (int64_t)nd.lo * J.ldx;
       p.lda = J.ldx;
-      p.B = dmat + doff[leaf_base[t] + li];
+      p.B = dmat + doff[leaf_base[J.g] + li];
       p.ldb = mm;
+      if (grouped) {
+        int kb, kl;
+        leaf_range(J, li, kb, kl);
+        p.A = J.X + (int64_t)(nd.lo + kb) * J.ldx;
+        p.K = kl;
+        p.B += kb;
+      }
       if (m.L > 0) {
         p.K2 = nd.kc;
         p.A2 = F(t, q);
@@ -933,14 +981,20 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     HssBatch::One m;
     m.K = M.K;
     m.L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
-    m.bounds = balanced_bounds(M.K, m.L);
+    // the leaves the packing grouped the columns by (moved on the device)
+    if (M.nleaf != (1 << m.L) || !M.lbounds) return ADC_ERR_ARG;
+    m.bounds.resize(M.nleaf + 1);
+    HIP_OK(hipMemcpyAsync(m.bounds.data(), M.lbounds, m.bounds.size() * 4, hipMemcpyDeviceToHost, st));
     m.stream = (uint32_t)((depth << 20) + which[t]);
     std::vector<double> d(M.K), g2(M.K), mu(M.K);
     HIP_OK(hipMemcpyAsync(d.data(), B.dS + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(g2.data(), B.gam + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(mu.data(), B.mu + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    // column groups of every leaf of the packed operand (k_leaf_group)
+    m.grp.resize(3 * (size_t)M.nleaf);
+    HIP_OK(hipMemcpyAsync(m.grp.data(), B.lcnt + M.s0, m.grp.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    m.r = hss_rank_estimate(d.data(), g2.data(), mu.data(), M.K, m.bounds, o);
+    m.r = hss_rank_estimate(d.data(), g2.data(), mu.data(), M.K, m.bounds, o, false);
     if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
     if (o.rank_mode == ADC_RANK_MLP && !mlp_collecting(c))
       m.r = mlp_rank(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, o, m.r);
@@ -949,6 +1003,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     m.dev.mu = B.mu + M.s0;
     m.dev.uh = B.uh + M.s0;
     m.dev.v = B.v + M.s0;
+    m.dev.perm = B.gorder + M.s0;
     m.dev.id_tol = o.id_tol;
     m.hd = std::move(d);
     m.hg = std::move(g2);
@@ -982,9 +1037,13 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
       ADC_TRY(mlp_collect_merge(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, lo, hi, kr, kc));
     }
     if (m.pass) {
-      (moved ? ajr : aj)
-          .push_back(ApplyJob{moved ? rb_of[t] : (int)t, B.pk + M.zoff, (int64_t)M.n, M.n, M.zn, M.ldn,
-                              B.posR + M.s0});
+      // the top and bottom rows of the packed operand, each against its
+      // leaf column ranges (columns grouped by row support inside leaves)
+      const int gi = moved ? rb_of[t] : (int)t;
+      auto& dst = moved ? ajr : aj;
+      dst.push_back(ApplyJob{gi, B.pk + M.zoff, (int64_t)M.n, M.n1, M.zn, M.ldn, B.posR + M.s0, 0});
+      dst.push_back(ApplyJob{gi, B.pk + M.zoff + M.n1, (int64_t)M.n, M.n - M.n1, M.zn + M.n1, M.ldn,
+                             B.posR + M.s0, 1});
     } else {
       dense_fb.push_back(which[t]);
       if (rep) rep->hss_fallbacks++;

@@ -33,6 +33,8 @@ struct HssMerge {
   double* phi;         // K x sp leaf row samples, row-major
   double* theta;       // K x sp leaf column samples, row-major
   HssNode* nodes;      // 2^(L+1) - 1 nodes
+  const int32_t* perm; // packed column -> index (leaf-grouped operand of the
+                       // solver's Algorithm 3), or null
   double* arena;       // generator and work storage
   int32_t* iarena;     // skeleton index storage
   double id_tol;
@@ -80,7 +82,9 @@ __global__ void k_probe_qt(const HssMerge* __restrict__ ms, int g, const double*
 __global__ void k_probe_sum(const double* __restrict__ part, int K, int nseg, int c0, int nc, int ntot,
                             double* __restrict__ out, int ldo);
 __global__ void k_hss_dmat(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
-                           double* __restrict__ dmat, const int64_t* __restrict__ doff);
+                           double* __restrict__ dmat, const int64_t* __restrict__ doff, int grouped);
+__global__ void k_hss_urows(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
+                            double* __restrict__ out, const int64_t* __restrict__ uoff);
 __global__ void k_diff_norms(const double* __restrict__ a, const double* __restrict__ b, int64_t K, int ld, int nc,
                              double* __restrict__ part);
 __global__ void k_sum_pairs(const double* __restrict__ part, int nblk, double* __restrict__ out2);
@@ -108,6 +112,10 @@ __global__ void k_fmm_leaf(const HssMerge* __restrict__ ms, const FmmJob* __rest
                            const int64_t* __restrict__ off);
 void fmm_lists(const double* d, const double* gam, const double* mu, const std::vector<HssNode>& nodes,
                std::vector<std::vector<int32_t>>& far, std::vector<std::vector<int32_t>>& near);
+
+// Leaf boundaries of the HSS tree over K indices with leaves of at most
+// `leaf` rows: L = ceil(log2(K / leaf)) levels (at least one), balanced.
+std::vector<int> hss_leaf_bounds(int K, int leaf);
 
 adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
                             const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes);

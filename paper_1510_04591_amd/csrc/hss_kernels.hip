@@ -609,7 +609,8 @@ __global__ void __launch_bounds__(256) k_hss_bblocks(const HssMerge* __restrict_
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_hss_dmat(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
-                                                  double* __restrict__ dmat, const int64_t* __restrict__ doff) {
+                                                  double* __restrict__ dmat, const int64_t* __restrict__ doff,
+                                                  int grouped) {
   const int2 jb = leafjobs[blockIdx.x];
   const HssMerge& M = ms[jb.x];
   const HssNode& nd = M.nodes[jb.y];
@@ -617,7 +618,24 @@ __global__ void __launch_bounds__(256) k_hss_dmat(const HssMerge* __restrict__ m
   double* D = dmat + doff[blockIdx.x];
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int r = e % m, c = e / m;
-    D[e] = gen_entry(M, nd.lo + r, nd.lo + c);
+    const int i = grouped ? M.perm[nd.lo + r] : nd.lo + r;
+    D[e] = gen_entry(M, i, nd.lo + c);
+  }
+}
+
+// U_i of every leaf with its rows in the packed (leaf-grouped) order of the
+// solver's operand: out[a + k m] = U_i[perm(lo + a) - lo, k], m x kr.
+__global__ void __launch_bounds__(256) k_hss_urows(const HssMerge* __restrict__ ms, const int2* __restrict__ leafjobs,
+                                                   double* __restrict__ out, const int64_t* __restrict__ uoff) {
+  const int2 jb = leafjobs[blockIdx.x];
+  const HssMerge& M = ms[jb.x];
+  const HssNode& nd = M.nodes[jb.y];
+  const int m = nd.hi - nd.lo;
+  const double* U = M.arena + nd.offU;
+  double* O = out + uoff[blockIdx.x];
+  for (int e = threadIdx.x; e < m * nd.kr; e += blockDim.x) {
+    const int a = e % m, k = e / m;
+    O[e] = U[(M.perm[nd.lo + a] - nd.lo) + (int64_t)k * nd.nr];
   }
 }
 

@@ -24,6 +24,13 @@ struct MergeDev {
   const double* zo;
   double* zn;
   int64_t ldo, ldn;
+  // HSS merges: leaf boundaries of the HSS tree over the survivors (pole
+  // order), nleaf + 1 entries, balanced then moved by k_leaf_bounds; the
+  // packing groups each leaf's columns by row support (top only, both,
+  // bottom only)
+  int32_t* lbounds;
+  int32_t nleaf;
+  int32_t pad_;
 };
 
 // Output block of one leaf: z points at its (first row, first column) corner.
@@ -86,7 +93,10 @@ struct LevelBufs {
   double* pk;           // packed survivor columns of U
   double* qc;           // materialised Cauchy matrix (dense update)
   int32_t* pidx;        // sorted position -> survivor r (>= 0) or -1 - deflated q
-  int32_t* ginv;        // survivor r -> position in the grouped order
+  int32_t* ginv;        // survivor r -> packed column: the grouped order (dense
+                        // update) or the leaf-grouped order (HSS update)
+  int32_t* lcnt;        // HSS merges: per leaf the counts of top-only, both and
+                        // bottom-only survivors (3 per leaf, at the merge's s0)
   int32_t* rot_i_of;    // sorted position -> rotation t with rot_i[t] = position, else -1
   int32_t* rot_j_of;    // sorted position -> rotation t with rot_j[t] = position, else -1
 };
@@ -115,6 +125,10 @@ __global__ void k_vnorm(const MergeDev* __restrict__ merges, const RootBlock* __
 
 __global__ void k_final_order(const MergeDev* __restrict__ merges, LevelBufs B,
                               const RootBlock* __restrict__ blocks);
+
+__global__ void k_leaf_bounds(const MergeDev* __restrict__ merges, const int32_t* __restrict__ which, LevelBufs B,
+                              double thresh, int shift_max);
+__global__ void k_leaf_group(const MergeDev* __restrict__ merges, const int2* __restrict__ jobs, LevelBufs B);
 
 __global__ void k_pack_rot(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
                            const int32_t* __restrict__ col_idx, LevelBufs B);

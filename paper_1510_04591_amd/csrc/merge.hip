@@ -483,6 +483,85 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
 }
 
 // ---------------------------------------------------------------------------
+// HSS merges: the leaf boundaries of the rank estimate (Section 4.1).  From
+// the balanced boundaries, every interior boundary b whose segments are
+// closer than `thresh`, dist(b) = min(|lam_b - d_{b-1}|, |d_b - lam_{b-1}|)
+// by eq. (d-lambda), moves by up to shift_max indices to the largest
+// distance, boundaries taken in order (a window starts after the previous,
+// already moved, boundary).  One workgroup per merge; thread 0 walks the
+// boundaries.
+__global__ void __launch_bounds__(64) k_leaf_bounds(const MergeDev* __restrict__ merges,
+                                                    const int32_t* __restrict__ which, LevelBufs B,
+                                                    double thresh, int shift_max) {
+  if (threadIdx.x != 0) return;
+  const MergeDev& M = merges[which[blockIdx.x]];
+  const int64_t s0 = M.s0;
+  const int K = M.K;
+  const double* d = B.dS + s0;
+  const double* gam = B.gam + s0;
+  const double* mu = B.mu + s0;
+  int32_t* bd = M.lbounds;
+  auto dist = [&](int b) {
+    const double x = (b < K) ? (d[b] - d[b - 1]) + gam[b] : INFINITY;
+    return fmin(fabs(x), fabs(mu[b - 1]));
+  };
+  for (int t = 1; t < M.nleaf; ++t) {
+    const int b = bd[t];
+    double best_d = dist(b);
+    if (!(best_d < thresh)) continue;
+    int best = b;
+    const int lo = max(bd[t - 1] + 1, b - shift_max);
+    const int hi = min(bd[t + 1] - 1, b + shift_max);
+    for (int bb = lo; bb <= hi; ++bb) {
+      const double dd = dist(bb);
+      if (dd > best_d) {
+        best = bb;
+        best_d = dd;
+      }
+    }
+    bd[t] = best;
+  }
+}
+
+// HSS merges: inside every leaf of the HSS tree (survivors in pole order)
+// the packed columns are grouped by row support, top only, both, then bottom
+// only (stable), so that each half of the rows meets one contiguous column
+// range of the leaf in Algorithm 3.  Writes ginv (survivor -> packed column),
+// gorder (packed column -> survivor) and lcnt[3 leaf + g], the three group
+// sizes.  One workgroup per (merge, leaf); leaves hold at most 512 survivors
+// (hss_leaf <= 256, boundaries moved by at most shift_max each).
+__global__ void __launch_bounds__(512) k_leaf_group(const MergeDev* __restrict__ merges,
+                                                    const int2* __restrict__ jobs, LevelBufs B) {
+  __shared__ int grp[512];
+  const int2 jb = jobs[blockIdx.x];
+  const MergeDev& M = merges[jb.x];
+  const int64_t s0 = M.s0;
+  const int lo = M.lbounds[jb.y], hi = M.lbounds[jb.y + 1];
+  const int m = hi - lo;
+  const int t = threadIdx.x;
+  int g = 3;
+  if (t < m) {
+    const int f = B.supp[s0 + B.surv[s0 + lo + t]];
+    g = (f == 1) ? 0 : (f == 3) ? 1 : 2;
+  }
+  grp[t] = g;
+  __syncthreads();
+  if (t < m) {
+    int pos = 0;
+    for (int u = 0; u < m; ++u) {
+      const int gu = grp[u];
+      pos += (gu < g) || (gu == g && u < t);
+    }
+    B.ginv[s0 + lo + t] = lo + pos;
+    B.gorder[s0 + lo + pos] = lo + t;
+  }
+  if (t < 3) {
+    int cnt = 0;
+    for (int u = 0; u < m; ++u) cnt += grp[u] == t;
+    B.lcnt[s0 + 3 * jb.y + t] = cnt;
+  }
+}
+
 // Packing with the type-2 rotations applied on the fly.  One block per sorted
 // position of the level (job -> merge col_merge[job], position col_idx[job]).
 // A position untouched by rotations copies its column; the first position of
@@ -504,7 +583,7 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
   auto dst_of = [&](int pos) -> double* {
     const int role = B.pidx[s0 + pos];
     if (role >= 0) {
-      const int pk = (M.mode == 1) ? role : B.ginv[s0 + role];
+      const int pk = B.ginv[s0 + role];
       return B.pk + M.zoff + (int64_t)pk * n;
     }
     const int q = -1 - role;
