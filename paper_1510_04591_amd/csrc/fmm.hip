@@ -16,8 +16,11 @@
 //
 // Side 0 computes Phi (targets d, sources lam, weights v Omega), side 1
 // Theta (targets lam, sources d, weights uh Omega, kernel of opposite sign).
-// Every kernel works on 32-column chunks of the samples; W (multipole) and F
-// (local) coefficients are stored per merge at off[merge] as
+// Near-field entries use the rule of eq. (d-lambda) entry by entry, so a
+// leaf's near list may also hold the leaf itself (its diagonal block).  Every
+// kernel works on 32-column chunks; the operands of a merge are io[merge]
+// (Omega in, out[side], row-major with leading dimension sp), and the W
+// (multipole) and F (local) coefficients live at io[merge].off as
 // [(node * 2 + side) * P + k] * sp + column.
 #include <algorithm>
 #include <cmath>
@@ -66,8 +69,8 @@ __device__ inline void lagrange_col(double x, double h, int P, const double* t, 
   }
 }
 
-__device__ inline int64_t coef_base(const int64_t* off, const FmmJob& jb, int node, int P, int sp) {
-  return off[jb.merge] + ((int64_t)node * 2 + jb.side) * P * sp;
+__device__ inline int64_t coef_base(const FmmIo& io, const FmmJob& jb, int node, int P) {
+  return io.off + ((int64_t)node * 2 + jb.side) * P * io.sp;
 }
 
 }  // namespace
@@ -75,13 +78,14 @@ __device__ inline int64_t coef_base(const int64_t* off, const FmmJob& jb, int no
 // P2M at the leaves: W_S = sum_{j in S} ell^S(y_j) q_j for one 32-column chunk.
 // 256 threads; thread (k0, c) = (tid / 32, tid % 32) owns rows k0 + 8 r.
 __global__ __launch_bounds__(256) void k_fmm_p2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                                                 int P, double* __restrict__ W, const int64_t* __restrict__ off) {
+                                                 const FmmIo* __restrict__ io, int P, double* __restrict__ W) {
   __shared__ double t[PMAX], beta[PMAX];
   __shared__ double ell[PMAX * PCH];
   __shared__ double q[PCH * CW];
   const FmmJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
   const HssNode nd = M.nodes[jb.node];
+  const FmmIo IO = io[jb.merge];
   cheb_init(P, t, beta);
   const double h = half_width(M, nd);
   const double a = M.d[nd.lo];
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const HssMerge* __restrict__ ms
     }
     for (int e = tid; e < nj * CW; e += blockDim.x) {
       const int j = e / CW, cc = e % CW;
-      q[e] = wgt[j0 + j] * M.omega[(int64_t)(j0 + j) * M.sp + jb.c0 + cc];
+      q[e] = wgt[j0 + j] * IO.omega[(int64_t)(j0 + j) * IO.sp + jb.c0 + cc];
     }
     __syncthreads();
 #pragma unroll
@@ -114,22 +118,24 @@ __global__ __launch_bounds__(256) void k_fmm_p2m(const HssMerge* __restrict__ ms
     }
     __syncthreads();
   }
-  double* Wn = W + coef_base(off, jb, jb.node, P, M.sp);
+  double* Wn = W + coef_base(IO, jb, jb.node, P);
 #pragma unroll
   for (int r = 0; r < PMAX / 8; ++r) {
     const int k = k0 + 8 * r;
-    if (k < P) Wn[(int64_t)k * M.sp + jb.c0 + c] = acc[r];
+    if (k < P) Wn[(int64_t)k * IO.sp + jb.c0 + c] = acc[r];
   }
 }
 
 // M2M: W_P = sum over the two children C of E_PC W_C,
 // E_PC[k][l] = ell_k^P(tau_l^C + d_lo(C) - d_lo(P)).
 __global__ __launch_bounds__(256) void k_fmm_m2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                                                 int P, double* __restrict__ W, const int64_t* __restrict__ off) {
+                                                 const FmmIo* __restrict__ io, int P, double* __restrict__ W) {
   __shared__ double t[PMAX], beta[PMAX];
   __shared__ double E[2 * PMAX * PMAX];
   const FmmJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
+  const FmmIo IO = io[jb.merge];
+  const int sp = IO.sp;
   const HssNode nd = M.nodes[jb.node];
   cheb_init(P, t, beta);
   __syncthreads();
@@ -144,19 +150,19 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(const HssMerge* __restrict__ ms
   }
   __syncthreads();
   const int c = tid % CW, k0 = tid / CW;
-  const double* W1 = W + coef_base(off, jb, 2 * jb.node + 1, P, M.sp) + jb.c0 + c;
-  const double* W2 = W + coef_base(off, jb, 2 * jb.node + 2, P, M.sp) + jb.c0 + c;
-  double* Wn = W + coef_base(off, jb, jb.node, P, M.sp) + jb.c0 + c;
+  const double* W1 = W + coef_base(IO, jb, 2 * jb.node + 1, P) + jb.c0 + c;
+  const double* W2 = W + coef_base(IO, jb, 2 * jb.node + 2, P) + jb.c0 + c;
+  double* Wn = W + coef_base(IO, jb, jb.node, P) + jb.c0 + c;
 #pragma unroll
   for (int r = 0; r < PMAX / 8; ++r) {
     const int k = k0 + 8 * r;
     if (k < P) {
       double s = 0.0;
       for (int l = 0; l < P; ++l) {
-        s = fma(E[k * PMAX + l], W1[(int64_t)l * M.sp], s);
-        s = fma(E[PMAX * PMAX + k * PMAX + l], W2[(int64_t)l * M.sp], s);
+        s = fma(E[k * PMAX + l], W1[(int64_t)l * sp], s);
+        s = fma(E[PMAX * PMAX + k * PMAX + l], W2[(int64_t)l * sp], s);
       }
-      Wn[(int64_t)k * M.sp] = s;
+      Wn[(int64_t)k * sp] = s;
     }
   }
 }
@@ -165,13 +171,14 @@ __global__ __launch_bounds__(256) void k_fmm_m2m(const HssMerge* __restrict__ ms
 // G_TS[l][k] = sigma / ((d_lo(T) - d_lo(S)) + (tau_l^T - tau_k^S)); sigma = +1
 // for side 0, -1 for side 1.  Writes F_T (zero for an empty list).
 __global__ __launch_bounds__(256) void k_fmm_m2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                                                 const int32_t* __restrict__ lists, int P,
-                                                 const double* __restrict__ W, double* __restrict__ F,
-                                                 const int64_t* __restrict__ off) {
+                                                 const int32_t* __restrict__ lists, const FmmIo* __restrict__ io,
+                                                 int P, const double* __restrict__ W, double* __restrict__ F) {
   __shared__ double t[PMAX], beta[PMAX];
   __shared__ double G[PMAX * PMAX];
   const FmmJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
+  const FmmIo IO = io[jb.merge];
+  const int sp = IO.sp;
   const HssNode nd = M.nodes[jb.node];
   cheb_init(P, t, beta);
   const double hT = half_width(M, nd);
@@ -192,33 +199,35 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(const HssMerge* __restrict__ ms
       G[l * PMAX + k] = sigma / (shift + (hT * (1.0 + t[l]) - hS * (1.0 + t[k])));
     }
     __syncthreads();
-    const double* Ws = W + coef_base(off, jb, sn, P, M.sp) + jb.c0 + c;
+    const double* Ws = W + coef_base(IO, jb, sn, P) + jb.c0 + c;
 #pragma unroll
     for (int r = 0; r < PMAX / 8; ++r) {
       const int l = k0 + 8 * r;
       if (l < P) {
         double s = acc[r];
-        for (int k = 0; k < P; ++k) s = fma(G[l * PMAX + k], Ws[(int64_t)k * M.sp], s);
+        for (int k = 0; k < P; ++k) s = fma(G[l * PMAX + k], Ws[(int64_t)k * sp], s);
         acc[r] = s;
       }
     }
     __syncthreads();
   }
-  double* Fn = F + coef_base(off, jb, jb.node, P, M.sp) + jb.c0 + c;
+  double* Fn = F + coef_base(IO, jb, jb.node, P) + jb.c0 + c;
 #pragma unroll
   for (int r = 0; r < PMAX / 8; ++r) {
     const int l = k0 + 8 * r;
-    if (l < P) Fn[(int64_t)l * M.sp] = acc[r];
+    if (l < P) Fn[(int64_t)l * sp] = acc[r];
   }
 }
 
 // L2L: F_C += E_PC^T F_P for the child C of the job (its parent's F is final).
 __global__ __launch_bounds__(256) void k_fmm_l2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                                                 int P, double* __restrict__ F, const int64_t* __restrict__ off) {
+                                                 const FmmIo* __restrict__ io, int P, double* __restrict__ F) {
   __shared__ double t[PMAX], beta[PMAX];
   __shared__ double E[PMAX * PMAX];
   const FmmJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
+  const FmmIo IO = io[jb.merge];
+  const int sp = IO.sp;
   const int pn = (jb.node - 1) / 2;
   const HssNode ch = M.nodes[jb.node];
   const HssNode par = M.nodes[pn];
@@ -232,15 +241,15 @@ __global__ __launch_bounds__(256) void k_fmm_l2l(const HssMerge* __restrict__ ms
   }
   __syncthreads();
   const int c = tid % CW, k0 = tid / CW;
-  const double* Fp = F + coef_base(off, jb, pn, P, M.sp) + jb.c0 + c;
-  double* Fc = F + coef_base(off, jb, jb.node, P, M.sp) + jb.c0 + c;
+  const double* Fp = F + coef_base(IO, jb, pn, P) + jb.c0 + c;
+  double* Fc = F + coef_base(IO, jb, jb.node, P) + jb.c0 + c;
 #pragma unroll
   for (int r = 0; r < PMAX / 8; ++r) {
     const int l = k0 + 8 * r;
     if (l < P) {
-      double s = Fc[(int64_t)l * M.sp];
-      for (int k = 0; k < P; ++k) s = fma(E[k * PMAX + l], Fp[(int64_t)k * M.sp], s);
-      Fc[(int64_t)l * M.sp] = s;
+      double s = Fc[(int64_t)l * sp];
+      for (int k = 0; k < P; ++k) s = fma(E[k * PMAX + l], Fp[(int64_t)k * sp], s);
+      Fc[(int64_t)l * sp] = s;
     }
   }
 }
@@ -250,8 +259,8 @@ __global__ __launch_bounds__(256) void k_fmm_l2l(const HssMerge* __restrict__ ms
 // writes the leaf's rows of Phi or Theta for one 32-column chunk.  128
 // threads, one target row each (leaves longer than 128 rows take passes).
 __global__ __launch_bounds__(128) void k_fmm_leaf(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                                                  const int32_t* __restrict__ lists, int P,
-                                                  const double* __restrict__ F, const int64_t* __restrict__ off) {
+                                                  const int32_t* __restrict__ lists, const FmmIo* __restrict__ io,
+                                                  int P, const double* __restrict__ F) {
   __shared__ double t[PMAX], beta[PMAX];
   __shared__ double Fl[PMAX * CW];
   __shared__ double qs[NCH * CW];
@@ -259,14 +268,15 @@ __global__ __launch_bounds__(128) void k_fmm_leaf(const HssMerge* __restrict__ m
   const FmmJob jb = jobs[blockIdx.x];
   const HssMerge& M = ms[jb.merge];
   const HssNode T = M.nodes[jb.node];
-  const int K = M.K, sp = M.sp;
+  const FmmIo IO = io[jb.merge];
+  const int K = M.K, sp = IO.sp;
   cheb_init(P, t, beta);
-  const double* Fn = F + coef_base(off, jb, jb.node, P, sp) + jb.c0;
+  const double* Fn = F + coef_base(IO, jb, jb.node, P) + jb.c0;
   for (int e = threadIdx.x; e < P * CW; e += blockDim.x) Fl[e] = Fn[(int64_t)(e / CW) * sp + e % CW];
   const double hT = half_width(M, T);
   const double aT = M.d[T.lo];
   const double* wgt = jb.side == 0 ? M.v : M.uh;
-  double* out = jb.side == 0 ? M.phi : M.theta;
+  double* out = IO.out[jb.side];
   __syncthreads();
   for (int row0 = T.lo; row0 < T.hi; row0 += blockDim.x) {
     const int i = row0 + threadIdx.x;
@@ -300,7 +310,6 @@ __global__ __launch_bounds__(128) void k_fmm_leaf(const HssMerge* __restrict__ m
     }
     for (int e = 0; e < jb.lcnt; ++e) {
       const HssNode S = M.nodes[lists[jb.loff + e]];
-      const bool s_after = S.lo >= T.hi;
       for (int j0 = S.lo; j0 < S.hi; j0 += NCH) {
         const int nj = min(NCH, S.hi - j0);
         __syncthreads();
@@ -313,16 +322,17 @@ __global__ __launch_bounds__(128) void k_fmm_leaf(const HssMerge* __restrict__ m
         }
         for (int x2 = threadIdx.x; x2 < nj * CW; x2 += blockDim.x) {
           const int j = x2 / CW, cc = x2 % CW;
-          qs[x2] = wgt[j0 + j] * M.omega[(int64_t)(j0 + j) * sp + jb.c0 + cc];
+          qs[x2] = wgt[j0 + j] * IO.omega[(int64_t)(j0 + j) * sp + jb.c0 + cc];
         }
         __syncthreads();
         if (active) {
           for (int j = 0; j < nj; ++j) {
+            const int gj = j0 + j;
             double df;
-            if (jb.side == 0)  // target pole i, source root j
-              df = s_after ? (td - s0[j]) - s1[j] : (td - s2[j]) + s3[j];
-            else  // target root i, source pole j
-              df = s_after ? (s0[j] - tdn) + tm : (s0[j] - td) - tg;
+            if (jb.side == 0)  // target pole i, source root gj: d_i - lam_gj
+              df = (i <= gj) ? (td - s0[j]) - s1[j] : (td - s2[j]) + s3[j];
+            else  // target root i, source pole gj: d_gj - lam_i
+              df = (gj <= i) ? (s0[j] - td) - tg : (s0[j] - tdn) + tm;
             const double inv = 1.0 / df;
 #pragma unroll
             for (int c = 0; c < CW; ++c) acc[c] = fma(inv, qs[j * CW + c], acc[c]);

@@ -278,20 +278,23 @@ static adc_status sample_direct(adc_ctx c, HssBatch& hb) {
   return ADC_OK;
 }
 
-// Fast sampling (one-dimensional Chebyshev FMM over each merge's HSS tree):
-// P2M at the leaves, M2M by height, M2L over the far lists, L2L by depth,
-// then the leaves' local expansions and near fields.  Every job covers one
-// (node, side, 32-column chunk).
-static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
+// Fast Cauchy products (one-dimensional Chebyshev FMM over each merge's HSS
+// tree): P2M at the leaves, M2M by height, M2L over the far lists, L2L by
+// depth, then the leaves' local expansions and near fields.  Sides
+// side_lo..side_hi (0: Phi-type, targets d; 1: Theta-type, targets lam).
+// io[g] gives merge g's Omega, outputs and leading dimension sp (a multiple
+// of 32); every job covers one (node, side, 32-column chunk).  `host` keeps
+// the launch lists alive until the stream has consumed them.
+static adc_status fmm_run(adc_ctx c, HssBatch& hb, std::vector<FmmIo>& io, int side_lo, int side_hi,
+                          std::vector<char>& host, int kt_leaf) {
   hipStream_t st = c->stream;
   const int P = hb.fmm_p;
   const int nm = (int)hb.ms.size();
-  std::vector<int64_t> off(nm);
   int64_t tot = 0;
   int Lmax = 0;
   for (int g = 0; g < nm; ++g) {
-    off[g] = tot;
-    tot += (int64_t)hb.ms[g].nodes.size() * 2 * P * hb.ms[g].sp;
+    io[g].off = tot;
+    tot += (int64_t)hb.ms[g].nodes.size() * 2 * P * io[g].sp;
     Lmax = std::max(Lmax, hb.ms[g].L);
   }
   double* W;
@@ -307,6 +310,7 @@ static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
     if ((int64_t)m.hd.size() != m.K || (int64_t)m.hg.size() != m.K || (int64_t)m.hmu.size() != m.K)
       return ADC_ERR_ARG;
     fmm_lists(m.hd.data(), m.hg.data(), m.hmu.data(), m.nodes, far, near);
+    const int ncol = io[g].sp == m.sp ? m.s : io[g].sp;  // columns that carry data
     for (int q = 0; q < (int)m.nodes.size(); ++q) {
       const HssNode& nd = m.nodes[q];
       int l = 0;
@@ -315,8 +319,8 @@ static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
       lists.insert(lists.end(), far[q].begin(), far[q].end());
       const int noff = (int)lists.size();
       lists.insert(lists.end(), near[q].begin(), near[q].end());
-      for (int side = 0; side < 2; ++side)
-        for (int c0 = 0; c0 < m.sp; c0 += 32) {
+      for (int side = side_lo; side <= side_hi; ++side)
+        for (int c0 = 0; c0 < io[g].sp; c0 += 32) {
           if (nd.leaf) {
             p2m.push_back(FmmJob{g, q, side, c0, 0, 0});
             leaf.push_back(FmmJob{g, q, side, c0, noff, (int)near[q].size()});
@@ -326,20 +330,20 @@ static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
           if (l >= 1) m2l.push_back(FmmJob{g, q, side, c0, foff, (int)far[q].size()});
           if (l >= 2) l2l[l].push_back(FmmJob{g, q, side, c0, 0, 0});
         }
-      for (int32_t sn : near[q]) near_fl += 2.0 * 2.0 * m.s * (double)(nd.hi - nd.lo) * (m.nodes[sn].hi - m.nodes[sn].lo);
-      m2l_fl += 2.0 * 2.0 * m.s * (double)P * P * far[q].size();
+      const double sides = side_hi - side_lo + 1;
+      for (int32_t sn : near[q]) near_fl += sides * 2.0 * ncol * (double)(nd.hi - nd.lo) * (m.nodes[sn].hi - m.nodes[sn].lo);
+      m2l_fl += sides * 2.0 * ncol * (double)P * P * far[q].size();
     }
   }
-  // one upload: offsets, lists and every job array
-  std::vector<char>& hj = hb.sample_host;
-  hj.clear();
+  // one upload: operand descriptors, lists and every job array
+  host.clear();
   auto put = [&](const void* src, size_t n) {
-    const size_t o = hj.size();
-    hj.resize((o + n + 255) & ~(size_t)255);
-    if (n) std::memcpy(hj.data() + o, src, n);
+    const size_t o = host.size();
+    host.resize((o + n + 255) & ~(size_t)255);
+    if (n) std::memcpy(host.data() + o, src, n);
     return o;
   };
-  const size_t o_off = put(off.data(), off.size() * sizeof(int64_t));
+  const size_t o_io = put(io.data(), io.size() * sizeof(FmmIo));
   const size_t o_lists = put(lists.data(), lists.size() * sizeof(int32_t));
   const size_t o_p2m = put(p2m.data(), p2m.size() * sizeof(FmmJob));
   const size_t o_m2l = put(m2l.data(), m2l.size() * sizeof(FmmJob));
@@ -348,34 +352,43 @@ static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
   for (int h = 0; h <= Lmax; ++h) o_m2m[h] = put(m2m[h].data(), m2m[h].size() * sizeof(FmmJob));
   for (int l = 0; l <= Lmax; ++l) o_l2l[l] = put(l2l[l].data(), l2l[l].size() * sizeof(FmmJob));
   void* dp;
-  ADC_TRY(c->buffer(SLOT_SAMPLE_JOBS, hj.size() + 256, &dp));
+  ADC_TRY(c->buffer(SLOT_SAMPLE_JOBS, host.size() + 256, &dp));
   char* dj = (char*)dp;
-  HIP_OK(hipMemcpyAsync(dj, hj.data(), hj.size(), hipMemcpyHostToDevice, st));
-  const int64_t* d_off = (const int64_t*)(dj + o_off);
+  HIP_OK(hipMemcpyAsync(dj, host.data(), host.size(), hipMemcpyHostToDevice, st));
+  const FmmIo* d_io = (const FmmIo*)(dj + o_io);
   const int32_t* d_lists = (const int32_t*)(dj + o_lists);
   if (!p2m.empty())
     hipLaunchKernelGGL(k_fmm_p2m, dim3((unsigned)p2m.size()), dim3(256), 0, st, hb.d_ms,
-                       (const FmmJob*)(dj + o_p2m), P, W, d_off);
+                       (const FmmJob*)(dj + o_p2m), d_io, P, W);
   for (int h = 1; h <= Lmax; ++h)
     if (!m2m[h].empty())
       hipLaunchKernelGGL(k_fmm_m2m, dim3((unsigned)m2m[h].size()), dim3(256), 0, st, hb.d_ms,
-                         (const FmmJob*)(dj + o_m2m[h]), P, W, d_off);
+                         (const FmmJob*)(dj + o_m2m[h]), d_io, P, W);
   if (!m2l.empty()) {
     c->ktimer.pre(st);
     hipLaunchKernelGGL(k_fmm_m2l, dim3((unsigned)m2l.size()), dim3(256), 0, st, hb.d_ms,
-                       (const FmmJob*)(dj + o_m2l), d_lists, P, (const double*)W, F, d_off);
+                       (const FmmJob*)(dj + o_m2l), d_lists, d_io, P, (const double*)W, F);
     c->ktimer.post(st, KT_FMMM2L, m2l_fl, 0.0);
   }
   for (int l = 2; l <= Lmax; ++l)
     if (!l2l[l].empty())
       hipLaunchKernelGGL(k_fmm_l2l, dim3((unsigned)l2l[l].size()), dim3(256), 0, st, hb.d_ms,
-                         (const FmmJob*)(dj + o_l2l[l]), P, F, d_off);
-  c->ktimer.pre(st);
+                         (const FmmJob*)(dj + o_l2l[l]), d_io, P, F);
+  if (kt_leaf >= 0) c->ktimer.pre(st);
   hipLaunchKernelGGL(k_fmm_leaf, dim3((unsigned)leaf.size()), dim3(128), 0, st, hb.d_ms,
-                     (const FmmJob*)(dj + o_leaf), d_lists, P, (const double*)F, d_off);
-  c->ktimer.post(st, KT_FMMLEAF, near_fl, 0.0);
+                     (const FmmJob*)(dj + o_leaf), d_lists, d_io, P, (const double*)F);
+  if (kt_leaf >= 0) c->ktimer.post(st, kt_leaf, near_fl, 0.0);
   HIP_OK(hipGetLastError());
   return ADC_OK;
+}
+
+static adc_status sample_fmm(adc_ctx c, HssBatch& hb) {
+  std::vector<FmmIo> io(hb.ms.size());
+  for (size_t g = 0; g < hb.ms.size(); ++g) {
+    const auto& m = hb.ms[g];
+    io[g] = FmmIo{m.dev.omega, {m.dev.phi, m.dev.theta}, 0, m.sp, 0};
+  }
+  return fmm_run(c, hb, io, 0, 1, hb.sample_host, KT_FMMLEAF);
 }
 
 static adc_status batch_sample(adc_ctx c, HssBatch& hb) {
@@ -842,7 +855,9 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
     aj.push_back(ApplyJob{g, W, SP_PROBE, SP_PROBE, WH, SP_PROBE, nullptr});
   }
   // W^T Q' per merge: FP64 vector kernel over the generated entries (four
-  // probes do not fill a matrix-core tile), then the padding columns zeroed
+  // probes do not fill a matrix-core tile), then the padding columns zeroed.
+  // (The FMM of the sampling, with diagonal blocks, was measured slower here:
+  // its per-level launch chain outweighs the 4-column direct product.)
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
     double* W = buf + base[g];

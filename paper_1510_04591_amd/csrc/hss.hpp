@@ -98,18 +98,27 @@ struct FmmJob {
   int32_t loff;  // offset of the node's far (M2L) or near (leaf) list
   int32_t lcnt;  // its length
 };
-__global__ void k_fmm_p2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs, int P,
-                          double* __restrict__ W, const int64_t* __restrict__ off);
-__global__ void k_fmm_m2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs, int P,
-                          double* __restrict__ W, const int64_t* __restrict__ off);
+// Operands of one merge's fast product: omega (K x sp row-major) in, out[side]
+// (K x sp row-major) written; coefficient storage at off.
+struct FmmIo {
+  const double* omega;
+  double* out[2];
+  int64_t off;
+  int32_t sp;
+  int32_t pad;
+};
+__global__ void k_fmm_p2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
+                          const FmmIo* __restrict__ io, int P, double* __restrict__ W);
+__global__ void k_fmm_m2m(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
+                          const FmmIo* __restrict__ io, int P, double* __restrict__ W);
 __global__ void k_fmm_m2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                          const int32_t* __restrict__ lists, int P, const double* __restrict__ W,
-                          double* __restrict__ F, const int64_t* __restrict__ off);
-__global__ void k_fmm_l2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs, int P,
-                          double* __restrict__ F, const int64_t* __restrict__ off);
+                          const int32_t* __restrict__ lists, const FmmIo* __restrict__ io, int P,
+                          const double* __restrict__ W, double* __restrict__ F);
+__global__ void k_fmm_l2l(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
+                          const FmmIo* __restrict__ io, int P, double* __restrict__ F);
 __global__ void k_fmm_leaf(const HssMerge* __restrict__ ms, const FmmJob* __restrict__ jobs,
-                           const int32_t* __restrict__ lists, int P, const double* __restrict__ F,
-                           const int64_t* __restrict__ off);
+                           const int32_t* __restrict__ lists, const FmmIo* __restrict__ io, int P,
+                           const double* __restrict__ F);
 void fmm_lists(const double* d, const double* gam, const double* mu, const std::vector<HssNode>& nodes,
                std::vector<std::vector<int32_t>>& far, std::vector<std::vector<int32_t>>& near);
 

@@ -129,3 +129,22 @@ def test_solver_with_fast_sampling(ctx, N):
     print("  ", res, flush=True)
     for resid, orth, _, _ in res.values():
         assert resid <= 1e-13 and orth <= 1e-12
+
+
+def test_hss_from_fast_samples_as_accurate_as_from_direct(ctx):
+    """adc_hss_build with fast and with direct sampling: the adaptive check
+    measures the same approximation error."""
+    gen = generators(*merge_case("example1"))
+    d, uh, gam, mu, v = gen
+    K = len(d)
+    errs = {}
+    for mode in (adc.ADC_SAMPLE_FMM, adc.ADC_SAMPLE_DIRECT):
+        o = adc.opts(hss_leaf=64, sample_mode=mode)
+        st, h = adc.adc_hss_build(ctx.h, K, cuda(d), cuda(gam), cuda(mu), cuda(uh), cuda(v), None, 0, o)
+        assert st == adc.ADC_OK
+        errs[mode] = adc.adc_hss_info(h)["check_err"]
+        adc.adc_hss_free(h)
+    print("  check errors", errs, flush=True)
+    e1, e2 = errs[adc.ADC_SAMPLE_FMM], errs[adc.ADC_SAMPLE_DIRECT]
+    assert 0 < e1 <= 1e-13 and 0 < e2 <= 1e-13
+    assert abs(e1 - e2) <= 0.5 * max(e1, e2)
