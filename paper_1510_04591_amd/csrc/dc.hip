@@ -176,7 +176,9 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   HIP_OK(hipMemcpyAsync(dg, &P, sizeof(P), hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(dtm, tm.data(), nt * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(dtc, tc.data(), nt * 4, hipMemcpyHostToDevice, st));
-  // rows of qc in the packed order of the merge's columns
+  // rows of qc in the packed order of the merge's columns; the packed
+  // columns' unsupported halves zeroed, since this product reads all n rows
+  hipLaunchKernelGGL(k_zero_unsupported, dim3((unsigned)M.K), dim3(256), 0, st, d_m, g, B);
   hipLaunchKernelGGL(k_cauchy, dim3((unsigned)nt), dim3(256), 0, st, d_m, dtm, dtc, B, ncols, 1);
   hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, st, dg, 1);
   HIP_OK(hipGetLastError());

@@ -130,6 +130,8 @@ __global__ void k_leaf_bounds(const MergeDev* __restrict__ merges, const int32_t
                               double thresh, int shift_max);
 __global__ void k_leaf_group(const MergeDev* __restrict__ merges, const int2* __restrict__ jobs, LevelBufs B);
 
+__global__ void k_zero_unsupported(const MergeDev* __restrict__ merges, int g, LevelBufs B);
+
 __global__ void k_pack_rot(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
                            const int32_t* __restrict__ col_idx, LevelBufs B);
 

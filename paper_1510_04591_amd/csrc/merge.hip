@@ -562,6 +562,22 @@ __global__ void __launch_bounds__(512) k_leaf_group(const MergeDev* __restrict__
   }
 }
 
+// The zero rows of the packed operand of merge `g` (rows outside each
+// column's support, which the packing leaves unwritten), for a product that
+// reads whole columns.  One workgroup per packed column.
+__global__ void __launch_bounds__(256) k_zero_unsupported(const MergeDev* __restrict__ merges, int g, LevelBufs B) {
+  const MergeDev& M = merges[g];
+  const int c = blockIdx.x;
+  if (c >= M.K) return;
+  const int64_t s0 = M.s0;
+  const int f = B.supp[s0 + B.surv[s0 + B.gorder[s0 + c]]];
+  const int n = M.n, n1 = M.n1;
+  double* col = B.pk + M.zoff + (int64_t)c * n;
+  const int lo = (f & 1) ? n1 : 0, hi = (f & 2) ? n1 : n;  // the unsupported half
+  if (f == 3) return;
+  for (int r = lo + threadIdx.x; r < hi; r += blockDim.x) col[r] = 0.0;
+}
+
 // Packing with the type-2 rotations applied on the fly.  One block per sorted
 // position of the level (job -> merge col_merge[job], position col_idx[job]).
 // A position untouched by rotations copies its column; the first position of
@@ -596,9 +612,11 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
     const double* __restrict__ sc = src_of(p);
     double* __restrict__ dc = dst_of(p);
     const int f = supp_of(p);
-    // rows outside the support are zero; the dense path's grouped GEMM never
-    // reads them in a packed column, every other destination needs them
-    const bool zero = !(B.pidx[s0 + p] >= 0 && M.mode == 0);
+    // rows outside the support are zero; no product reads them in a packed
+    // column (the grouped GEMMs of the dense update and the row-half
+    // products of Algorithm 3 skip them; the dense fallback of a failed HSS
+    // merge fills them first), a deflated column's final place needs them
+    const bool zero = B.pidx[s0 + p] < 0;
     const int lo = (f & 1) ? 0 : n1, hi = (f & 2) ? n : n1;
     if (zero) {
       for (int r = tid; r < lo; r += bs) dc[r] = 0.0;

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import dc as odc, hss as ohss, rng as orng, secular as osec
+from oracle import dc as odc, hss as ohss, rng as orng, secular as osec, sturm
 from paper_1510_04591_amd import adc, workloads
 from conftest import cuda
 
@@ -138,3 +138,25 @@ def test_stedc_hss_retries_rebuild_failing_merges(ctx, rank):
     assert np.max(np.abs(w - exact)) <= 1e-13 * 4
     assert odc.residual(a, b, w, Z) <= 1e-13
     assert odc.orthogonality(Z) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["toeplitz", "legendre"])
+def test_stedc_dense_fallback_after_failed_check(ctx, case):
+    """Two samples and no retries: every HSS merge fails the check and falls
+    back to the dense update of its packed (leaf-grouped) columns, whose
+    unsupported halves are zero-filled first; the result stays exact.  With
+    strict, the failed check is an error."""
+    print(f"stedc dense fallback {case}", flush=True)
+    N = 6000
+    a, b = workloads.toeplitz(N) if case == "toeplitz" else workloads.legendre(N)
+    kw = dict(hss_leaf=128, hss_min_k=1024, hss_levels=-1, hss_min_flops=0, rank_mode=adc.ADC_RANK_FIXED,
+              fixed_rank=2, oversample=0, max_retries=0)
+    w, Z, rep = solve(ctx, a, b, **kw)
+    assert rep["hss_merges"] >= 1 and rep["hss_fallbacks"] == rep["hss_merges"]
+    ks = np.array([0, 1, N // 3, N // 2, N - 1])
+    assert np.max(np.abs(w[ks] - sturm.eigenvalues_by_index(a, b, ks))) <= 1e-13 * odc.tnorm1(a, b)
+    assert odc.residual(a, b, w, Z) <= 1e-13
+    assert odc.orthogonality(Z) <= 1e-12
+    with pytest.raises(adc.AdcError) as ei:
+        adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), strict=1, **kw)
+    assert ei.value.status == adc.ADC_ERR_ACCURACY
