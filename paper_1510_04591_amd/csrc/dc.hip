@@ -499,9 +499,16 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       c->timer.mark(st, 3);
     }
     hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
-    // packing: every column's support rows read once, all n rows written
+    // packing: a survivor column reads and writes its support rows (top
+    // half, bottom half or both), a deflated column reads its child's half
+    // and writes all n rows of its final place
     double pack_by = 0.0;
-    for (int g2 = 0; g2 < nm; ++g2) pack_by += 12.0 * (double)h_m[g2].n * h_m[g2].n;
+    for (int g2 = 0; g2 < nm; ++g2) {
+      const MergeDev& M = h_m[g2];
+      const double n1 = M.n1, n2 = M.n - M.n1;
+      pack_by += 8.0 * (2.0 * ((double)M.k1 * n1 + (double)M.k2 * M.n + (double)M.k3 * n2) +
+                        (double)(M.n - M.K) * (0.5 * M.n + M.n));
+    }
     if (!lg_jobs.empty()) {
       hipLaunchKernelGGL(k_leaf_bounds, dim3((unsigned)lg_merges.size()), dim3(64), 0, st, d_m, d_lgm, B,
                          o.shift_thresh, o.shift_max);
