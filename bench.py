@@ -32,21 +32,19 @@ sys.path.insert(0, ROOT)
 # kernel and its launches are unchanged (first 16 hex digits of their
 # SHA-256); otherwise the traffic is reported as null.
 TRAFFIC = {
-    "k_gemm_f64_n64": {"bytes_per_launch": 467.1e6,
-                       "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "d193b9f0441b2099"}},
-    "k_gemm_f64": {"bytes_per_launch": 1140.0e6,
-                   "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "d193b9f0441b2099"}},
-    "k_gemm_f64_n96": {"bytes_per_launch": 147.6e6,
-                       "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "d193b9f0441b2099"}},
-    "k_hss_sample": {"bytes_per_launch": 264.3e6,
-                     "sources": {"hss_kernels.hip": "764103e1389605a7", "hss.hip": "d193b9f0441b2099"}},
-    "k_pack_rot": {"bytes_per_launch": 2569.6e6,
-                   "sources": {"merge.hip": "5ccb844d13b5b4bc", "dc.hip": "b04feee61a3c93c0"}},
+    "k_gemm_f64_n64": {"bytes_per_launch": 440.2e6,
+                       "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "c377eeabdb91edb7"}},
+    "k_gemm_f64": {"bytes_per_launch": 1034.2e6,
+                   "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "c377eeabdb91edb7"}},
+    "k_gemm_f64_n96": {"bytes_per_launch": 152.2e6,
+                       "sources": {"gemm.hip": "ea8b930235887c5b", "hss.hip": "c377eeabdb91edb7"}},
+    "k_pack_rot": {"bytes_per_launch": 2301.6e6,
+                   "sources": {"merge.hip": "2ef1343f8fbf01be", "dc.hip": "14dbbb08f0f98f83"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 31177.4e6,
-                       "sources": {"gemm.hip": "ea8b930235887c5b", "dc.hip": "b04feee61a3c93c0"}},
+    "k_gemm_f64_big": {"bytes_per_launch": 30835.3e6,
+                       "sources": {"gemm.hip": "ea8b930235887c5b", "dc.hip": "14dbbb08f0f98f83"}},
 }
 
 
