@@ -77,6 +77,7 @@ typedef enum adc_sample_mode { ADC_SAMPLE_DIRECT = 0, ADC_SAMPLE_FMM = 1 } adc_s
 typedef struct adc_opts {
   int32_t dc_leaf;       /* [32] DC leaf size m (Algorithm 1); 2..64            */
   int32_t hss_min_k;     /* [2048] HSS update only if the deflated size K >= this
+                            (and K >= 8 in any case)
                             (Section 4.3 uses "larger than 2000")             */
   int32_t hss_levels;    /* [-1] only the top hss_levels merge levels may use
                             HSS; <0 means every level                         */

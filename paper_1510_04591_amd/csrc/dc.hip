@@ -374,13 +374,14 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       return 2.0 * M.K * ((double)M.n1 * (M.k1 + M.k2) + (double)(M.n - M.n1) * (M.k2 + M.k3));
     };
     const bool level_ok = !o.force_dense && ((o.hss_levels < 0) || (t < o.hss_levels));
+    const int min_k = std::max(o.hss_min_k, 8);  // at least two leaves of four
     bool level_hss = false;
     for (int g2 = 0; g2 < nm; ++g2)
-      level_hss |= level_ok && h_m[g2].K >= o.hss_min_k && dense_flops(h_m[g2]) >= o.hss_min_flops;
+      level_hss |= level_ok && h_m[g2].K >= min_k && dense_flops(h_m[g2]) >= o.hss_min_flops;
     for (int g2 = 0; g2 < nm; ++g2) {
       MergeDev& M = h_m[g2];
       M.zoff = M.s0 * (int64_t)nmax;
-      M.mode = (level_hss && M.K >= o.hss_min_k && dense_flops(M) >= 0.25 * o.hss_min_flops) ? 1 : 0;
+      M.mode = (level_hss && M.K >= min_k && dense_flops(M) >= 0.25 * o.hss_min_flops) ? 1 : 0;
       hss_here += M.mode == 1;
       Kmax = std::max<int64_t>(Kmax, M.K);
       Ksum += M.K;
