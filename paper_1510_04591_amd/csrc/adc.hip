@@ -88,7 +88,27 @@ extern "C" adc_status adc_destroy(adc_ctx c) {
   return ADC_OK;
 }
 
+adc_status adc_ctx_s::side_stream() {
+  if (side) return ADC_OK;
+  if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+    side = nullptr;
+    return ADC_ERR_HIP;
+  }
+  if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+    return ADC_ERR_HIP;
+  return ADC_OK;
+}
+
 void adc_ctx_s::release() {
+  if (side) {
+    hipStreamSynchronize(side);
+    hipStreamDestroy(side);
+    side = nullptr;
+  }
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
+  ev_fork = ev_join = nullptr;
   for (auto& b : bufs) {
     if (b.ptr) hipFree(b.ptr);
     b.ptr = nullptr;

@@ -154,6 +154,11 @@ struct adc_ctx_s {
   void* batch_cache = nullptr;  // graph cache of the batched solver
   PhaseTimer timer;
   KernTimer ktimer;
+  // second stream (default priority) for work that overlaps the HSS
+  // construction inside one level; joined back before the level ends
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  adc_status side_stream();
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);
   adc_status stage2(size_t bytes, void** p);

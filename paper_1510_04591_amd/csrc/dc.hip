@@ -515,21 +515,49 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
                          o.shift_thresh, o.shift_max);
       hipLaunchKernelGGL(k_leaf_group, dim3((unsigned)lg_jobs.size()), dim3(512), 0, st, d_m, d_lg, B);
     }
-    c->ktimer.pre(st);
-    hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)njob), dim3(256), 0, st, d_m, d_cm, d_cc, B);
-    c->ktimer.post(st, KT_PACK, 0.0, pack_by);
-    HIP_OK(hipGetLastError());
-    if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, ncols, 1);
-    c->timer.mark(st, 9);
-    if (gtiles) {
-      c->ktimer.pre(st);
-      hipLaunchKernelGGL(k_gemm_f64_big, dim3(gtiles), dim3(1024), 0, st, d_gp, ngp);
-      c->ktimer.post(st, KT_GEMMBIG, lvl_gf, lvl_gb);
-    }
-    c->timer.mark(st, 4);
-    HIP_OK(hipGetLastError());
-    if (hss_here) {
-      ADC_TRY(hss_level_update(c, o, h_m, d_m, nm, B, t, rep, &flops, &bytes));
+    // The packing and the dense merges' update.  With HSS merges in the
+    // level they read nothing the HSS construction writes and vice versa:
+    // the HSS update starts them on the side stream once its sampling is
+    // queued (so that they overlap the latency-bound compression rather
+    // than the sampling) and waits for them only before its products read
+    // the packed operand.
+    auto pack = [&](hipStream_t sp) {
+      c->ktimer.pre(sp);
+      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)njob), dim3(256), 0, sp, d_m, d_cm, d_cc, B);
+      c->ktimer.post(sp, KT_PACK, 0.0, pack_by);
+      if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, sp, d_m, d_tm, d_tc, B, ncols, 1);
+    };
+    auto dense = [&](hipStream_t sp) {
+      if (!gtiles) return;
+      c->ktimer.pre(sp);
+      hipLaunchKernelGGL(k_gemm_f64_big, dim3(gtiles), dim3(1024), 0, sp, d_gp, ngp);
+      c->ktimer.post(sp, KT_GEMMBIG, lvl_gf, lvl_gb);
+    };
+    if (!hss_here) {
+      pack(st);
+      c->timer.mark(st, 9);
+      dense(st);
+      c->timer.mark(st, 4);
+      HIP_OK(hipGetLastError());
+    } else {
+      ADC_TRY(c->side_stream());
+      c->timer.mark(st, 9);
+      c->timer.mark(st, 4);
+      bool forked = false;
+      auto fork = [&]() {
+        if (forked) return;
+        forked = true;
+        hipEventRecord(c->ev_fork, st);
+        hipStreamWaitEvent(c->side, c->ev_fork, 0);
+        pack(c->side);
+        dense(c->side);
+        hipEventRecord(c->ev_join, c->side);
+      };
+      adc_status hs = hss_level_update(c, o, h_m, d_m, nm, B, t, rep, &flops, &bytes, fork, c->ev_join);
+      fork();                                         // when the update returned before sampling
+      HIP_OK(hipStreamWaitEvent(st, c->ev_join, 0));  // joined even when the update failed
+      HIP_OK(hipGetLastError());
+      ADC_TRY(hs);
     }
     HIP_OK(hipStreamSynchronize(st));  // staging buffer reused by the next level
     c->timer.collect(rep);

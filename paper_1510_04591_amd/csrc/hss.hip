@@ -108,6 +108,7 @@ struct HssBatch {
   char* mem = nullptr;
   HssMerge* d_ms = nullptr;
   int fmm_p = 0;                   // Chebyshev points per node; 0: direct sampling
+  std::function<void()> after_sampling;  // called once, after the first sampling pass is queued
   std::vector<char> sample_host;   // launch lists of the last sampling pass
 };
 
@@ -401,6 +402,10 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   const int nm = (int)hb.ms.size();
   ADC_TRY(batch_sample(c, hb));
   c->timer.mark(st, 5);
+  if (hb.after_sampling) {
+    hb.after_sampling();
+    hb.after_sampling = nullptr;
+  }
   // compression jobs per level
   int Lmax = 0;
   for (auto& m : hb.ms) Lmax = std::max(Lmax, m.L);
@@ -983,7 +988,8 @@ static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool c
 
 // ---------------------------------------------------------------------------
 adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
-                            const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes) {
+                            const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes,
+                            const std::function<void()>& after_sampling, hipEvent_t operand_ready) {
   (void)bytes;
   hipStream_t st = c->stream;
   HssBatch hb;
@@ -1026,6 +1032,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     hb.ms.push_back(std::move(m));
   }
   hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
+  hb.after_sampling = after_sampling;
   HssBatch rb;
   std::vector<int> rb_of;
   ADC_TRY(batch_build(c, hb, o, true, rep, flops, nullptr, &rb, &rb_of));
@@ -1065,6 +1072,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     }
   }
   if (!dense_fb.empty() && o.strict) return ADC_ERR_ACCURACY;
+  if (operand_ready) HIP_OK(hipStreamWaitEvent(st, operand_ready, 0));  // the packed operand
   double fm = 0.0;
   if (!aj.empty()) ADC_TRY(batch_apply(c, hb, aj, &fm));
   if (!ajr.empty()) ADC_TRY(batch_apply(c, rb, ajr, &fm));

@@ -1,6 +1,8 @@
 // Randomized HSS approximation of the Cauchy-like eigenvector matrix
 // (Algorithm 2) and its product from the right (Algorithm 3) on gfx950.
 #pragma once
+#include <functional>
+
 #include "adc_internal.hpp"
 
 // One HSS tree node (heap numbering inside its merge: root 0, children of p
@@ -126,5 +128,9 @@ void fmm_lists(const double* d, const double* gam, const double* mu, const std::
 // `leaf` rows: L = ceil(log2(K / leaf)) levels (at least one), balanced.
 std::vector<int> hss_leaf_bounds(int K, int leaf);
 
+// HSS update of the level's HSS merges.  `after_sampling` (may be empty) is
+// called once the first sampling pass is queued; the packed operand is ready
+// once `operand_ready` (may be null) has completed.
 adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDev* d_m, int nm,
-                            const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes);
+                            const LevelBufs& B, int depth, adc_report* rep, double* flops, double* bytes,
+                            const std::function<void()>& after_sampling, hipEvent_t operand_ready);
