@@ -580,14 +580,14 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
   };
   std::vector<Lay> lays(jobs.size());
   int64_t total = 0;
-  std::vector<int2> leafjobs;
-  std::vector<int64_t> doff, uoff;
-  // leaf data (D_i, and U_i in leaf-grouped row order) once per merge
-  std::vector<int64_t> leaf_base(hb.ms.size(), -1);
+  // leaf data once per (merge, flavour): D_i for jobs in index order (0), and
+  // D_i and U_i with rows in the leaf-grouped order for grouped jobs (1)
+  std::vector<int2> lj[2];
+  std::vector<int64_t> doff[2], uoff;
+  std::vector<int64_t> leaf_base(2 * hb.ms.size(), -1);
   int64_t dtotal = 0, utotal = 0;
-  const bool grouped = !jobs.empty() && jobs[0].half >= 0;
   for (size_t t = 0; t < jobs.size(); ++t) {
-    if ((jobs[t].half >= 0) != grouped) return ADC_ERR_ARG;
+    const int flav = jobs[t].half >= 0 ? 1 : 0;
     const auto& m = hb.ms[jobs[t].g];
     Lay& ly = lays[t];
     const int nn = (int)m.nodes.size();
@@ -608,39 +608,56 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       ly.lev_f[l] = total;
       total += sf * jobs[t].P;
     }
-    if (leaf_base[jobs[t].g] >= 0) continue;
-    leaf_base[jobs[t].g] = (int64_t)leafjobs.size();
-    if (grouped && (int)m.grp.size() != 3 * (1 << m.L)) return ADC_ERR_ARG;
+    int64_t& lb = leaf_base[2 * jobs[t].g + flav];
+    if (lb >= 0) continue;
+    lb = (int64_t)lj[flav].size();
+    if (flav && ((int)m.grp.size() != 3 * (1 << m.L) || !m.dev.perm)) return ADC_ERR_ARG;
     for (int q = (1 << m.L) - 1; q < (1 << (m.L + 1)) - 1; ++q) {
       const int mm = m.nodes[q].hi - m.nodes[q].lo;
-      leafjobs.push_back(int2{jobs[t].g, q});
-      doff.push_back(dtotal);
+      lj[flav].push_back(int2{jobs[t].g, q});
+      doff[flav].push_back(dtotal);
       dtotal += (int64_t)mm * mm;
-      uoff.push_back(utotal);
-      if (grouped) utotal += (int64_t)mm * m.nodes[q].kr;
+      if (flav) {
+        uoff.push_back(utotal);
+        utotal += (int64_t)mm * m.nodes[q].kr;
+      }
     }
   }
   void* wp;
-  const size_t lj_bytes = (leafjobs.size() * sizeof(int2) + 255) & ~(size_t)255;
-  const size_t of_bytes = (doff.size() * 8 + 255) & ~(size_t)255;
-  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal + utotal) * 8 + lj_bytes + 2 * of_bytes + 1024, &wp));
+  auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t lj_bytes = rup(lj[0].size() * sizeof(int2)) + rup(lj[1].size() * sizeof(int2));
+  const size_t of_bytes = rup(doff[0].size() * 8) + rup(doff[1].size() * 8) + rup(uoff.size() * 8);
+  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal + utotal) * 8 + lj_bytes + of_bytes + 1024, &wp));
   double* work = (double*)wp;
   double* dmat = work + total;
   double* uperm = dmat + dtotal;
   char* tail = (char*)(uperm + utotal);
-  int2* d_lj = (int2*)tail;
-  int64_t* d_doff = (int64_t*)(tail + lj_bytes);
-  int64_t* d_uoff = (int64_t*)(tail + lj_bytes + of_bytes);
-  HIP_OK(hipMemcpyAsync(d_lj, leafjobs.data(), leafjobs.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(d_doff, doff.data(), doff.size() * 8, hipMemcpyHostToDevice, st));
-  if (grouped) HIP_OK(hipMemcpyAsync(d_uoff, uoff.data(), uoff.size() * 8, hipMemcpyHostToDevice, st));
-  // D_i (rows in the packed order for grouped jobs) and the grouped U_i
-  hipLaunchKernelGGL(k_hss_dmat, dim3((unsigned)leafjobs.size()), dim3(256), 0, st, hb.d_ms, d_lj, dmat, d_doff,
-                     grouped ? 1 : 0);
-  if (grouped)
-    hipLaunchKernelGGL(k_hss_urows, dim3((unsigned)leafjobs.size()), dim3(256), 0, st, hb.d_ms, d_lj, uperm,
+  int2* d_lj[2];
+  int64_t* d_doff[2];
+  d_lj[0] = (int2*)tail;
+  d_lj[1] = (int2*)(tail + rup(lj[0].size() * sizeof(int2)));
+  char* t2 = tail + lj_bytes;
+  d_doff[0] = (int64_t*)t2;
+  d_doff[1] = (int64_t*)(t2 + rup(doff[0].size() * 8));
+  int64_t* d_uoff = (int64_t*)(t2 + rup(doff[0].size() * 8) + rup(doff[1].size() * 8));
+  // D_i of both flavours and the grouped U_i
+  for (int f = 0; f < 2; ++f) {
+    if (lj[f].empty()) continue;
+    HIP_OK(hipMemcpyAsync(d_lj[f], lj[f].data(), lj[f].size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(d_doff[f], doff[f].data(), doff[f].size() * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_hss_dmat, dim3((unsigned)lj[f].size()), dim3(256), 0, st, hb.d_ms, d_lj[f], dmat,
+                       d_doff[f], f);
+  }
+  if (!lj[1].empty()) {
+    HIP_OK(hipMemcpyAsync(d_uoff, uoff.data(), uoff.size() * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_hss_urows, dim3((unsigned)lj[1].size()), dim3(256), 0, st, hb.d_ms, d_lj[1], uperm,
                        d_uoff);
+  }
   HIP_OK(hipGetLastError());
+  auto dmat_of = [&](const ApplyJob& J, int li) {
+    const int f = J.half >= 0 ? 1 : 0;
+    return dmat + doff[f][leaf_base[2 * J.g + f] + li];
+  };
   // the leaf column range of a grouped job: top rows meet top-only and both,
   // bottom rows both and bottom-only
   auto leaf_range = [&](const ApplyJob& J, int li, int& kb, int& kl) {
@@ -696,14 +713,14 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         p.ldc = J.P;
         p.B = m.dev.arena + nd.offU;
         p.ldb = nd.nr;
-        if (nd.leaf && grouped) {
+        if (nd.leaf && J.half >= 0) {
           const int li = q - ((1 << m.L) - 1);
           int kb, kl;
           leaf_range(J, li, kb, kl);
           p.A = J.X + (int64_t)(nd.lo + kb) * J.ldx;
           p.lda = J.ldx;
           p.K = kl;
-          p.B = uperm + uoff[leaf_base[J.g] + li] + kb;
+          p.B = uperm + uoff[leaf_base[2 * J.g + 1] + li] + kb;
           p.ldb = nd.hi - nd.lo;
         } else if (nd.leaf) {
           p.A = J.X + (int64_t)nd.lo * J.ldx;
@@ -783,9 +800,9 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       p.K = mm;
       p.A = J.X + (int64_t)nd.lo * J.ldx;
       p.lda = J.ldx;
-      p.B = dmat + doff[leaf_base[J.g] + li];
+      p.B = dmat_of(J, li);
       p.ldb = mm;
-      if (grouped) {
+      if (J.half >= 0) {
         int kb, kl;
         leaf_range(J, li, kb, kl);
         p.A = J.X + (int64_t)(nd.lo + kb) * J.ldx;
@@ -825,33 +842,43 @@ static void draw_omega(adc_ctx c, const HssBatch::One& m, uint64_t seed) {
 }
 
 // Accuracy check of every merge: err = ||W^T (Q' - H)||_F / ||W^T Q'||_F for
-// nprobe Gaussian probes (stream 2*id + 1).
-static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double* flops) {
+// nprobe Gaussian probes (stream 2*id + 1).  In three parts so that the
+// probe products W^T H can share the launches of another HSS product:
+// check_prepare draws W, forms W^T Q' and appends one ApplyJob per merge
+// (W H into the check buffer); after those jobs have run, check_finish
+// reduces the norms and sets err and pass.
+struct CheckBufs {
+  double* buf = nullptr;
+  double* npart = nullptr;
+  double* norms = nullptr;
+  std::vector<int64_t> base;
+};
+constexpr int CHECK_NBLK = 128;  // blocks of the norm partial sums
+
+static adc_status check_prepare(adc_ctx c, HssBatch& hb, const adc_opts& o, CheckBufs& cb,
+                                std::vector<ApplyJob>& aj) {
   hipStream_t st = c->stream;
   const int nm = (int)hb.ms.size();
   int64_t tot = 0, part_max = 0;
-  std::vector<int64_t> base(nm);
+  cb.base.assign(nm, 0);
   std::vector<int> nseg(nm);
   for (int g = 0; g < nm; ++g) {
-    base[g] = tot;
+    cb.base[g] = tot;
     const int K = hb.ms[g].K;
     tot += 3 * (int64_t)K * SP_PROBE;
     // row segments so that a launch has about 2048 single-wave workgroups
     nseg[g] = std::max(1, std::min(64, (2048 + (K + 63) / 64 - 1) / ((K + 63) / 64)));
     part_max = std::max(part_max, (int64_t)nseg[g] * K * 8);
   }
-  constexpr int NBLK = 128;  // blocks of the norm partial sums
   void* p;
-  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)(tot + part_max + 2 * NBLK * nm) * 8 + nm * 16 + 1024, &p));
-  double* buf = (double*)p;
-  double* part = buf + tot;
-  double* npart = part + part_max;
-  double* norms = npart + 2 * NBLK * nm;
-  std::vector<SampleJob> sj;
-  std::vector<ApplyJob> aj;
+  ADC_TRY(c->buffer(SLOT_HSS_CHECK, (size_t)(tot + part_max + 2 * CHECK_NBLK * nm) * 8 + nm * 16 + 1024, &p));
+  cb.buf = (double*)p;
+  double* part = cb.buf + tot;
+  cb.npart = part + part_max;
+  cb.norms = cb.npart + 2 * CHECK_NBLK * nm;
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
-    double* W = buf + base[g];
+    double* W = cb.buf + cb.base[g];
     double* WQ = W + (int64_t)m.K * SP_PROBE;
     double* WH = WQ + (int64_t)m.K * SP_PROBE;
     const int64_t n = (int64_t)m.K * SP_PROBE;
@@ -865,7 +892,7 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
   // its per-level launch chain outweighs the 4-column direct product.)
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
-    double* W = buf + base[g];
+    double* W = cb.buf + cb.base[g];
     double* WQ = W + (int64_t)m.K * SP_PROBE;
     const int ntj = (m.K + 63) / 64;
     for (int c0 = 0; c0 < o.nprobe; c0 += 8) {
@@ -877,18 +904,24 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
     }
     HIP_OK(hipGetLastError());
   }
-  ADC_TRY(batch_apply(c, hb, aj, flops));
+  return ADC_OK;
+}
+
+static adc_status check_finish(adc_ctx c, HssBatch& hb, const adc_opts& o, const CheckBufs& cb) {
+  hipStream_t st = c->stream;
+  const int nm = (int)hb.ms.size();
   for (int g = 0; g < nm; ++g) {
-    double* W = buf + base[g];
+    double* W = cb.buf + cb.base[g];
     double* WQ = W + (int64_t)hb.ms[g].K * SP_PROBE;
     double* WH = WQ + (int64_t)hb.ms[g].K * SP_PROBE;
-    hipLaunchKernelGGL(k_diff_norms, dim3(NBLK), dim3(256), 0, st, WH, WQ, (int64_t)hb.ms[g].K, SP_PROBE, o.nprobe,
-                       npart + 2 * NBLK * g);
-    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, st, (const double*)(npart + 2 * NBLK * g), NBLK,
-                       norms + 2 * g);
+    hipLaunchKernelGGL(k_diff_norms, dim3(CHECK_NBLK), dim3(256), 0, st, WH, WQ, (int64_t)hb.ms[g].K, SP_PROBE,
+                       o.nprobe, cb.npart + 2 * CHECK_NBLK * g);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, st, (const double*)(cb.npart + 2 * CHECK_NBLK * g),
+                       CHECK_NBLK, cb.norms + 2 * g);
   }
+  HIP_OK(hipGetLastError());
   std::vector<double> hn(2 * nm);
-  HIP_OK(hipMemcpyAsync(hn.data(), norms, 2 * nm * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hn.data(), cb.norms, 2 * nm * 8, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
@@ -896,6 +929,14 @@ static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double
     m.pass = std::isfinite(m.err) && m.err <= o.check_tol;
   }
   return ADC_OK;
+}
+
+static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double* flops) {
+  CheckBufs cb;
+  std::vector<ApplyJob> aj;
+  ADC_TRY(check_prepare(c, hb, o, cb, aj));
+  ADC_TRY(batch_apply(c, hb, aj, flops));
+  return check_finish(c, hb, o, cb);
 }
 
 // One attempt for every merge of the batch with its current s: storage,
@@ -940,28 +981,29 @@ static bool grow_failing(HssBatch& hb) {
   return any;
 }
 
-// Build (construct + check + retries) for a batch whose merges have K, L,
-// bounds, r and stream set.  Without `rb` a retry rebuilds the whole batch
-// in place.  With `rb`, the merges that pass the first check keep their HSS
-// forms in `hb`; the ones that fail move to `rb` (own storage) and only they
-// are rebuilt with doubled samples; rb_of[g] is the merge's index in `rb`,
-// -1 for the merges that stay in `hb`.
-static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool check, adc_report* rep,
-                              double* flops, const std::vector<const double*>* omega_given,
-                              HssBatch* rb = nullptr, std::vector<int>* rb_of = nullptr) {
+// The first sample count of every merge: estimated rank plus oversampling.
+static void batch_init_s(HssBatch& hb, const adc_opts& o) {
   for (auto& m : hb.ms) {
     m.s = std::min({m.K, m.r + o.oversample, S_MAX});
     m.s = std::max(m.s, 1);
     m.sp = (m.s + 31) / 32 * 32;
     m.retries = 0;
   }
+}
+
+// Retries after the first check of `hb`.  Without `rb` a retry rebuilds the
+// whole batch in place.  With `rb`, the merges that passed keep their HSS
+// forms in `hb`; the ones that failed move to `rb` (own storage) and only they
+// are rebuilt with doubled samples; rb_of[g] is the merge's index in `rb`,
+// -1 for the merges that stay in `hb`.
+static adc_status batch_retry(adc_ctx c, HssBatch& hb, const adc_opts& o, adc_report* rep, double* flops,
+                              const std::vector<const double*>* omega_given, HssBatch* rb = nullptr,
+                              std::vector<int>* rb_of = nullptr) {
   if (rb_of) rb_of->assign(hb.ms.size(), -1);
   if (rb) {
     rb->ms.clear();
     rb->fmm_p = hb.fmm_p;
   }
-  ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, check, rep, flops, omega_given));
-  if (!check) return ADC_OK;
   for (int attempt = 1; attempt <= o.max_retries; ++attempt) {
     if (!rb || attempt == 1) {
       // first retry (or every retry in place): the failing merges of hb
@@ -984,6 +1026,24 @@ static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool c
     if (all) return ADC_OK;
   }
   return ADC_OK;
+}
+
+// Build (construct + check + retries in place) for a batch whose merges have
+// K, L, bounds, r and stream set.
+static adc_status batch_build(adc_ctx c, HssBatch& hb, const adc_opts& o, bool check, adc_report* rep,
+                              double* flops, const std::vector<const double*>* omega_given) {
+  batch_init_s(hb, o);
+  ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, check, rep, flops, omega_given));
+  if (!check) return ADC_OK;
+  return batch_retry(c, hb, o, rep, flops, omega_given);
+}
+
+// The update product of one solver merge: the top and bottom rows of the
+// packed operand, each against its leaf column ranges (columns grouped by row
+// support inside leaves).
+static void push_update_jobs(std::vector<ApplyJob>& aj, int g, const MergeDev& M, const LevelBufs& B) {
+  aj.push_back(ApplyJob{g, B.pk + M.zoff, (int64_t)M.n, M.n1, M.zn, M.ldn, B.posR + M.s0, 0});
+  aj.push_back(ApplyJob{g, B.pk + M.zoff + M.n1, (int64_t)M.n, M.n - M.n1, M.zn + M.n1, M.ldn, B.posR + M.s0, 1});
 }
 
 // ---------------------------------------------------------------------------
@@ -1033,10 +1093,26 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
   }
   hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
   hb.after_sampling = after_sampling;
+  // First attempt.  Its accuracy check shares the launches of the update
+  // product: the probe products W H and the products of the packed operand
+  // by every merge's HSS form run together once the operand is ready.  The
+  // columns of a merge that fails the check are written again afterwards
+  // (by its retry or by the dense fallback), so writing them now is harmless.
+  batch_init_s(hb, o);
+  ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, false, rep, flops, nullptr));
+  CheckBufs cb;
+  std::vector<ApplyJob> aj0;
+  ADC_TRY(check_prepare(c, hb, o, cb, aj0));
+  for (size_t t = 0; t < which.size(); ++t) push_update_jobs(aj0, (int)t, h_m[which[t]], B);
+  if (operand_ready) HIP_OK(hipStreamWaitEvent(st, operand_ready, 0));  // the packed operand
+  double fm = 0.0;
+  ADC_TRY(batch_apply(c, hb, aj0, &fm));
+  ADC_TRY(check_finish(c, hb, o, cb));
+  c->timer.mark(st, 8);
   HssBatch rb;
   std::vector<int> rb_of;
-  ADC_TRY(batch_build(c, hb, o, true, rep, flops, nullptr, &rb, &rb_of));
-  std::vector<ApplyJob> aj, ajr;
+  ADC_TRY(batch_retry(c, hb, o, rep, flops, nullptr, &rb, &rb_of));
+  std::vector<ApplyJob> ajr;
   std::vector<int> dense_fb;
   for (size_t t = 0; t < which.size(); ++t) {
     const MergeDev& M = h_m[which[t]];
@@ -1058,25 +1134,18 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
       }
       ADC_TRY(mlp_collect_merge(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, lo, hi, kr, kc));
     }
-    if (m.pass) {
-      // the top and bottom rows of the packed operand, each against its
-      // leaf column ranges (columns grouped by row support inside leaves)
-      const int gi = moved ? rb_of[t] : (int)t;
-      auto& dst = moved ? ajr : aj;
-      dst.push_back(ApplyJob{gi, B.pk + M.zoff, (int64_t)M.n, M.n1, M.zn, M.ldn, B.posR + M.s0, 0});
-      dst.push_back(ApplyJob{gi, B.pk + M.zoff + M.n1, (int64_t)M.n, M.n - M.n1, M.zn + M.n1, M.ldn,
-                             B.posR + M.s0, 1});
-    } else {
+    if (m.pass && moved) {
+      push_update_jobs(ajr, rb_of[t], M, B);
+    } else if (!m.pass) {
       dense_fb.push_back(which[t]);
       if (rep) rep->hss_fallbacks++;
     }
   }
   if (!dense_fb.empty() && o.strict) return ADC_ERR_ACCURACY;
-  if (operand_ready) HIP_OK(hipStreamWaitEvent(st, operand_ready, 0));  // the packed operand
-  double fm = 0.0;
-  if (!aj.empty()) ADC_TRY(batch_apply(c, hb, aj, &fm));
-  if (!ajr.empty()) ADC_TRY(batch_apply(c, rb, ajr, &fm));
-  c->timer.mark(st, 8);
+  if (!ajr.empty()) {
+    ADC_TRY(batch_apply(c, rb, ajr, &fm));
+    c->timer.mark(st, 8);
+  }
   if (flops) *flops += fm;
   if (rep) {
     rep->phase_flops[8] += fm;
