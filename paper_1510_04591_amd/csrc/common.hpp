@@ -34,6 +34,12 @@ __device__ __forceinline__ double d_minus_lam(int i, int j, double di, double dj
   return (i <= j) ? ((di - dj) - gj) : ((di - dj1) + mj);
 }
 
+// The index of the calling wave in its workgroup, as a wave-uniform value:
+// loop bounds derived from it stay in scalar registers, so that operands
+// indexed by them are read with scalar loads (threadIdx.x >> 6 alone is
+// taken as divergent by the compiler).
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ __forceinline__ double wave_sum(double x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;

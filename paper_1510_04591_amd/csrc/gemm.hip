@@ -37,7 +37,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   __shared__ double Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = wave_index();
   const int wm = wv % WM, wn = wv / WM;
   const int li = lane & 15, lk = lane >> 4;
   const int M = P.M, N = P.N;

@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_hss_sample(const HssMerge* __restrict__
   // inner-dimension segment, whole staging rounds
   const int len = ((K + jb.nseg - 1) / jb.nseg + JT - 1) / JT * JT;
   const int qa = jb.seg * len, qb = min(K, qa + len);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_index();
   const int li = lane & 15, lk = lane >> 4;
   const int ncols = min(16 * NT, sp - jb.c0);
   const int ntl = (ncols + 15) / 16;
@@ -258,7 +258,7 @@ __device__ __forceinline__ void argmax_step(double& v, int& i) {
 __device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
                        double* redv, int* redi, bool in_global) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = wave_index();
   const int grp = tid >> 3, q = tid & 7, ngrp = (int)(blockDim.x >> 3);
   __shared__ int s_stop;
   __shared__ double s_r11, s_vn2;
@@ -409,7 +409,7 @@ __device__ void block_small_gemm(double* C, int ldc, const double* Cinit, int ld
   qc = min(qc, max(Q, 1));
   double* As = lds;                // R x qc
   double* Ys = lds + R * qc;       // qc x ncol
-  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const int lane = tid & 63, wv = wave_index(), nw = blockDim.x >> 6;
   for (int q0 = 0; q0 == 0 || q0 < Q; q0 += qc) {
     const int qn = max(0, min(qc, Q - q0));
     __syncthreads();
@@ -444,7 +444,7 @@ __device__ void write_interp(const double* A, int lda, int n, int k, const int* 
   const int tid = threadIdx.x;
   for (int c = tid; c < n; c += blockDim.x) inv[perm[c]] = c;
   __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const int lane = tid & 63, wv = wave_index(), nw = blockDim.x >> 6;
   for (int j = wv; j < k; j += nw)
     for (int row = lane; row < n; row += 64) {
       const int pos = inv[row];
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     const bool in_lds = lds_doubles >= nc * lw_lds;
     const int lw = in_lds ? lw_lds : sp;
     double* Aw = in_lds ? dyn : (W0 + (int64_t)nc * sp);
-    for (int c = tid >> 6; c < nc; c += blockDim.x >> 6)
+    for (int c = wave_index(); c < nc; c += blockDim.x >> 6)
       for (int r = tid & 63; r < s; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
     __syncthreads();
     const int k = cpqr_id(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi, !in_lds);
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     int* skel = ia + (side ? nd.offSc : nd.offSr);
     double* sk = ar + (side ? nd.offTs : nd.offPs);
     for (int j = tid; j < k; j += blockDim.x) skel[j] = s_cand[s_perm[j]];
-    for (int j = tid >> 6; j < k; j += blockDim.x >> 6)
+    for (int j = wave_index(); j < k; j += blockDim.x >> 6)
       for (int col = tid & 63; col < sp; col += 64) sk[(int64_t)j * sp + col] = W0[(int64_t)s_perm[j] * sp + col];
     if (tid == 0) {
       if (side) {

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(1024) k_lowner(const MergeDev* __restrict__ me
   const MergeDev& M = merges[rb.merge];
   const int K = M.K;
   if (rb.i0 >= K) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wv = wave_index(), W = blockDim.x >> 6;
   const int64_t base = M.s0;
   const double* __restrict__ d = dS + base;
   const double* __restrict__ gam = gamS + base;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(1024) k_vnorm(const MergeDev* __restrict__ mer
   const MergeDev& M = merges[rb.merge];
   const int K = M.K;
   if (rb.i0 >= K) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wv = wave_index(), W = blockDim.x >> 6;
   const int64_t base = M.s0;
   const double* __restrict__ d = dS + base;
   const double* __restrict__ uh = uhS + base;

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
   const MergeDev& M = merges[rb.merge];
   const int K = M.K;
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = wave_index();
   const int W = blockDim.x >> 6;
   if (rb.i0 >= K) return;  // block-uniform
   const int64_t base = M.s0;
