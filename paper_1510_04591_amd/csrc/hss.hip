@@ -897,8 +897,12 @@ static adc_status check_prepare(adc_ctx c, HssBatch& hb, const adc_opts& o, Chec
     const int ntj = (m.K + 63) / 64;
     for (int c0 = 0; c0 < o.nprobe; c0 += 8) {
       const int nc = std::min(8, o.nprobe - c0);
-      hipLaunchKernelGGL(k_probe_qt, dim3((unsigned)(ntj * nseg[g])), dim3(64), 0, st, hb.d_ms, g, (const double*)W,
-                         SP_PROBE, c0, nc, nseg[g], part);
+      if (nc <= 4)
+        hipLaunchKernelGGL(k_probe_qt<4>, dim3((unsigned)(ntj * nseg[g])), dim3(64), 0, st, hb.d_ms, g,
+                           (const double*)W, SP_PROBE, c0, nc, nseg[g], part);
+      else
+        hipLaunchKernelGGL(k_probe_qt<8>, dim3((unsigned)(ntj * nseg[g])), dim3(64), 0, st, hb.d_ms, g,
+                           (const double*)W, SP_PROBE, c0, nc, nseg[g], part);
       hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)(((int64_t)m.K * SP_PROBE + 255) / 256)), dim3(256), 0, st,
                          (const double*)part, m.K, nseg[g], c0, nc, o.nprobe, WQ, SP_PROBE);
     }

@@ -79,6 +79,8 @@ struct NodeJob {
 };
 __global__ void k_hss_bblocks(const HssMerge* __restrict__ ms, const NodeJob* __restrict__ jobs);
 __global__ void k_hss_compress(const HssMerge* __restrict__ ms, const NodeJob* __restrict__ jobs, int lds_doubles);
+// NCP: probe columns per launch held in registers (4 or 8, nc <= NCP)
+template <int NCP>
 __global__ void k_probe_qt(const HssMerge* __restrict__ ms, int g, const double* __restrict__ W, int ldw, int c0,
                            int nc, int nseg, double* __restrict__ part);
 __global__ void k_probe_sum(const double* __restrict__ part, int K, int nseg, int c0, int nc, int ntot,

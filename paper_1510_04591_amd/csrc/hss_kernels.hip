@@ -654,9 +654,10 @@ __device__ __forceinline__ double rcp_refined(double x) {
   return fma(r, e, r);
 }
 
+template <int NCP>
 __global__ void __launch_bounds__(64) k_probe_qt(const HssMerge* __restrict__ ms, int g, const double* __restrict__ W,
                                                  int ldw, int c0, int nc, int nseg, double* __restrict__ part) {
-  __shared__ double s_d[65], s_u[64], s_w[64][8];
+  __shared__ double s_d[65], s_u[64], s_w[64][NCP];
   const HssMerge& M = ms[g];
   const int K = M.K;
   const int ntj = (K + 63) / 64;
@@ -674,16 +675,16 @@ __global__ void __launch_bounds__(64) k_probe_qt(const HssMerge* __restrict__ ms
     mj = M.mu[j];
     vj = M.v[j];
   }
-  double acc[8];
+  double acc[NCP];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int c = 0; c < NCP; ++c) acc[c] = 0.0;
   for (int i0 = ia; i0 < ib; i0 += 64) {
     __syncthreads();
     const int i = i0 + lane;
     s_d[lane] = (i < ib) ? M.d[i] : 0.0;
     s_u[lane] = (i < ib) ? M.uh[i] : 0.0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) s_w[lane][c] = (i < ib && c < nc) ? W[(int64_t)i * ldw + c0 + c] : 0.0;
+    for (int c = 0; c < NCP; ++c) s_w[lane][c] = (i < ib && c < nc) ? W[(int64_t)i * ldw + c0 + c] : 0.0;
     __syncthreads();
     const int cnt = min(64, ib - i0);
     if (valid) {
@@ -691,15 +692,17 @@ __global__ void __launch_bounds__(64) k_probe_qt(const HssMerge* __restrict__ ms
         const double dl = d_minus_lam(i0 + t, j, s_d[t], dj, dj1, gj, mj);
         const double q = s_u[t] * vj * rcp_refined(dl);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = fma(q, s_w[t][c], acc[c]);
+        for (int c = 0; c < NCP; ++c) acc[c] = fma(q, s_w[t][c], acc[c]);
       }
     }
   }
   if (valid) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) part[((int64_t)seg * K + j) * 8 + c] = acc[c];
+    for (int c = 0; c < NCP; ++c) part[((int64_t)seg * K + j) * 8 + c] = acc[c];
   }
 }
+template __global__ void k_probe_qt<4>(const HssMerge*, int, const double*, int, int, int, int, double*);
+template __global__ void k_probe_qt<8>(const HssMerge*, int, const double*, int, int, int, int, double*);
 
 // out[j ldo + col] = sum over segments of part[seg][j][col - c0] for col in
 // [c0, c0 + nc); columns at or beyond ntot (the probe count) are zeroed.

@@ -34,11 +34,14 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
-// s += sum z_j^2/(delta_j - t), ds += sum z_j^2/(delta_j - t)^2, ea += sum |.|
-// over j in [ja, jb), delta_j = d_j - dorg; two independent accumulator sets.
+// s += sum z_j^2/(delta_j - t), ds += sum z_j^2/(delta_j - t)^2 over j in
+// [ja, jb), delta_j = d_j - dorg; two independent accumulator pairs.  (The
+// sum of the terms' magnitudes that the error bound needs is not summed
+// here: all terms of poles left of the root have one sign and all others
+// the other, so it follows from psi and phi.)
 __device__ __forceinline__ void pole_sums(const double* __restrict__ d, const double* __restrict__ z, int ja, int jb,
-                                          double dorg, double t, double& s, double& ds, double& ea) {
-  double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0, e0 = 0.0, e1 = 0.0;
+                                          double dorg, double t, double& s, double& ds) {
+  double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0;
   int j = ja;
   // four poles per step: their (wave-uniform) loads are all issued before
   // the first is used
@@ -49,37 +52,19 @@ __device__ __forceinline__ void pole_sums(const double* __restrict__ d, const do
     const double t1 = z1 * rcp_nr((d1 - dorg) - t);
     const double t2 = z2 * rcp_nr((d2 - dorg) - t);
     const double t3 = z3 * rcp_nr((d3 - dorg) - t);
-    const double u0 = z0 * t0, u1 = z1 * t1, u2 = z2 * t2, u3 = z3 * t3;
-    s0 += u0 + u2;
-    s1 += u1 + u3;
+    s0 = fma(z0, t0, fma(z2, t2, s0));
+    s1 = fma(z1, t1, fma(z3, t3, s1));
     q0 = fma(t0, t0, fma(t2, t2, q0));
     q1 = fma(t1, t1, fma(t3, t3, q1));
-    e0 += fabs(u0) + fabs(u2);
-    e1 += fabs(u1) + fabs(u3);
   }
-  for (; j + 1 < jb; j += 2) {
-    const double za = z[j], zb = z[j + 1];
-    const double ta = za * rcp_nr((d[j] - dorg) - t);
-    const double tb = zb * rcp_nr((d[j + 1] - dorg) - t);
-    const double ua = za * ta, ub = zb * tb;
-    s0 += ua;
-    s1 += ub;
-    q0 = fma(ta, ta, q0);
-    q1 = fma(tb, tb, q1);
-    e0 += fabs(ua);
-    e1 += fabs(ub);
-  }
-  if (j < jb) {
+  for (; j < jb; ++j) {
     const double za = z[j];
     const double ta = za * rcp_nr((d[j] - dorg) - t);
-    const double ua = za * ta;
-    s0 += ua;
+    s0 = fma(za, ta, s0);
     q0 = fma(ta, ta, q0);
-    e0 += fabs(ua);
   }
   s += s0 + s1;
   ds += q0 + q1;
-  ea += e0 + e1;
 }
 
 __device__ __forceinline__ double bits_mid(double lo, double hi) {
@@ -101,7 +86,7 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
                                                   const double* __restrict__ zS, double* __restrict__ lamS,
                                                   double* __restrict__ gamS, double* __restrict__ muS,
                                                   int max_iter, int* __restrict__ noconv) {
-  __shared__ double s_part[5][MAXW][64];
+  __shared__ double s_part[4][MAXW][64];
   __shared__ double s_tau[64];
   __shared__ int s_org[64];
   __shared__ int s_done[64];
@@ -167,45 +152,45 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
     const bool act = !s_done[lane];
     const int sp = last ? K - 2 : i;
     const double dorg = valid ? d[o_l] : 0.0;
-    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, eabs = 0.0;
+    double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
     if (act) {
       // poles j <= spmin belong to psi for every lane, j > spmax to phi
       const int ja = min(j1, max(j0, spmin + 1));
       const int jb = min(j1, max(ja, spmax + 1));
-      pole_sums(d, z, j0, ja, dorg, t_l, psi, dpsi, eabs);
+      pole_sums(d, z, j0, ja, dorg, t_l, psi, dpsi);
       for (int j = ja; j < jb; ++j) {
         const double zj = z[j];
         const double t = zj * rcp_nr((d[j] - dorg) - t_l);
-        const double term = zj * t;
         if (j <= sp) {
-          psi += term;
-          dpsi += t * t;
+          psi = fma(zj, t, psi);
+          dpsi = fma(t, t, dpsi);
         } else {
-          phi += term;
-          dphi += t * t;
+          phi = fma(zj, t, phi);
+          dphi = fma(t, t, dphi);
         }
-        eabs += fabs(term);
       }
-      pole_sums(d, z, jb, j1, dorg, t_l, phi, dphi, eabs);
+      pole_sums(d, z, jb, j1, dorg, t_l, phi, dphi);
     }
     s_part[0][wv][lane] = psi;
     s_part[1][wv][lane] = dpsi;
     s_part[2][wv][lane] = phi;
     s_part[3][wv][lane] = dphi;
-    s_part[4][wv][lane] = eabs;
     __syncthreads();
 
     if (wv == 0) {
       if (!done) {
-        psi = dpsi = phi = dphi = eabs = 0.0;
+        psi = dpsi = phi = dphi = 0.0;
         for (int w2 = 0; w2 < W; ++w2) {
           psi += s_part[0][w2][lane];
           dpsi += s_part[1][w2][lane];
           phi += s_part[2][w2][lane];
           dphi += s_part[3][w2][lane];
-          eabs += s_part[4][w2][lane];
         }
         const double g = rhoinv + psi + phi;
+        // sum of the terms' magnitudes: the poles d_j, j <= sp, lie left of
+        // the root (negative terms), the others right of it (positive), but
+        // for the last root, where every pole lies to its left
+        const double eabs = last ? -(psi + phi) : (phi - psi);
         if (iter == 0) {
           // origin choice (frame d_i): root left of the midpoint iff g >= 0
           if (last) {

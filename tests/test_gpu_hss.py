@@ -91,6 +91,31 @@ def test_hss_adaptive_retry(ctx):
     adc.adc_hss_free(h)
 
 
+@pytest.mark.parametrize("nprobe", [1, 4, 8, 13])
+def test_check_error_by_its_definition(ctx, nprobe):
+    """The reported check error equals ||W^T (Q' - H)||_F / ||W^T Q'||_F with
+    the probes W drawn by the oracle's Philox stream (element (i, c) is normal
+    number i*nprobe + c of stream 1 for a single build), Q' from the oracle and
+    W^T H by applying the handle.  A deliberately low fixed rank without
+    retries makes the error large, so that rounding does not blur it."""
+    print(f"check error by definition, {nprobe} probes", flush=True)
+    d, u, rho = workloads.example1_merge(1500, seed=2)
+    gen, Q = generators(d, u, rho)
+    K = len(d)
+    seed = adc.opts().seed
+    h = gpu_build(ctx, gen, None, 0, rank_mode=adc.ADC_RANK_FIXED, fixed_rank=6, max_retries=0, hss_leaf=128,
+                  nprobe=nprobe)
+    inf = adc.adc_hss_info(h)
+    W = orng.philox_normal(K, nprobe, seed, 1)
+    WQ = W.T @ Q
+    WH = gpu_apply(ctx, h, np.ascontiguousarray(W.T))
+    want = np.linalg.norm(WQ - WH) / np.linalg.norm(WQ)
+    print(f"  reported {inf['check_err']:.6e} definition {want:.6e}", flush=True)
+    assert want > 1e-10
+    assert abs(inf["check_err"] - want) <= 1e-8 * want
+    adc.adc_hss_free(h)
+
+
 def solve(ctx, a, b, **kw):
     w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), **kw)
     torch.cuda.synchronize()
