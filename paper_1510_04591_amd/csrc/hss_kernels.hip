@@ -253,10 +253,14 @@ __device__ __forceinline__ void argmax_step(double& v, int& i) {
 
 // The work on columns is spread over groups of 8 lanes (rows split between
 // the lanes, sums by DPP inside the group); wave 0 takes the pivot and builds
-// the reflector.  in_global: A lives in global memory, where stores of one
-// lane are fenced before other lanes of the group read them.
-__device__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm, double* vv,
-                       double* redv, int* redi, bool in_global) {
+// the reflector.  IN_GLOBAL: A lives in global memory, where stores of one
+// lane are fenced before other lanes of the group read them.  (One
+// instantiation per address space, inlined into the kernel, so that the LDS
+// one is compiled to LDS instructions rather than generic ones.)
+template <bool IN_GLOBAL>
+__device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm,
+                                       double* vv, double* redv, int* redi) {
+  constexpr bool in_global = IN_GLOBAL;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = wave_index();
   const int grp = tid >> 3, q = tid & 7, ngrp = (int)(blockDim.x >> 3);
@@ -440,7 +444,8 @@ __device__ void block_small_gemm(double* C, int ldc, const double* Cinit, int ld
 
 // Write U (n x k, column-major, ld n): rows perm[j] (j < k) are e_j, rows
 // perm[c] (c >= k) are T(:, c)^T.
-__device__ void write_interp(const double* A, int lda, int n, int k, const int* perm, int* inv, double* U) {
+__device__ __forceinline__ void write_interp(const double* A, int lda, int n, int k, const int* perm, int* inv,
+                                             double* U) {
   const int tid = threadIdx.x;
   for (int c = tid; c < n; c += blockDim.x) inv[perm[c]] = c;
   __syncthreads();
@@ -521,14 +526,26 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
     // 8-lane column groups of a wave fall on different banks
     const int lw_lds = s + (((8 - s) % 32) + 32) % 32;
     const bool in_lds = lds_doubles >= nc * lw_lds;
-    const int lw = in_lds ? lw_lds : sp;
-    double* Aw = in_lds ? dyn : (W0 + (int64_t)nc * sp);
-    for (int c = wave_index(); c < nc; c += blockDim.x >> 6)
-      for (int r = tid & 63; r < s; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
-    __syncthreads();
-    const int k = cpqr_id(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi, !in_lds);
     double* U = ar + (side ? nd.offV : nd.offU);
-    write_interp(Aw, lw, nc, k, s_perm, s_inv, U);
+    int k;
+    // the two address spaces in separate branches, with the LDS one reading
+    // the shared array itself
+    if (in_lds) {
+      const int lw = lw_lds;
+      for (int c = wave_index(); c < nc; c += blockDim.x >> 6)
+        for (int r = tid & 63; r < s; r += 64) dyn[r + c * lw] = W0[r + (int64_t)c * sp];
+      __syncthreads();
+      k = cpqr_id<false>(dyn, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+      write_interp(dyn, lw, nc, k, s_perm, s_inv, U);
+    } else {
+      const int lw = sp;
+      double* Aw = W0 + (int64_t)nc * sp;
+      for (int c = wave_index(); c < nc; c += blockDim.x >> 6)
+        for (int r = tid & 63; r < s; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
+      __syncthreads();
+      k = cpqr_id<true>(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+      write_interp(Aw, lw, nc, k, s_perm, s_inv, U);
+    }
     int* skel = ia + (side ? nd.offSc : nd.offSr);
     double* sk = ar + (side ? nd.offTs : nd.offPs);
     for (int j = tid; j < k; j += blockDim.x) skel[j] = s_cand[s_perm[j]];
