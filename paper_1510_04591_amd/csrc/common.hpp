@@ -34,6 +34,18 @@ __device__ __forceinline__ double d_minus_lam(int i, int j, double di, double dj
   return (i <= j) ? ((di - dj) - gj) : ((di - dj1) + mj);
 }
 
+// Global-memory views of pointers: loads and stores through them compile to
+// global instructions.  Through a generic pointer (one read from a structure,
+// say) they are generic (flat) instructions, which also count as LDS
+// operations, so that every wait for an LDS read would also wait for all
+// global loads in flight.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) const int32_t gcint;
+__device__ __forceinline__ gdouble* gmem(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ gcdouble* gmem(const double* p) { return (gcdouble*)p; }
+__device__ __forceinline__ gcint* gmem(const int32_t* p) { return (gcint*)p; }
+
 // The index of the calling wave in its workgroup, as a wave-uniform value:
 // loop bounds derived from it stay in scalar registers, so that operands
 // indexed by them are read with scalar loads (threadIdx.x >> 6 alone is

@@ -49,6 +49,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
+  gcdouble* const gA = gmem(P.A);
+  gcdouble* const gA2 = gmem(P.A2);
+  gcdouble* const gB = gmem(P.B);
+  gcdouble* const gB2 = gmem(P.B2);
   double ra[ALOADS], rb[BLOADS];
   // A K step lies entirely in one segment: steps of the first segment start
   // at multiples of BK below P.K and stop at P.K; those of the second start
@@ -62,7 +66,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
       const int r = e % BM, c = e / BM;
       const int gr = m0 + r, gk = k0 + c;
       double x = 0.0;
-      if (gr < M && gk < lim) x = s1 ? P.A[gr + (int64_t)gk * P.lda] : P.A2[gr + (int64_t)(gk - P.K) * P.lda2];
+      if (gr < M && gk < lim) x = s1 ? gA[gr + (int64_t)gk * P.lda] : gA2[gr + (int64_t)(gk - P.K) * P.lda2];
       ra[q] = x;
     }
     const bool tr = s1 ? P.transB : P.transB2;
@@ -74,10 +78,10 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
       const int gk = k0 + kr, gn = n0 + cc;
       double x = 0.0;
       if (gk < lim && gn < N) {
-        if (s1) x = tr ? P.B[gn + (int64_t)gk * P.ldb] : P.B[gk + (int64_t)gn * P.ldb];
+        if (s1) x = tr ? gB[gn + (int64_t)gk * P.ldb] : gB[gk + (int64_t)gn * P.ldb];
         else {
           const int g2 = gk - P.K;
-          x = tr ? P.B2[gn + (int64_t)g2 * P.ldb2] : P.B2[g2 + (int64_t)gn * P.ldb2];
+          x = tr ? gB2[gn + (int64_t)g2 * P.ldb2] : gB2[g2 + (int64_t)gn * P.ldb2];
         }
       }
       rb[q] = x;
@@ -131,8 +135,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   for (int b = 0; b < TN; ++b) {
     const int col = n0 + wn * WTN + b * 16 + li;
     if (col >= N) continue;
-    const double vs = P.vscale ? P.vscale[col] : 1.0;
-    const int64_t cc = (int64_t)(P.colmap ? P.colmap[col] : col) * P.ldc;
+    const double vs = P.vscale ? gmem(P.vscale)[col] : 1.0;
+    const int64_t cc = (int64_t)(P.colmap ? gmem(P.colmap)[col] : col) * P.ldc;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
       const int row0 = m0 + wm * WTM + a * 16 + lk;
@@ -140,7 +144,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * r;
         if (row < M) {
-          double* cp = P.C + row + cc;
+          gdouble* cp = gmem(P.C) + row + cc;
           const double x = acc[a][b][r] * vs;
           *cp = (P.beta != 0.0) ? (P.beta * *cp + x) : x;
         }
