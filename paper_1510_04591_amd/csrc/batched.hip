@@ -7,12 +7,13 @@
 // never reads the deflation results: every launch of a level is sized for the
 // worst case (K = n) and each workgroup reads its merge's K from device
 // memory and exits when it has no work; the GEMM problem descriptors of the
-// dense update are filled in on the device.  The whole sequence (input
-// gather, tears, leaves, all levels, output scatter) is therefore fixed by
-// the sizes alone: the first call for a size set runs it eagerly, tuning the
-// GEMM tile shape and the secular kernel's wave count per level with HIP
-// events, and captures it in a HIP graph that later calls with the same sizes
-// replay.  Caller pointers live in device descriptor arrays refreshed before
+// dense update are filled in on the device.  Every call first gathers the
+// inputs and checks them (non-finite input is rejected before any solver
+// kernel runs); the sequence after that (tears, leaves, all levels, output
+// scatter) is fixed by the sizes alone: the first call for a size set runs it
+// eagerly, tuning the GEMM tile shape and the secular kernel's wave count per
+// level with HIP events, and captures it in a HIP graph that later calls
+// with the same sizes replay.  Caller pointers live in device descriptor arrays refreshed before
 // each replay, so they may change between calls.
 //
 // The update is the dense one (merges up to a few thousand, where HSS does
@@ -455,7 +456,10 @@ void launch_gemm(BEntry* e, const BLevel& L, int gv, hipStream_t st) {
 // wave counts and tile widths (HIP events, synchronising after each
 // candidate set) and re-runs the winner last, so that the results are those
 // of the configuration the graph will hold.
-adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool tune) {
+// Before every call (eager or graph replay): the flags reset, the batch's
+// inputs gathered into the entry's buffers and checked, so that non-finite
+// input returns ADC_ERR_ARG before any solver kernel reads it.
+adc_status gather_and_check(BEntry* e, hipStream_t st) {
   const int count = (int)e->N.size();
   const int64_t tot = e->Ntot;
   char* d = e->desc;
@@ -466,6 +470,18 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
                      (const int64_t*)(d + e->o_n), e->din, e->offg);
   hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, e->din, tot, e->flags + 1);
   hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, e->offg, tot, e->flags + 1);
+  HIP_OK(hipGetLastError());
+  int bad = 0;
+  HIP_OK(hipMemcpyAsync(&bad, e->flags + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return bad ? ADC_ERR_ARG : ADC_OK;
+}
+
+// The solver sequence from the tear on (the gathered inputs are in place).
+adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool tune) {
+  const int count = (int)e->N.size();
+  const int64_t tot = e->Ntot;
+  char* d = e->desc;
   hipLaunchKernelGGL(k_tear, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, e->din, e->offg,
                      (const int64_t*)(d + e->o_sp), e->nsplit, e->a, tot);
   if (e->nleaf)
@@ -667,6 +683,7 @@ extern "C" adc_status adc_stedc_batched(adc_ctx c, int32_t count, const int64_t*
     HIP_OK(hipStreamSynchronize(st));
     e->last_ptrs = ptrs;
   }
+  ADC_TRY(gather_and_check(e, st));
   if (!e->captured) {
     // first call: eager run with tuning, then capture for later calls
     ADC_TRY(run_sequence(c, bc, e, st, true));

@@ -1,0 +1,121 @@
+"""Error paths of the solver entry points on the GPU: what each rejects
+before any work (sizes, pointers, options, non-finite input) and a secular
+root that does not converge, forced from the host through a one-iteration
+limit (every kernel still runs to its end).  After each failure the same
+context must solve the next matrix correctly."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dc as odc
+from paper_1510_04591_amd import adc, workloads
+from conftest import cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def buffers(n):
+    w = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    Z = torch.empty(max(n, 1) * max(n, 1), dtype=torch.float64, device="cuda")
+    return w, Z
+
+
+def still_solves(ctx):
+    a, b = workloads.toeplitz(300)
+    w, Z, _ = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b))
+    torch.cuda.synchronize()
+    w, Z = w.cpu().numpy(), Z.cpu().numpy()
+    exact = np.sort(2 + 2 * np.cos(np.arange(1, 301) * np.pi / 301))
+    assert np.max(np.abs(w - exact)) <= 1e-13 * 4
+    assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
+
+
+def test_nonfinite_input_is_rejected(ctx):
+    print("non-finite input", flush=True)
+    n = 200
+    a, b = workloads.toeplitz(n)
+    w, Z = buffers(n)
+    for bad_a, bad_b in ((np.nan, None), (None, np.inf), (-np.inf, None)):
+        aa, bb = a.copy(), b.copy()
+        if bad_a is not None:
+            aa[77] = bad_a
+        if bad_b is not None:
+            bb[13] = bad_b
+        st = adc.adc_stedc(ctx.h, n, cuda(aa), cuda(bb), w, Z, n, None, 0, adc.opts(), adc.adc_report())
+        assert st == adc.ADC_ERR_ARG, adc.status_string(st)
+    # the batched entry point: one bad matrix among good ones
+    ns = [120, 64, 300]
+    mats = [workloads.toeplitz(k) for k in ns]
+    ds = [cuda(m[0]) for m in mats]
+    es = [cuda(m[1]) for m in mats]
+    es[1][5] = float("nan")
+    ws = [torch.empty(k, dtype=torch.float64, device="cuda") for k in ns]
+    Zs = [torch.empty(k * k, dtype=torch.float64, device="cuda") for k in ns]
+    st = adc.adc_stedc_batched(ctx.h, ns, ds, es, ws, Zs, ns, adc.opts(force_dense=1))
+    assert st == adc.ADC_ERR_ARG, adc.status_string(st)
+    torch.cuda.synchronize()
+    still_solves(ctx)
+
+
+def test_sizes_pointers_and_workspace(ctx):
+    print("sizes, pointers, workspace", flush=True)
+    n = 100
+    a, b = workloads.toeplitz(n)
+    ad, bd = cuda(a), cuda(b)
+    w, Z = buffers(n)
+    o = adc.opts()
+    assert adc.adc_stedc(ctx.h, -1, ad, bd, w, Z, n, None, 0, o) == adc.ADC_ERR_ARG
+    assert adc.adc_stedc(ctx.h, 0, None, None, None, None, 0, None, 0, o) == adc.ADC_OK
+    assert adc.adc_stedc(ctx.h, n, ad, bd, w, Z, n - 1, None, 0, o) == adc.ADC_ERR_ARG
+    assert adc.adc_stedc(ctx.h, n, ad, None, w, Z, n, None, 0, o) == adc.ADC_ERR_ARG
+    assert adc.adc_stedc(ctx.h, n, None, bd, w, Z, n, None, 0, o) == adc.ADC_ERR_ARG
+    assert adc.adc_stedc(ctx.h, n, ad, bd, None, Z, n, None, 0, o) == adc.ADC_ERR_ARG
+    need = adc.adc_workspace_query(ctx.h, n, o)
+    ws = torch.empty((need + 7) // 8, dtype=torch.float64, device="cuda")
+    assert adc.adc_stedc(ctx.h, n, ad, bd, w, Z, n, ws, need - 8, o) == adc.ADC_ERR_ARG
+    # a caller workspace of the queried size works, and so does ldz > n
+    Z2 = torch.empty((n + 3) * n, dtype=torch.float64, device="cuda")
+    assert adc.adc_stedc(ctx.h, n, ad, bd, w, Z2, n + 3, ws, need, o) == adc.ADC_OK
+    torch.cuda.synchronize()
+    Zh = Z2.cpu().numpy().reshape(n, n + 3)[:, :n].T
+    wh = w.cpu().numpy()
+    assert odc.residual(a, b, wh, Zh) <= 1e-13 and odc.orthogonality(Zh) <= 1e-12
+
+
+@pytest.mark.parametrize("field,value", [("dc_leaf", 1), ("dc_leaf", 65), ("hss_leaf", 8), ("hss_leaf", 512),
+                                         ("nprobe", 0), ("nprobe", 33), ("fmm_order", 3), ("fmm_order", 33),
+                                         ("shift_max", 65), ("rank_mode", 3), ("max_iter", 0),
+                                         ("sample_mode", 2), ("oversample", -1)])
+def test_invalid_option_is_rejected(ctx, field, value):
+    n = 64
+    a, b = workloads.toeplitz(n)
+    w, Z = buffers(n)
+    o = adc.opts(**{field: value})
+    assert adc.adc_stedc(ctx.h, n, cuda(a), cuda(b), w, Z, n, None, 0, o) == adc.ADC_ERR_ARG
+
+
+@pytest.mark.parametrize("dense", [1, 0])
+def test_nonconvergence_is_reported(ctx, dense):
+    """One secular iteration per root: the solve runs to its end, returns
+    ADC_ERR_NOCONV and names a root; the context then solves normally."""
+    print(f"non-convergence, force_dense={dense}", flush=True)
+    n = 3000
+    a, b = workloads.toeplitz(n)  # no deflation: the top merges reach HSS
+    w, Z = buffers(n)
+    rep = adc.adc_report()
+    o = adc.opts(max_iter=1, force_dense=dense, hss_min_k=256, hss_min_flops=0, hss_leaf=64)
+    st = adc.adc_stedc(ctx.h, n, cuda(a), cuda(b), w, Z, n, None, 0, o, rep)
+    torch.cuda.synchronize()
+    assert st == adc.ADC_ERR_NOCONV, adc.status_string(st)
+    assert 0 <= rep.info_index < n
+    assert dense or rep.hss_merges + rep.hss_fallbacks > 0
+    # the batched entry point reports it as well
+    ns = [500, 700]
+    mats = [workloads.random_uniform(k, 6 + k) for k in ns]
+    ws = [torch.empty(k, dtype=torch.float64, device="cuda") for k in ns]
+    Zs = [torch.empty(k * k, dtype=torch.float64, device="cuda") for k in ns]
+    st = adc.adc_stedc_batched(ctx.h, ns, [cuda(m[0]) for m in mats], [cuda(m[1]) for m in mats], ws, Zs, ns,
+                               adc.opts(max_iter=1, force_dense=1))
+    torch.cuda.synchronize()
+    assert st == adc.ADC_ERR_NOCONV, adc.status_string(st)
+    still_solves(ctx)
