@@ -392,14 +392,18 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
 
 // C[r ldc + col] = (Cinit ? Cinit[r ldi + col] : 0) + sgn sum_q A(r, q) Y[q ldy + col]
 // for r < R, col < ncol, with A(r, q) = A[r ars + q acs]; both operands are
-// staged through `lds` (cap doubles) in chunks of q.  Every output element
-// is owned by one thread, so Cinit may alias C.
-__device__ void block_small_gemm(double* C, int ldc, const double* Cinit, int ldi, double sgn, const double* A,
-                                 int ars, int acs, const double* Y, int ldy, int R, int Q, int ncol, double* lds,
-                                 int cap) {
+// staged through `lds` (cap doubles) in chunks of q, A transposed with its
+// rows padded to groups of four.  A thread owns four rows of one column and
+// keeps them in registers, so that each staged Y entry feeds four FMAs (one
+// LDS read of Y and one of four consecutive A entries per four FMAs).
+// Every output element is owned by one thread, so Cinit may alias C.
+__device__ __forceinline__ void block_small_gemm(double* C, int ldc, const double* Cinit, int ldi, double sgn,
+                                                 const double* A, int ars, int acs, const double* Y, int ldy, int R,
+                                                 int Q, int ncol, double* lds, int cap) {
   const int tid = threadIdx.x;
-  int qc = (cap > 0) ? cap / (R + ncol) : 0;
   if (R <= 0 || ncol <= 0) return;
+  const int Rp = (R + 3) & ~3;
+  int qc = (cap > 0) ? cap / (Rp + ncol) : 0;
   if (qc <= 0) {
     for (int e = tid; e < R * ncol; e += blockDim.x) {
       const int r = e / ncol, col = e % ncol;
@@ -411,30 +415,53 @@ __device__ void block_small_gemm(double* C, int ldc, const double* Cinit, int ld
     return;
   }
   qc = min(qc, max(Q, 1));
-  double* As = lds;                // R x qc
-  double* Ys = lds + R * qc;       // qc x ncol
-  const int lane = tid & 63, wv = wave_index(), nw = blockDim.x >> 6;
+  double* As = lds;                     // qc x Rp: As[qq Rp + r] = A(r, q0 + qq), padding rows zero
+  double* Ys = lds + (int64_t)qc * Rp;  // qc x ncol
+  const int ngrp = Rp / 4;
+  const int items = ngrp * ncol;        // (row group, column) pairs
   for (int q0 = 0; q0 == 0 || q0 < Q; q0 += qc) {
     const int qn = max(0, min(qc, Q - q0));
     __syncthreads();
-    for (int r = wv; r < R; r += nw)
-      for (int qq = lane; qq < qn; qq += 64) As[r * qc + qq] = A[(int64_t)r * ars + (int64_t)(q0 + qq) * acs];
-    for (int qq = wv; qq < qn; qq += nw)
-      for (int col = lane; col < ncol; col += 64) Ys[qq * ncol + col] = Y[(int64_t)(q0 + qq) * ldy + col];
+    // staging, consecutive threads on A's contiguous index
+    if (acs == 1) {
+      for (int e = tid; e < Rp * qn; e += blockDim.x) {
+        const int r = e / qn, qq = e % qn;
+        As[qq * Rp + r] = (r < R) ? A[(int64_t)r * ars + q0 + qq] : 0.0;
+      }
+    } else {
+      for (int e = tid; e < Rp * qn; e += blockDim.x) {
+        const int qq = e / Rp, r = e % Rp;
+        As[qq * Rp + r] = (r < R) ? A[(int64_t)r * ars + (int64_t)(q0 + qq) * acs] : 0.0;
+      }
+    }
+    for (int e = tid; e < qn * ncol; e += blockDim.x) {
+      const int qq = e / ncol, col = e % ncol;
+      Ys[qq * ncol + col] = Y[(int64_t)(q0 + qq) * ldy + col];
+    }
     __syncthreads();
-    for (int r = wv; r < R; r += nw) {
-      const double* ar = As + r * qc;
-      for (int col = lane; col < ncol; col += 64) {
-        double x0 = 0.0, x1 = 0.0;
-        int qq = 0;
-        for (; qq + 1 < qn; qq += 2) {
-          x0 += ar[qq] * Ys[qq * ncol + col];
-          x1 += ar[qq + 1] * Ys[(qq + 1) * ncol + col];
+    for (int e = tid; e < items; e += blockDim.x) {
+      const int g = e / ncol, col = e % ncol;
+      const int r0 = 4 * g;
+      const double* ap = As + r0;
+      const double* yp = Ys + col;
+      double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+      for (int qq = 0; qq < qn; ++qq) {
+        const double y = yp[qq * ncol];
+        const double* a4 = ap + qq * Rp;
+        x0 = fma(a4[0], y, x0);
+        x1 = fma(a4[1], y, x1);
+        x2 = fma(a4[2], y, x2);
+        x3 = fma(a4[3], y, x3);
+      }
+      const double xs[4] = {x0, x1, x2, x3};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + u;
+        if (r < R) {
+          double* cp = C + (int64_t)r * ldc + col;
+          const double base = (q0 == 0) ? (Cinit ? Cinit[(int64_t)r * ldi + col] : 0.0) : *cp;
+          *cp = base + sgn * xs[u];
         }
-        if (qq < qn) x0 += ar[qq] * Ys[qq * ncol + col];
-        double* cp = C + (int64_t)r * ldc + col;
-        const double base = (q0 == 0) ? (Cinit ? Cinit[(int64_t)r * ldi + col] : 0.0) : *cp;
-        *cp = base + sgn * (x0 + x1);
       }
     }
     if (Q <= 0) break;
