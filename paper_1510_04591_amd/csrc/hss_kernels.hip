@@ -210,11 +210,11 @@ __global__ void k_sample_sum(const double* __restrict__ part, int nseg, int64_t 
 // Column interpolative decomposition of A (m x n, column-major, ld lda) by
 // column-pivoted Householder QR (pivot: largest remaining norm, recomputed
 // every step; ties to the smaller index), stopped when that norm is <= tol
-// times the first one.  On return A[0:k, k:n] = R11^-1 R12 and perm lists the
-// chosen columns first.  All threads of the block take part.
+// times the first one.  Columns are not moved: perm lists the chosen columns
+// first, and on return column perm[c] of A holds, in rows 0:k, R11^-1 R12's
+// column c for c >= k.  All threads of the block take part.
 namespace {
 constexpr int CMAX = 512;  // candidates
-constexpr int SMAX = 256;  // samples
 
 // (value, index) maximum with ties to the smaller index
 __device__ __forceinline__ void argmax_merge(double& v, int& i, double ov, int oi) {
@@ -259,13 +259,13 @@ __device__ __forceinline__ void argmax_step(double& v, int& i) {
 // one is compiled to LDS instructions rather than generic ones.)
 template <bool IN_GLOBAL>
 __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double tol, int* perm, double* nrm,
-                                       double* vv, double* redv, int* redi) {
+                                       double* redv, int* redi) {
   constexpr bool in_global = IN_GLOBAL;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = wave_index();
   const int grp = tid >> 3, q = tid & 7, ngrp = (int)(blockDim.x >> 3);
-  __shared__ int s_stop;
-  __shared__ double s_r11, s_vn2;
+  __shared__ int s_stop, s_pc;
+  __shared__ double s_vn2, s_vk;
   for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
   // squared column norms
   for (int c0 = 0; c0 < n; c0 += ngrp) {
@@ -281,6 +281,7 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
   __syncthreads();
   const int kmax = min(m, n);
   int k = 0;
+  double r11 = 0.0;  // |R_11|, kept by wave 0
   for (; k < kmax; ++k) {
     if (wv == 0) {
       // pivot: largest remaining norm, ties to the smaller index; rows of 16
@@ -301,55 +302,50 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
       bi = redi[0];
       for (int w = 1; w < 4; ++w) argmax_merge(best, bi, redv[w], redi[w]);
       const double pn = sqrt(fmax(best, 0.0));
-      const double r11 = (k == 0) ? pn : s_r11;
+      if (k == 0) r11 = pn;
       const int stop = (bi >= n) || (pn == 0.0) || (pn <= tol * r11);
       if (!stop) {
-        double* ck = A + (int64_t)k * lda;
-        if (bi != k) {
-          double* ci = A + (int64_t)bi * lda;
-          for (int r = lane; r < m; r += 64) {
-            const double t = ck[r];
-            ck[r] = ci[r];
-            ci[r] = t;
-          }
-          if (in_global) __threadfence_block();
-        }
-        // Householder vector v = x - alpha e_1, alpha = -sign(x_0)||x||,
-        // v^T v = 2 ||x|| (||x|| + |x_0|)
-        const double x0 = ck[k];
+        // Columns stay in place: perm maps the pivot order to them, so the
+        // swap is one of indices.  The Householder vector v = x - alpha e_1
+        // (alpha = -sign(x_0)||x||, v^T v = 2 ||x|| (||x|| + |x_0|)) is read
+        // from the pivot column below row k and from s_vk at row k, where
+        // the column takes R(k, k) = alpha; its rows below k are not part
+        // of R and are left as they are.
+        const int pb = perm[bi];
+        double* pc = A + (int64_t)pb * lda;
+        const double x0 = pc[k];
         const double alpha = (x0 != 0.0) ? -copysign(pn, x0) : -pn;
-        for (int r = k + lane; r < m; r += 64) {
-          const double x = ck[r];
-          vv[r] = (r == k) ? x - alpha : x;
-          ck[r] = (r == k) ? alpha : 0.0;
-        }
         if (lane == 0) {
           if (bi != k) {
-            const int t = perm[k];
-            perm[k] = perm[bi];
-            perm[bi] = t;
+            perm[bi] = perm[k];
+            perm[k] = pb;
             nrm[bi] = nrm[k];
           }
+          pc[k] = alpha;
           s_vn2 = 2.0 * pn * (pn + fabs(x0));
+          s_vk = x0 - alpha;
+          s_pc = pb;
         }
       }
-      if (lane == 0) {
-        if (k == 0) s_r11 = pn;
-        s_stop = stop;
-      }
+      if (lane == 0) s_stop = stop;
     }
     __syncthreads();
     if (s_stop) break;
-    const double vn2 = s_vn2;
+    const double vn2 = s_vn2, vk = s_vk;
+    const double* __restrict__ v = A + (int64_t)s_pc * lda;  // rows > k of the reflector
     // a group per remaining column: reflect it and take its norm below row k
     for (int c0 = k + 1; c0 < n; c0 += ngrp) {
       const int c = c0 + grp;
       const bool act = c < n;
-      double* __restrict__ col = A + (int64_t)(act ? c : k) * lda;
-      const double* __restrict__ v = vv;
       double d0 = 0.0, d1 = 0.0;
+      double* __restrict__ col = A;
       if (act) {
+        col = A + (int64_t)perm[c] * lda;
         int r = k + q;
+        if (q == 0) {
+          d0 = vk * col[k];
+          r += 8;
+        }
         for (; r + 8 < m; r += 16) {
           d0 = fma(v[r], col[r], d0);
           d1 = fma(v[r + 8], col[r + 8], d1);
@@ -360,10 +356,15 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
       const double f = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;
       double s2 = 0.0;
       if (act) {
-        for (int r = k + q; r < m; r += 8) {
+        int r = k + q;
+        if (q == 0) {
+          col[k] -= f * vk;
+          r += 8;
+        }
+        for (; r < m; r += 8) {
           const double x = col[r] - f * v[r];
           col[r] = x;
-          if (r > k) s2 = fma(x, x, s2);
+          s2 = fma(x, x, s2);
         }
       }
       s2 = sum8(s2);
@@ -372,14 +373,15 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
     __syncthreads();
   }
   // T = R11^-1 R12 in place: back substitution, a group per column (rows of
-  // the update split between its lanes)
+  // the update split between its lanes); column c of the pivot order is
+  // stored in column perm[c]
   for (int c0 = k; c0 < n; c0 += ngrp) {
     const int c = c0 + grp;
     if (c < n) {
-      double* col = A + (int64_t)c * lda;
+      double* col = A + (int64_t)perm[c] * lda;
       for (int j = k - 1; j >= 0; --j) {
-        const double xj = col[j] / A[j + (int64_t)j * lda];
-        const double* aj = A + (int64_t)j * lda;
+        const double* aj = A + (int64_t)perm[j] * lda;
+        const double xj = col[j] / aj[j];
         for (int r = q; r < j; r += 8) col[r] = fma(-xj, aj[r], col[r]);
         if (q == 0) col[j] = xj;
         if (in_global) __threadfence_block();
@@ -470,7 +472,8 @@ __device__ __forceinline__ void block_small_gemm(double* C, int ldc, const doubl
 }
 
 // Write U (n x k, column-major, ld n): rows perm[j] (j < k) are e_j, rows
-// perm[c] (c >= k) are T(:, c)^T.
+// perm[c] (c >= k) are T(:, c)^T, which the back substitution left in
+// column perm[c] of A.
 __device__ __forceinline__ void write_interp(const double* A, int lda, int n, int k, const int* perm, int* inv,
                                              double* U) {
   const int tid = threadIdx.x;
@@ -482,7 +485,7 @@ __device__ __forceinline__ void write_interp(const double* A, int lda, int n, in
       const int pos = inv[row];
       double x;
       if (pos < k) x = (pos == j) ? 1.0 : 0.0;
-      else x = A[j + (int64_t)pos * lda];
+      else x = A[j + (int64_t)row * lda];
       U[row + (int64_t)j * n] = x;
     }
   __syncthreads();
@@ -496,7 +499,6 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
   __shared__ int s_perm[CMAX];
   __shared__ int s_inv[CMAX];
   __shared__ int s_cand[CMAX];
-  __shared__ double s_vv[SMAX];
   __shared__ double s_redv[16];
   __shared__ int s_redi[16];
 
@@ -562,7 +564,7 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
       for (int c = wave_index(); c < nc; c += blockDim.x >> 6)
         for (int r = tid & 63; r < s; r += 64) dyn[r + c * lw] = W0[r + (int64_t)c * sp];
       __syncthreads();
-      k = cpqr_id<false>(dyn, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+      k = cpqr_id<false>(dyn, lw, s, nc, M.id_tol, s_perm, s_nrm, s_redv, s_redi);
       write_interp(dyn, lw, nc, k, s_perm, s_inv, U);
     } else {
       const int lw = sp;
@@ -570,7 +572,7 @@ __global__ void __launch_bounds__(1024) k_hss_compress(const HssMerge* __restric
       for (int c = wave_index(); c < nc; c += blockDim.x >> 6)
         for (int r = tid & 63; r < s; r += 64) Aw[r + (int64_t)c * lw] = W0[r + (int64_t)c * sp];
       __syncthreads();
-      k = cpqr_id<true>(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_vv, s_redv, s_redi);
+      k = cpqr_id<true>(Aw, lw, s, nc, M.id_tol, s_perm, s_nrm, s_redv, s_redi);
       write_interp(Aw, lw, nc, k, s_perm, s_inv, U);
     }
     int* skel = ia + (side ? nd.offSc : nd.offSr);
