@@ -265,7 +265,7 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
   const int lane = tid & 63, wv = wave_index();
   const int grp = tid >> 3, q = tid & 7, ngrp = (int)(blockDim.x >> 3);
   __shared__ int s_stop, s_pc;
-  __shared__ double s_vn2, s_vk;
+  __shared__ double s_f2, s_vk;
   for (int c = tid; c < n; c += blockDim.x) perm[c] = c;
   // squared column norms
   for (int c0 = 0; c0 < n; c0 += ngrp) {
@@ -322,7 +322,8 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
             nrm[bi] = nrm[k];
           }
           pc[k] = alpha;
-          s_vn2 = 2.0 * pn * (pn + fabs(x0));
+          const double vn2 = 2.0 * pn * (pn + fabs(x0));
+          s_f2 = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;  // the reflection factor 2 / v^T v
           s_vk = x0 - alpha;
           s_pc = pb;
         }
@@ -331,7 +332,7 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
     }
     __syncthreads();
     if (s_stop) break;
-    const double vn2 = s_vn2, vk = s_vk;
+    const double f2 = s_f2, vk = s_vk;
     const double* __restrict__ v = A + (int64_t)s_pc * lda;  // rows > k of the reflector
     // a group per remaining column: reflect it and take its norm below row k
     for (int c0 = k + 1; c0 < n; c0 += ngrp) {
@@ -353,7 +354,7 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
         if (r < m) d0 = fma(v[r], col[r], d0);
       }
       const double dt = sum8(d0 + d1);
-      const double f = (vn2 > 0.0) ? 2.0 * dt / vn2 : 0.0;
+      const double f = dt * f2;
       double s2 = 0.0;
       if (act) {
         int r = k + q;
@@ -374,14 +375,17 @@ __device__ __forceinline__ int cpqr_id(double* A, int lda, int m, int n, double 
   }
   // T = R11^-1 R12 in place: back substitution, a group per column (rows of
   // the update split between its lanes); column c of the pivot order is
-  // stored in column perm[c]
+  // stored in column perm[c].  The reciprocals of R11's diagonal go first
+  // into nrm (no longer needed).
+  for (int j = tid; j < k; j += blockDim.x) nrm[j] = 1.0 / A[j + (int64_t)perm[j] * lda];
+  __syncthreads();
   for (int c0 = k; c0 < n; c0 += ngrp) {
     const int c = c0 + grp;
     if (c < n) {
       double* col = A + (int64_t)perm[c] * lda;
       for (int j = k - 1; j >= 0; --j) {
         const double* aj = A + (int64_t)perm[j] * lda;
-        const double xj = col[j] / aj[j];
+        const double xj = col[j] * nrm[j];
         for (int r = q; r < j; r += 8) col[r] = fma(-xj, aj[r], col[r]);
         if (q == 0) col[j] = xj;
         if (in_global) __threadfence_block();
