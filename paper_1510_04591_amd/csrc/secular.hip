@@ -2,8 +2,11 @@
 //
 // One root per lane; a workgroup owns 64 consecutive roots of one merge and
 // splits the pole sum over its W waves (W = blockDim/64), so that large
-// secular sizes still put many waves on every SIMD.  The poles d_j and
-// weights z_j are read as wave-uniform (scalar) loads, one j per step.
+// secular sizes still put many waves on every SIMD.  Each wave stages its
+// share of the poles d_j and weights z_j through LDS in chunks of 64 (one
+// coalesced vector load per chunk, prefetched one chunk ahead) and reads
+// them back as broadcasts; only the few poles whose side of the split differs
+// between the block's roots are read directly.
 //
 // Iteration (written from the rational-interpolation literature: Bunch,
 // Nielsen & Sorensen 1978; Li 1993): with origin d_o the nearer pole and
@@ -35,33 +38,45 @@ __device__ __forceinline__ double rcp_nr(double x) {
 }
 
 // s += sum z_j^2/(delta_j - t), ds += sum z_j^2/(delta_j - t)^2 over j in
-// [ja, jb), delta_j = d_j - dorg; two independent accumulator pairs.  (The
-// sum of the terms' magnitudes that the error bound needs is not summed
-// here: all terms of poles left of the root have one sign and all others
-// the other, so it follows from psi and phi.)
-__device__ __forceinline__ void pole_sums(const double* __restrict__ d, const double* __restrict__ z, int ja, int jb,
-                                          double dorg, double t, double& s, double& ds) {
+// [ja, jb), delta_j = d_j - dorg; two independent accumulator pairs.  The
+// wave's poles are staged through its own LDS buffer (buf: 128 doubles, d
+// then z) in chunks of 64, one pole per lane by a coalesced vector load, the
+// next chunk loaded while this one is summed; every lane of the wave takes
+// part (its own t and dorg).  (The sum of the terms' magnitudes that the
+// error bound needs is not summed here: all terms of poles left of the root
+// have one sign and all others the other, so it follows from psi and phi.)
+__device__ __forceinline__ void pole_sums_staged(const double* __restrict__ d, const double* __restrict__ z, int ja,
+                                                 int jb, double dorg, double t, double& s, double& ds, double* buf,
+                                                 int lane) {
   double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0;
-  int j = ja;
-  // four poles per step: their (wave-uniform) loads are all issued before
-  // the first is used
-  for (; j + 3 < jb; j += 4) {
-    const double z0 = z[j], z1 = z[j + 1], z2 = z[j + 2], z3 = z[j + 3];
-    const double d0 = d[j], d1 = d[j + 1], d2 = d[j + 2], d3 = d[j + 3];
-    const double t0 = z0 * rcp_nr((d0 - dorg) - t);
-    const double t1 = z1 * rcp_nr((d1 - dorg) - t);
-    const double t2 = z2 * rcp_nr((d2 - dorg) - t);
-    const double t3 = z3 * rcp_nr((d3 - dorg) - t);
-    s0 = fma(z0, t0, fma(z2, t2, s0));
-    s1 = fma(z1, t1, fma(z3, t3, s1));
-    q0 = fma(t0, t0, fma(t2, t2, q0));
-    q1 = fma(t1, t1, fma(t3, t3, q1));
-  }
-  for (; j < jb; ++j) {
-    const double za = z[j];
-    const double ta = za * rcp_nr((d[j] - dorg) - t);
-    s0 = fma(za, ta, s0);
-    q0 = fma(ta, ta, q0);
+  if (ja >= jb) return;
+  double dn = (ja + lane < jb) ? d[ja + lane] : 0.0;
+  double zn = (ja + lane < jb) ? z[ja + lane] : 0.0;
+  for (int c0 = ja; c0 < jb; c0 += 64) {
+    const int cnt = min(64, jb - c0);
+    buf[lane] = dn;
+    buf[64 + lane] = zn;
+    const int c1 = c0 + 64;
+    dn = (c1 + lane < jb) ? d[c1 + lane] : 0.0;
+    zn = (c1 + lane < jb) ? z[c1 + lane] : 0.0;
+    int u = 0;
+    for (; u + 3 < cnt; u += 4) {
+      const double z0 = buf[64 + u], z1 = buf[65 + u], z2 = buf[66 + u], z3 = buf[67 + u];
+      const double t0 = z0 * rcp_nr((buf[u] - dorg) - t);
+      const double t1 = z1 * rcp_nr((buf[u + 1] - dorg) - t);
+      const double t2 = z2 * rcp_nr((buf[u + 2] - dorg) - t);
+      const double t3 = z3 * rcp_nr((buf[u + 3] - dorg) - t);
+      s0 = fma(z0, t0, fma(z2, t2, s0));
+      s1 = fma(z1, t1, fma(z3, t3, s1));
+      q0 = fma(t0, t0, fma(t2, t2, q0));
+      q1 = fma(t1, t1, fma(t3, t3, q1));
+    }
+    for (; u < cnt; ++u) {
+      const double za = buf[64 + u];
+      const double ta = za * rcp_nr((buf[u] - dorg) - t);
+      s0 = fma(za, ta, s0);
+      q0 = fma(ta, ta, q0);
+    }
   }
   s += s0 + s1;
   ds += q0 + q1;
@@ -87,6 +102,7 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
                                                   double* __restrict__ gamS, double* __restrict__ muS,
                                                   int max_iter, int* __restrict__ noconv) {
   __shared__ double s_part[4][MAXW][64];
+  __shared__ double s_stage[MAXW][128];
   __shared__ double s_tau[64];
   __shared__ int s_org[64];
   __shared__ int s_done[64];
@@ -153,11 +169,15 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
     const int sp = last ? K - 2 : i;
     const double dorg = valid ? d[o_l] : 0.0;
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+    // poles j <= spmin belong to psi for every lane, j > spmax to phi
+    const int ja = min(j1, max(j0, spmin + 1));
+    const int jb = min(j1, max(ja, spmax + 1));
+    if (__any(act)) {
+      // the whole wave stages the poles; lanes already done discard theirs
+      pole_sums_staged(d, z, j0, ja, dorg, t_l, psi, dpsi, s_stage[wv], lane);
+      pole_sums_staged(d, z, jb, j1, dorg, t_l, phi, dphi, s_stage[wv], lane);
+    }
     if (act) {
-      // poles j <= spmin belong to psi for every lane, j > spmax to phi
-      const int ja = min(j1, max(j0, spmin + 1));
-      const int jb = min(j1, max(ja, spmax + 1));
-      pole_sums(d, z, j0, ja, dorg, t_l, psi, dpsi);
       for (int j = ja; j < jb; ++j) {
         const double zj = z[j];
         const double t = zj * rcp_nr((d[j] - dorg) - t_l);
@@ -169,7 +189,6 @@ __global__ void __launch_bounds__(1024) k_secular(const MergeDev* __restrict__ m
           dphi = fma(t, t, dphi);
         }
       }
-      pole_sums(d, z, jb, j1, dorg, t_l, phi, dphi);
     }
     s_part[0][wv][lane] = psi;
     s_part[1][wv][lane] = dpsi;
