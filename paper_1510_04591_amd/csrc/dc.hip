@@ -339,6 +339,11 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     Arena ha{hs, 0, 0}, da{dd, 0, 0};
     MergeDev* h_m = ha.take<MergeDev>(nm);
     MergeDev* d_m = da.take<MergeDev>(nm);
+    // blocks of 256 elements over every merge (the merged order, later the
+    // final order)
+    RootBlock* h_ob = ha.take<RootBlock>(blocks64);
+    RootBlock* d_ob = da.take<RootBlock>(blocks64);
+    int nob = 0;
     int32_t nmax = 0;
     for (int g2 = 0; g2 < nm; ++g2) {
       MergeDev& M = h_m[g2];
@@ -353,9 +358,13 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       M.ldn = ldn;
       nmax = std::max(nmax, M.n);
     }
+    for (int g2 = 0; g2 < nm; ++g2)
+      for (int i0 = 0; i0 < h_m[g2].n; i0 += 256) h_ob[nob++] = RootBlock{g2, i0};
     HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(d_m, h_m, nm * sizeof(MergeDev), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(d_ob, h_ob, nob * sizeof(RootBlock), hipMemcpyHostToDevice, st));
     c->timer.start(st, rep != nullptr);
+    hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);
     hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
     HIP_OK(hipGetLastError());
     c->timer.mark(st, 1);
@@ -416,11 +425,6 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     int nrb = 0;
     for (int g2 = 0; g2 < nm; ++g2)
       for (int i0 = 0; i0 < h_m[g2].K; i0 += 64) h_rb[nrb++] = RootBlock{g2, i0};
-    RootBlock* h_ob = ha.take<RootBlock>(blocks64);
-    RootBlock* d_ob = da.take<RootBlock>(blocks64);
-    int nob = 0;
-    for (int g2 = 0; g2 < nm; ++g2)
-      for (int i0 = 0; i0 < h_m[g2].n; i0 += 256) h_ob[nob++] = RootBlock{g2, i0};
     int32_t* h_cm = ha.take<int32_t>(n);
     int32_t* d_cm = da.take<int32_t>(n);
     int32_t* h_cc = ha.take<int32_t>(n);

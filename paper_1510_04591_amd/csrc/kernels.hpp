@@ -106,6 +106,8 @@ __global__ void k_leaf_jacobi(const double* __restrict__ a, const double* __rest
                               const int64_t* __restrict__ leaf_s0, const int32_t* __restrict__ leaf_m,
                               double* __restrict__ w, const LeafOut* __restrict__ outs, int max_sweeps);
 
+__global__ void k_merge_sort(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,
+                             LevelBufs B);
 __global__ void k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B);
 
 __global__ void k_secular(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,

@@ -1,9 +1,11 @@
 // Merge-step kernels around the secular solve (Algorithm 1, "form M = D +
 // b_k u u^T", deflation, and the assembly of the merged eigenpairs).
 //
-// k_merge_prep   eq. (T3): z = [last row of Q1; first row of Q2] (second half
-//                negated when b_k < 0), rho = |b_k| ||z||^2, z normalised;
-//                stable merge of the two sorted child spectra; deflation with
+// k_merge_sort   the stable merge of the two sorted child spectra, one thread
+//                per element (binary search in the other child), with the
+//                entries of z = [last row of Q1; first row of Q2] (second
+//                half negated when b_k < 0, eq. T3), not yet normalised.
+// k_merge_prep   rho = |b_k| ||z||^2, z normalised; deflation with
 //                tol = 8 eps max(max|d|, rho max|z|): type 1 when |rho z_j| <=
 //                tol, type 2 (a Givens rotation of two columns) when the
 //                coupling |(d_j - d_i) c s| <= tol.  The scan is sequential
@@ -84,24 +86,42 @@ __device__ int block_exclusive_scan(int x, int* sh) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Blocks of 256 elements (merge, first element), one thread per element j of
+// the merge: its place in the merged order is j plus the number of the other
+// child's values below it (ties: the first child's value first), where it
+// writes d_j, u_j = z_j before normalisation, its origin j and its support.
+__global__ void __launch_bounds__(256) k_merge_sort(const MergeDev* __restrict__ merges,
+                                                    const RootBlock* __restrict__ blocks, LevelBufs B) {
+  const RootBlock rb = blocks[blockIdx.x];
+  const MergeDev& M = merges[rb.merge];
+  const int n = M.n, n1 = M.n1, n2 = n - n1;
+  const int j = rb.i0 + (int)threadIdx.x;
+  if (j >= n) return;
+  const int64_t s0 = M.s0;
+  const double beta = B.off[s0 + n1 - 1];
+  const double sg = (beta >= 0.0) ? 1.0 : -1.0;
+  const double* __restrict__ win = B.w_in + s0;
+  const double u = (j < n1) ? M.zo[(n1 - 1) + j * M.ldo] : sg * M.zo[n1 + j * M.ldo];
+  const double dj = win[j];
+  const int pos = (j < n1) ? j + lower_bound_d(win + n1, n2, dj) : (j - n1) + upper_bound_d(win, n1, dj);
+  B.dsort[s0 + pos] = dj;
+  B.zsort[s0 + pos] = u;
+  B.src[s0 + pos] = j;
+  B.supp[s0 + pos] = (j < n1) ? 1 : 2;
+}
+
 __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B) {
   __shared__ double sh[1025];
   MergeDev& M = merges[blockIdx.x];
   const int64_t s0 = M.s0;
-  const int n = M.n, n1 = M.n1, n2 = n - n1;
+  const int n = M.n, n1 = M.n1;
   const double beta = B.off[s0 + n1 - 1];
-  const double sg = (beta >= 0.0) ? 1.0 : -1.0;
   const int tid = threadIdx.x;
-  const double* __restrict__ win = B.w_in + s0;
-  const double* __restrict__ d1 = win;
-  const double* __restrict__ d2 = win + n1;
-  const int64_t ldz = M.ldo;
-  const double* __restrict__ zo = M.zo;
 
-  // ||u||^2 with u = [last row of Q1; +-first row of Q2]
+  // ||u||^2 over the merged order (k_merge_sort placed u unnormalised)
   double ss = 0.0;
-  for (int j = tid; j < n; j += blockDim.x) {
-    const double u = (j < n1) ? zo[(n1 - 1) + j * ldz] : sg * zo[n1 + j * ldz];
+  for (int p = tid; p < n; p += blockDim.x) {
+    const double u = B.zsort[s0 + p];
     ss += u * u;
   }
   const double nu2 = block_reduce(ss, sh, OpAdd());
@@ -109,18 +129,10 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
   const double inv = (nu2 > 0.0) ? 1.0 / sqrt(nu2) : 0.0;
 
   double md = 0.0, mz = 0.0;
-  for (int j = tid; j < n; j += blockDim.x) {
-    const double u = (j < n1) ? zo[(n1 - 1) + j * ldz] : sg * zo[n1 + j * ldz];
-    const double dj = win[j];
-    int pos;
-    if (j < n1) pos = j + lower_bound_d(d2, n2, dj);
-    else pos = (j - n1) + upper_bound_d(d1, n1, dj);
-    const double zj = u * inv;
-    B.dsort[s0 + pos] = dj;
-    B.zsort[s0 + pos] = zj;
-    B.src[s0 + pos] = j;
-    B.supp[s0 + pos] = (j < n1) ? 1 : 2;
-    md = fmax(md, fabs(dj));
+  for (int p = tid; p < n; p += blockDim.x) {
+    const double zj = B.zsort[s0 + p] * inv;
+    B.zsort[s0 + p] = zj;
+    md = fmax(md, fabs(B.dsort[s0 + p]));
     mz = fmax(mz, fabs(zj));
   }
   md = block_reduce(md, sh, OpMax());
