@@ -30,6 +30,16 @@
 
 namespace {
 
+// 1/x: hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each of which squares the relative error.
+__device__ __forceinline__ double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 constexpr int PMAX = 32;   // Chebyshev points per node at most
 constexpr int CW = 32;     // sample columns per job
 constexpr int PCH = 64;    // source points staged at a time (P2M)
@@ -333,7 +343,7 @@ __global__ __launch_bounds__(128) void k_fmm_leaf(const HssMerge* __restrict__ m
               df = (i <= gj) ? (td - s0[j]) - s1[j] : (td - s2[j]) + s3[j];
             else  // target root i, source pole gj: d_gj - lam_i
               df = (gj <= i) ? (s0[j] - td) - tg : (s0[j] - tdn) + tm;
-            const double inv = 1.0 / df;
+            const double inv = rcp_refined(df);
 #pragma unroll
             for (int c = 0; c < CW; ++c) acc[c] = fma(inv, qs[j * CW + c], acc[c]);
           }
