@@ -470,10 +470,22 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
     HIP_OK(hipGetLastError());
   }
   c->timer.mark(st, 6);
-  // ranks back to the host
-  for (auto& m : hb.ms)
-    HIP_OK(hipMemcpyAsync(m.nodes.data(), m.dev.nodes, m.nodes.size() * sizeof(HssNode), hipMemcpyDeviceToHost, st));
+  // ranks back to the host, through one pinned buffer
+  size_t nb = 0;
+  for (auto& m : hb.ms) nb += m.nodes.size() * sizeof(HssNode);
+  char* hp;
+  ADC_TRY(c->stage2(nb, (void**)&hp));
+  size_t ro = 0;
+  for (auto& m : hb.ms) {
+    HIP_OK(hipMemcpyAsync(hp + ro, m.dev.nodes, m.nodes.size() * sizeof(HssNode), hipMemcpyDeviceToHost, st));
+    ro += m.nodes.size() * sizeof(HssNode);
+  }
   HIP_OK(hipStreamSynchronize(st));
+  ro = 0;
+  for (auto& m : hb.ms) {
+    std::memcpy(m.nodes.data(), hp + ro, m.nodes.size() * sizeof(HssNode));
+    ro += m.nodes.size() * sizeof(HssNode);
+  }
   (void)rep;
   for (auto& m : hb.ms) {
     m.max_rank = 0;
@@ -1061,24 +1073,42 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
   for (int g = 0; g < nm; ++g)
     if (h_m[g].mode == 1) which.push_back(g);
   if (which.empty()) return ADC_OK;
+  // the host inputs of every merge (leaf bounds moved on the device, d, gam,
+  // mu, the column groups of every leaf of the packed operand) in one pinned
+  // buffer: all copies queued, one synchronisation
+  std::vector<size_t> hoff(which.size() + 1, 0);
+  for (size_t t = 0; t < which.size(); ++t) {
+    const MergeDev& M = h_m[which[t]];
+    const int L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
+    if (M.nleaf != (1 << L) || !M.lbounds) return ADC_ERR_ARG;
+    const size_t b = 3 * (size_t)M.K * 8 + (size_t)(M.nleaf + 1) * 4 + 3 * (size_t)M.nleaf * 4;
+    hoff[t + 1] = hoff[t] + ((b + 255) & ~(size_t)255);
+  }
+  char* hp;
+  ADC_TRY(c->stage2(hoff.back(), (void**)&hp));
+  for (size_t t = 0; t < which.size(); ++t) {
+    const MergeDev& M = h_m[which[t]];
+    char* q = hp + hoff[t];
+    HIP_OK(hipMemcpyAsync(q, B.dS + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(q + (size_t)M.K * 8, B.gam + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(q + 2 * (size_t)M.K * 8, B.mu + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
+    char* qi = q + 3 * (size_t)M.K * 8;
+    HIP_OK(hipMemcpyAsync(qi, M.lbounds, (M.nleaf + 1) * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(qi + (M.nleaf + 1) * 4, B.lcnt + M.s0, 3 * (size_t)M.nleaf * 4, hipMemcpyDeviceToHost,
+                          st));
+  }
+  HIP_OK(hipStreamSynchronize(st));
   for (size_t t = 0; t < which.size(); ++t) {
     const MergeDev& M = h_m[which[t]];
     HssBatch::One m;
     m.K = M.K;
     m.L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
-    // the leaves the packing grouped the columns by (moved on the device)
-    if (M.nleaf != (1 << m.L) || !M.lbounds) return ADC_ERR_ARG;
-    m.bounds.resize(M.nleaf + 1);
-    HIP_OK(hipMemcpyAsync(m.bounds.data(), M.lbounds, m.bounds.size() * 4, hipMemcpyDeviceToHost, st));
+    const double* q = (const double*)(hp + hoff[t]);
+    const int32_t* qi = (const int32_t*)(q + 3 * (size_t)M.K);
+    m.bounds.assign(qi, qi + M.nleaf + 1);
+    m.grp.assign(qi + M.nleaf + 1, qi + M.nleaf + 1 + 3 * (size_t)M.nleaf);
     m.stream = (uint32_t)((depth << 20) + which[t]);
-    std::vector<double> d(M.K), g2(M.K), mu(M.K);
-    HIP_OK(hipMemcpyAsync(d.data(), B.dS + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(g2.data(), B.gam + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(mu.data(), B.mu + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
-    // column groups of every leaf of the packed operand (k_leaf_group)
-    m.grp.resize(3 * (size_t)M.nleaf);
-    HIP_OK(hipMemcpyAsync(m.grp.data(), B.lcnt + M.s0, m.grp.size() * 4, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    std::vector<double> d(q, q + M.K), g2(q + M.K, q + 2 * (size_t)M.K), mu(q + 2 * (size_t)M.K, q + 3 * (size_t)M.K);
     m.r = hss_rank_estimate(d.data(), g2.data(), mu.data(), M.K, m.bounds, o, false);
     if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
     if (o.rank_mode == ADC_RANK_MLP && !mlp_collecting(c))
