@@ -2,7 +2,7 @@
 
 Workload (the headline configuration): N = 32768 tridiagonal Toeplitz
 (diagonal 2, off-diagonal 1), DC leaf 32, randomized HSS update at the
-merges whose dense update would cost at least 1e11 flops (the top three
+merges whose dense update would cost at least 2.5e10 flops (the top four
 levels here; HSS leaf 128, p = 16, adaptive oversampling), compared
 with the plain dense FP64 MFMA update on the same GPU.
 
@@ -286,7 +286,7 @@ def run_families(torch, adc, ctx, sizes, steps):
     headline HSS options and with the dense update; median seconds of
     `steps` timed solves after one untimed one, residual and orthogonality of
     the HSS result, eigenvalue error where the spectrum has a closed form."""
-    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=1e11, oversample=16)
+    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=2.5e10, oversample=16)
     dense_opts = adc.opts(dc_leaf=32, force_dense=1)
     out = {}
     for kind in FAMILIES:
@@ -369,7 +369,7 @@ def main():
     ctx = adc.Context(0)
     w = torch.empty(N, dtype=torch.float64, device="cuda")
     Zt = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=1e11, oversample=16)
+    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=2.5e10, oversample=16)
     dense_opts = adc.opts(dc_leaf=32, force_dense=1)
 
     def run(o, steps, warm):
@@ -454,7 +454,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=1e11 flops, HSS leaf 128, p=16",
+        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=2.5e10 flops, HSS leaf 128, p=16",
                    "update": head, "n": N, "K_per_level": r0["K_per_level"],
                    "hss_per_level": r0["hss_per_level"], "max_rank": r0["max_rank"],
                    "samples": r0["samples"], "retries": r0["retries"], "fallbacks": r0["hss_fallbacks"]},

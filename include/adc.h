@@ -100,12 +100,12 @@ typedef struct adc_opts {
   double  shift_thresh;  /* [1e-10] move a boundary when its distance is below  */
   int32_t r_cap;         /* [100] cap of the estimated rank                     */
   double  rank_eps;      /* [1e-16] epsilon of eq. (bounds)                     */
-  double  hss_min_flops; /* [1e11] HSS update only if the merge's dense update,
-                            2 n1 K (k1+k2) + 2 n2 K (k2+k3) flops with the
-                            column classes of the deflated Q (Section 2.1),
-                            reaches this (about 2 ms of FP64 MFMA GEMM; the
-                            HSS route's fixed costs outweigh smaller
-                            updates); once one merge of a level qualifies,
+  double  hss_min_flops; /* [2.5e10] HSS update only if the merge's dense
+                            update, 2 n1 K (k1+k2) + 2 n2 K (k2+k3) flops
+                            with the column classes of the deflated Q
+                            (Section 2.1), reaches this (about 0.5 ms of FP64
+                            MFMA GEMM; the HSS route's fixed costs outweigh
+                            smaller updates); once one merge of a level qualifies,
                             merges of the level reaching a quarter of it
                             (and hss_min_k) join; 0 disables the test     */
   int32_t sample_mode;   /* [ADC_SAMPLE_FMM] adc_sample_mode: how Algorithm 2

@@ -44,7 +44,7 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   o->shift_thresh = 1e-10;
   o->r_cap = 100;
   o->rank_eps = 1e-16;
-  o->hss_min_flops = 1e11;
+  o->hss_min_flops = 2.5e10;
   o->sample_mode = ADC_SAMPLE_FMM;
   o->fmm_order = 20;
   return ADC_OK;

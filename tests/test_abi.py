@@ -45,7 +45,7 @@ def test_status_strings_and_defaults():
     o = adc.opts()
     assert (o.dc_leaf, o.hss_min_k, o.hss_leaf, o.oversample, o.r_cap) == (32, 2048, 128, 16, 100)
     assert o.id_tol == 1e-14 and o.rank_eps == 1e-16
-    assert o.hss_levels == -1 and o.hss_min_flops == 1e11
+    assert o.hss_levels == -1 and o.hss_min_flops == 2.5e10
 
 
 def test_product_does_not_use_the_oracle():
