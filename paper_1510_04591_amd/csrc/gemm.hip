@@ -26,7 +26,10 @@ namespace {
 constexpr int BK = 16;
 constexpr int PAD = 4;
 
-template <int BM, int BN, int WM, int WN>
+// PF2: the operand tiles of two K steps ahead in flight (two register sets);
+// otherwise one step ahead.  The deeper prefetch costs registers and pays
+// only where occupancy is not the limit (the 256 x 128 tiles).
+template <int BM, int BN, int WM, int WN, bool PF2>
 __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   constexpr int NT = 64 * WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN;  // rows / columns per wave
@@ -44,103 +47,198 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   const int Kt = P.K + P.K2;
 
   dbl4 acc[TM][TN];
-#pragma unroll
+  #pragma unroll
   for (int a = 0; a < TM; ++a)
-#pragma unroll
+    #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   gcdouble* const gA = gmem(P.A);
   gcdouble* const gA2 = gmem(P.A2);
   gcdouble* const gB = gmem(P.B);
   gcdouble* const gB2 = gmem(P.B2);
-  double ra[ALOADS], rb[BLOADS];
-  // A K step lies entirely in one segment: steps of the first segment start
-  // at multiples of BK below P.K and stop at P.K; those of the second start
-  // at P.K + multiples of BK.
-  auto gload = [&](int k0) {
-    const bool s1 = k0 < P.K;
-    const int lim = s1 ? P.K : Kt;
-#pragma unroll
-    for (int q = 0; q < ALOADS; ++q) {
-      const int e = tid + NT * q;
-      const int r = e % BM, c = e / BM;
-      const int gr = m0 + r, gk = k0 + c;
-      double x = 0.0;
-      if (gr < M && gk < lim) x = s1 ? gA[gr + (int64_t)gk * P.lda] : gA2[gr + (int64_t)(gk - P.K) * P.lda2];
-      ra[q] = x;
-    }
-    const bool tr = s1 ? P.transB : P.transB2;
-#pragma unroll
-    for (int q = 0; q < BLOADS; ++q) {
-      const int e = tid + NT * q;
-      const int kr = tr ? e / BN : (e % BK);
-      const int cc = tr ? e % BN : (e / BK);
-      const int gk = k0 + kr, gn = n0 + cc;
-      double x = 0.0;
-      if (gk < lim && gn < N) {
-        if (s1) x = tr ? gB[gn + (int64_t)gk * P.ldb] : gB[gk + (int64_t)gn * P.ldb];
-        else {
-          const int g2 = gk - P.K;
-          x = tr ? gB2[gn + (int64_t)g2 * P.ldb2] : gB2[g2 + (int64_t)gn * P.ldb2];
-        }
+  if constexpr (PF2) {
+    // Two register sets of operand loads: the tile two K steps ahead is in
+    // flight while the next one is stored to LDS and the current one feeds
+    // the matrix cores (set indices are compile-time: the loop is unrolled
+    // by two).
+    double ra0[ALOADS], rb0[BLOADS], ra1[ALOADS], rb1[BLOADS];
+    // A K step lies entirely in one segment: steps of the first segment start
+    // at multiples of BK below P.K and stop at P.K; those of the second start
+    // at P.K + multiples of BK.
+    auto gload = [&](int k0, double* ra, double* rb) {
+      const bool s1 = k0 < P.K;
+      const int lim = s1 ? P.K : Kt;
+      #pragma unroll
+      for (int q = 0; q < ALOADS; ++q) {
+        const int e = tid + NT * q;
+        const int r = e % BM, c = e / BM;
+        const int gr = m0 + r, gk = k0 + c;
+        double x = 0.0;
+        if (gr < M && gk < lim) x = s1 ? gA[gr + (int64_t)gk * P.lda] : gA2[gr + (int64_t)(gk - P.K) * P.lda2];
+        ra[q] = x;
       }
-      rb[q] = x;
-    }
-  };
-  auto sstore = [&](int buf, int k0) {
-#pragma unroll
-    for (int q = 0; q < ALOADS; ++q) {
-      const int e = tid + NT * q;
-      As[buf][e / BM][e % BM] = ra[q];
-    }
-    const bool tr = (k0 < P.K) ? P.transB : P.transB2;
-#pragma unroll
-    for (int q = 0; q < BLOADS; ++q) {
-      const int e = tid + NT * q;
-      if (tr) Bs[buf][e / BN][e % BN] = rb[q];
-      else Bs[buf][e % BK][e / BK] = rb[q];
-    }
-  };
+      const bool tr = s1 ? P.transB : P.transB2;
+      #pragma unroll
+      for (int q = 0; q < BLOADS; ++q) {
+        const int e = tid + NT * q;
+        const int kr = tr ? e / BN : (e % BK);
+        const int cc = tr ? e % BN : (e / BK);
+        const int gk = k0 + kr, gn = n0 + cc;
+        double x = 0.0;
+        if (gk < lim && gn < N) {
+          if (s1) x = tr ? gB[gn + (int64_t)gk * P.ldb] : gB[gk + (int64_t)gn * P.ldb];
+          else {
+            const int g2 = gk - P.K;
+            x = tr ? gB2[gn + (int64_t)g2 * P.ldb2] : gB2[g2 + (int64_t)gn * P.ldb2];
+          }
+        }
+        rb[q] = x;
+      }
+    };
+    auto sstore = [&](int buf, int k0, const double* ra, const double* rb) {
+      #pragma unroll
+      for (int q = 0; q < ALOADS; ++q) {
+        const int e = tid + NT * q;
+        As[buf][e / BM][e % BM] = ra[q];
+      }
+      const bool tr = (k0 < P.K) ? P.transB : P.transB2;
+      #pragma unroll
+      for (int q = 0; q < BLOADS; ++q) {
+        const int e = tid + NT * q;
+        if (tr) Bs[buf][e / BN][e % BN] = rb[q];
+        else Bs[buf][e % BK][e / BK] = rb[q];
+      }
+    };
 
-  const int nk1 = (P.K + BK - 1) / BK;
-  const int nk2 = (P.K2 + BK - 1) / BK;
-  const int nk = nk1 + nk2;
-  auto kstart = [&](int kt) { return kt < nk1 ? kt * BK : P.K + (kt - nk1) * BK; };
-  if (nk > 0) {
-    gload(kstart(0));
-    sstore(0, kstart(0));
+    const int nk1 = (P.K + BK - 1) / BK;
+    const int nk2 = (P.K2 + BK - 1) / BK;
+    const int nk = nk1 + nk2;
+    auto kstart = [&](int kt) { return kt < nk1 ? kt * BK : P.K + (kt - nk1) * BK; };
+    auto mfma_step = [&](int buf) {
+      #pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int k = kk * 4 + lk;
+        double av[TM], bv[TN];
+        #pragma unroll
+        for (int t = 0; t < TM; ++t) av[t] = As[buf][k][wm * WTM + t * 16 + li];
+        #pragma unroll
+        for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][k][wn * WTN + t * 16 + li];
+        #pragma unroll
+        for (int a = 0; a < TM; ++a)
+          #pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    };
+    // step kt: LDS buffer kt & 1 holds tile kt; the set `nx` holds tile kt + 1
+    // (stored at the end of the step), the set `fr` is free and receives tile
+    // kt + 2
+    auto step = [&](int kt, const double* nxa, const double* nxb, double* fra, double* frb) {
+      if (kt + 2 < nk) gload(kstart(kt + 2), fra, frb);
+      mfma_step(kt & 1);
+      if (kt + 1 < nk) sstore((kt + 1) & 1, kstart(kt + 1), nxa, nxb);
+      __syncthreads();
+    };
+    if (nk > 0) {
+      gload(kstart(0), ra0, rb0);
+      sstore(0, kstart(0), ra0, rb0);
+    }
+    if (nk > 1) gload(kstart(1), ra1, rb1);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, ra1, rb1, ra0, rb0);
+      if (kt + 1 < nk) step(kt + 1, ra0, rb0, ra1, rb1);
+    }
+  } else {
+    double ra[ALOADS], rb[BLOADS];
+    // A K step lies entirely in one segment: steps of the first segment start
+    // at multiples of BK below P.K and stop at P.K; those of the second start
+    // at P.K + multiples of BK.
+    auto gload = [&](int k0) {
+      const bool s1 = k0 < P.K;
+      const int lim = s1 ? P.K : Kt;
+      #pragma unroll
+      for (int q = 0; q < ALOADS; ++q) {
+        const int e = tid + NT * q;
+        const int r = e % BM, c = e / BM;
+        const int gr = m0 + r, gk = k0 + c;
+        double x = 0.0;
+        if (gr < M && gk < lim) x = s1 ? gA[gr + (int64_t)gk * P.lda] : gA2[gr + (int64_t)(gk - P.K) * P.lda2];
+        ra[q] = x;
+      }
+      const bool tr = s1 ? P.transB : P.transB2;
+      #pragma unroll
+      for (int q = 0; q < BLOADS; ++q) {
+        const int e = tid + NT * q;
+        const int kr = tr ? e / BN : (e % BK);
+        const int cc = tr ? e % BN : (e / BK);
+        const int gk = k0 + kr, gn = n0 + cc;
+        double x = 0.0;
+        if (gk < lim && gn < N) {
+          if (s1) x = tr ? gB[gn + (int64_t)gk * P.ldb] : gB[gk + (int64_t)gn * P.ldb];
+          else {
+            const int g2 = gk - P.K;
+            x = tr ? gB2[gn + (int64_t)g2 * P.ldb2] : gB2[g2 + (int64_t)gn * P.ldb2];
+          }
+        }
+        rb[q] = x;
+      }
+    };
+    auto sstore = [&](int buf, int k0) {
+      #pragma unroll
+      for (int q = 0; q < ALOADS; ++q) {
+        const int e = tid + NT * q;
+        As[buf][e / BM][e % BM] = ra[q];
+      }
+      const bool tr = (k0 < P.K) ? P.transB : P.transB2;
+      #pragma unroll
+      for (int q = 0; q < BLOADS; ++q) {
+        const int e = tid + NT * q;
+        if (tr) Bs[buf][e / BN][e % BN] = rb[q];
+        else Bs[buf][e % BK][e / BK] = rb[q];
+      }
+    };
+
+    const int nk1 = (P.K + BK - 1) / BK;
+    const int nk2 = (P.K2 + BK - 1) / BK;
+    const int nk = nk1 + nk2;
+    auto kstart = [&](int kt) { return kt < nk1 ? kt * BK : P.K + (kt - nk1) * BK; };
+    if (nk > 0) {
+      gload(kstart(0));
+      sstore(0, kstart(0));
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload(kstart(kt + 1));
-#pragma unroll
+    #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int k = kk * 4 + lk;
       double av[TM], bv[TN];
-#pragma unroll
+      #pragma unroll
       for (int t = 0; t < TM; ++t) av[t] = As[buf][k][wm * WTM + t * 16 + li];
-#pragma unroll
+      #pragma unroll
       for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][k][wn * WTN + t * 16 + li];
-#pragma unroll
+      #pragma unroll
       for (int a = 0; a < TM; ++a)
-#pragma unroll
+        #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     if (kt + 1 < nk) sstore(buf ^ 1, kstart(kt + 1));
     __syncthreads();
   }
 
-#pragma unroll
+  }
+  #pragma unroll
   for (int b = 0; b < TN; ++b) {
     const int col = n0 + wn * WTN + b * 16 + li;
     if (col >= N) continue;
     const double vs = P.vscale ? gmem(P.vscale)[col] : 1.0;
     const int64_t cc = (int64_t)(P.colmap ? gmem(P.colmap)[col] : col) * P.ldc;
-#pragma unroll
+    #pragma unroll
     for (int a = 0; a < TM; ++a) {
       const int row0 = m0 + wm * WTM + a * 16 + lk;
-#pragma unroll
+      #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * r;
         if (row < M) {
@@ -163,13 +261,13 @@ __device__ __forceinline__ int find_prob(const GemmProb* __restrict__ probs, int
 }
 }  // namespace
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool PF2 = false>
 __device__ __forceinline__ void gemm_dispatch(const GemmProb* __restrict__ probs, int nprobs) {
   const GemmProb P = probs[find_prob(probs, nprobs, blockIdx.x)];
   const int local = blockIdx.x - P.tile0;
   const int m0 = (local % P.tiles_m) * BM, n0 = (local / P.tiles_m) * BN;
   if (m0 >= P.M || n0 >= P.N) return;
-  gemm_tile<BM, BN, WM, WN>(P, m0, n0);
+  gemm_tile<BM, BN, WM, WN, PF2>(P, m0, n0);
 }
 
 __global__ void __launch_bounds__(512) k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs) {
@@ -185,5 +283,5 @@ __global__ void __launch_bounds__(512) k_gemm_f64_n96(const GemmProb* __restrict
 }
 
 __global__ void __launch_bounds__(1024) k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs) {
-  gemm_dispatch<256, 128, 4, 4>(probs, nprobs);
+  gemm_dispatch<256, 128, 4, 4, true>(probs, nprobs);
 }
