@@ -95,7 +95,8 @@ adc_status adc_ctx_s::side_stream() {
     return ADC_ERR_HIP;
   }
   if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_probe, hipEventDisableTiming) != hipSuccess)
     return ADC_ERR_HIP;
   return ADC_OK;
 }
@@ -108,7 +109,8 @@ void adc_ctx_s::release() {
   }
   if (ev_fork) hipEventDestroy(ev_fork);
   if (ev_join) hipEventDestroy(ev_join);
-  ev_fork = ev_join = nullptr;
+  if (ev_probe) hipEventDestroy(ev_probe);
+  ev_fork = ev_join = ev_probe = nullptr;
   for (auto& b : bufs) {
     if (b.ptr) hipFree(b.ptr);
     b.ptr = nullptr;

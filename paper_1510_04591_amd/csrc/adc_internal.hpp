@@ -157,7 +157,7 @@ struct adc_ctx_s {
   // second stream (default priority) for work that overlaps the HSS
   // construction inside one level; joined back before the level ends
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_probe = nullptr;
   adc_status side_stream();
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);

@@ -868,8 +868,7 @@ struct CheckBufs {
 constexpr int CHECK_NBLK = 128;  // blocks of the norm partial sums
 
 static adc_status check_prepare(adc_ctx c, HssBatch& hb, const adc_opts& o, CheckBufs& cb,
-                                std::vector<ApplyJob>& aj) {
-  hipStream_t st = c->stream;
+                                std::vector<ApplyJob>& aj, hipStream_t st) {
   const int nm = (int)hb.ms.size();
   int64_t tot = 0, part_max = 0;
   cb.base.assign(nm, 0);
@@ -950,7 +949,7 @@ static adc_status check_finish(adc_ctx c, HssBatch& hb, const adc_opts& o, const
 static adc_status batch_check(adc_ctx c, HssBatch& hb, const adc_opts& o, double* flops) {
   CheckBufs cb;
   std::vector<ApplyJob> aj;
-  ADC_TRY(check_prepare(c, hb, o, cb, aj));
+  ADC_TRY(check_prepare(c, hb, o, cb, aj, c->stream));
   ADC_TRY(batch_apply(c, hb, aj, flops));
   return check_finish(c, hb, o, cb);
 }
@@ -1126,17 +1125,35 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     hb.ms.push_back(std::move(m));
   }
   hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
-  hb.after_sampling = after_sampling;
+  // Once the first sampling pass is queued: the caller's work for the side
+  // stream (packing, dense merges), then the first check's probes (W and
+  // W^T Q', which read only the generators) on the same stream, so that they
+  // overlap the compression; the main stream waits for them (ev_probe)
+  // before the products that read W.
+  CheckBufs cb;
+  std::vector<ApplyJob> aj0;
+  bool probes_queued = false;
+  adc_status probe_st = ADC_OK;
+  hb.after_sampling = [&]() {
+    if (after_sampling) after_sampling();
+    if (!c->side || !c->ev_probe) return;
+    probe_st = check_prepare(c, hb, o, cb, aj0, c->side);
+    if (probe_st == ADC_OK && hipEventRecord(c->ev_probe, c->side) == hipSuccess) probes_queued = true;
+  };
   // First attempt.  Its accuracy check shares the launches of the update
   // product: the probe products W H and the products of the packed operand
   // by every merge's HSS form run together once the operand is ready.  The
   // columns of a merge that fails the check are written again afterwards
   // (by its retry or by the dense fallback), so writing them now is harmless.
   batch_init_s(hb, o);
-  ADC_TRY(batch_attempt(c, hb, o, SLOT_HSS, false, rep, flops, nullptr));
-  CheckBufs cb;
-  std::vector<ApplyJob> aj0;
-  ADC_TRY(check_prepare(c, hb, o, cb, aj0));
+  const adc_status ast = batch_attempt(c, hb, o, SLOT_HSS, false, rep, flops, nullptr);
+  if (probes_queued) HIP_OK(hipStreamWaitEvent(st, c->ev_probe, 0));  // also before an error return
+  ADC_TRY(ast);
+  ADC_TRY(probe_st);
+  if (!probes_queued) {
+    aj0.clear();
+    ADC_TRY(check_prepare(c, hb, o, cb, aj0, st));
+  }
   for (size_t t = 0; t < which.size(); ++t) push_update_jobs(aj0, (int)t, h_m[which[t]], B);
   if (operand_ready) HIP_OK(hipStreamWaitEvent(st, operand_ready, 0));  // the packed operand
   double fm = 0.0;
