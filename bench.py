@@ -33,17 +33,17 @@ sys.path.insert(0, ROOT)
 # SHA-256); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_gemm_f64_n64": {"bytes_per_launch": 719.6e6,
-                       "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "d048cafa6cd65898"}},
+                       "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "7278b19ea3154e7e"}},
     "k_gemm_f64": {"bytes_per_launch": 2045.1e6,
-                   "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "d048cafa6cd65898"}},
+                   "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "7278b19ea3154e7e"}},
     "k_gemm_f64_n96": {"bytes_per_launch": 273.8e6,
-                       "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "d048cafa6cd65898"}},
-    "k_pack_rot": {"bytes_per_launch": 2301.6e6,
+                       "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "7278b19ea3154e7e"}},
+    "k_pack_rot": {"bytes_per_launch": 2301.7e6,
                    "sources": {"merge.hip": "1f400c597a1f5ad8", "dc.hip": "469bfa54635284c3"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 32105.7e6,
+    "k_gemm_f64_big": {"bytes_per_launch": 35894.9e6,
                        "sources": {"gemm.hip": "87b930b274babbc4", "dc.hip": "469bfa54635284c3"}},
 }
 
