@@ -84,6 +84,23 @@ def random_merge(K, seed=0, spread="uniform"):
     return d, z / np.linalg.norm(z), float(rng.uniform(0.5, 2.0))
 
 
+def planted_merge(K, pairs, seed=0):
+    """Random rank-one problem with planted close poles: d sorted U(0, 1)
+    with d[j] = d[j-1] + gap for every (j, gap) in `pairs` (pairs applied in
+    index order, the rest of d shifted to stay increasing), z a random unit
+    vector, rho = 1."""
+    rng = np.random.default_rng(seed)
+    g = rng.uniform(0.5, 1.5, K)
+    for j, gap in pairs:
+        g[j] = 0.0
+    d = np.cumsum(g)
+    d = d / d[-1]
+    for j, gap in sorted(pairs):
+        d[j:] += (d[j - 1] + gap) - d[j]
+    z = rng.standard_normal(K)
+    return d, z / np.linalg.norm(z), 1.0
+
+
 def spectrum(kind, N, seed=5):
     """Prescribed spectra: 'uniform' sorted U(0,1); 'geometric' 10^(-6(i-1)/(N-1));
     'clusters' 10 clusters centred at (k+0.5)/10 of width 1e-8."""

@@ -143,3 +143,49 @@ def test_boundary_targets_and_predicted_rank():
     assert mlp.predicted_rank(np.log2([3.0, 9.0, 7.0])) == 16  # ceil(1.25 * 9) + 4
     assert mlp.predicted_rank(np.array([0.0])) == 8
     assert mlp.predicted_rank(np.array([9.0])) == 100
+
+
+def test_features_by_hand():
+    """All 16 features of a tiny merge, worked out by hand from the feature
+    definitions (module docstring of oracle/mlp.py).  K = 8 poles, leaves
+    [0,2) [2,4) [4,6) [6,8), boundaries p = 2, 4, 6.  Pole gaps g = 1 1 2 1 1 2 2,
+    gam = 1/4 1/2 1 1/4 1/2 1 1 6, mu = g - gam (mu_7 = inf), so
+    lam = 0.25 1.5 3 4.25 5.5 7 9 16 and span = lam_7 - d_0 = 16.  By
+    interlacing, dist(q) = mu_{q-1}: dist(1..7) = 3/4 1/2 1 3/4 1/2 1 1."""
+    d = np.array([0.0, 1, 2, 4, 5, 6, 8, 10])
+    gam = np.array([0.25, 0.5, 1.0, 0.25, 0.5, 1.0, 1.0, 6.0])
+    mu = np.array([0.75, 0.5, 1.0, 0.75, 0.5, 1.0, 1.0, np.inf])
+    F = mlp.features(d, gam, mu, [0, 2, 4, 6, 8])
+    l2 = math.log2
+    s2 = math.sqrt(2.0) / 3.0  # std of log2 gaps {-4,-4,-3} and {-4,-3,-3}
+    want = [
+        # p = 2: window [0,4); gaps 1 1 2 -> log2(g/16) = -4 -4 -3;
+        # min(gam, mu) = 1/4 1/2 1 1/4 -> log2(./16) = -6 -5 -4 -6
+        [3 / 16, 1 / 8, 1 / 8, l2(16 / 0.5) / 32, l2(16 / 0.5) / 32,
+         -4 / 32, (-11 / 3) / 32, -3 / 32, s2 / 8, (-21 / 4) / 32, -6 / 32,
+         0.0, 2 / 8, l2(4) / 8, l2(4 / 16) / 32, l2(0.5 / 1) / 32],
+        # p = 4: window [2,6); gaps 2 1 1; min(gam, mu) = 1 1/4 1/2 1;
+        # dist(4) = 3/4, min dist over q = 3, 4, 5 is 1/2
+        [3 / 16, 1 / 8, 1 / 8, l2(16 / 0.75) / 32, l2(16 / 0.5) / 32,
+         -4 / 32, (-11 / 3) / 32, -3 / 32, s2 / 8, (-19 / 4) / 32, -6 / 32,
+         0.0, 4 / 8, l2(4) / 8, l2(4 / 16) / 32, l2(0.75 / 1) / 32],
+        # p = 6: window [4,8); gaps 1 2 2; min(gam, mu) = 1/2 1 1 6;
+        # dist(6) = 1, min dist over q = 5, 6, 7 is 1/2
+        [3 / 16, 1 / 8, 1 / 8, l2(16 / 1.0) / 32, l2(16 / 0.5) / 32,
+         -4 / 32, (-10 / 3) / 32, -3 / 32, s2 / 8, ((-13 + l2(6 / 16)) / 4) / 32, -5 / 32,
+         0.0, 6 / 8, l2(4) / 8, l2(5 / 16) / 32, l2(1 / 2) / 32],
+    ]
+    assert np.max(np.abs(F - np.array(want))) <= 1e-15
+
+
+def test_feature_11_counts_tiny_gaps():
+    """Feature 11 by hand: K = 6, one window [0, 6) (two leaves); pole gaps
+    1 1e-12 1 1 2 over span 16 -> one of five gaps is below 1e-10 span."""
+    d = np.array([0.0, 1.0, 1.0 + 1e-12, 2.0 + 1e-12, 3.0 + 1e-12, 5.0 + 1e-12])
+    gap = np.diff(d)
+    gam = np.concatenate([gap / 2, [16.0 - d[-1]]])
+    mu = np.concatenate([gap - gap / 2, [np.inf]])
+    F = mlp.features(d, gam, mu, [0, 3, 6])
+    assert F.shape == (1, 16)
+    assert F[0, 11] == 1 / 5
+    assert F[0, 13] == 1 / 8  # log2(2 leaves) / 8
