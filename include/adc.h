@@ -77,8 +77,8 @@ typedef enum adc_sample_mode { ADC_SAMPLE_DIRECT = 0, ADC_SAMPLE_FMM = 1 } adc_s
 typedef struct adc_opts {
   int32_t dc_leaf;       /* [32] DC leaf size m (Algorithm 1); 2..64            */
   int32_t hss_min_k;     /* [2048] HSS update only if the deflated size K >= this
-                            (and K >= 8 in any case)
-                            (Section 4.3 uses "larger than 2000")             */
+                            (and K >= 8 in any case); Section 4.3 sets the
+                            threshold near 2000 for its CPUs                   */
   int32_t hss_levels;    /* [-1] only the top hss_levels merge levels may use
                             HSS; <0 means every level                         */
   int32_t hss_leaf;      /* [128] HSS leaf size (rows per leaf node)          */
@@ -112,6 +112,12 @@ typedef struct adc_opts {
                             takes its samples                                */
   int32_t fmm_order;     /* [20] Chebyshev points per tree node of the fast
                             sampling, 4..32                                  */
+  int32_t sat_guard;     /* [0] 1: an HSS merge whose interpolative
+                            decompositions saturate (a node rank equal to s
+                            with more than s candidates, so the samples may
+                            not span the block) fails its check like a large
+                            probe error: its samples double and it is rebuilt;
+                            0: saturated merges are only counted            */
 } adc_opts;
 
 /* Report of one solve (host struct, optional). */
@@ -136,7 +142,12 @@ typedef struct adc_report {
                                 10 total wall time (host clock), 11 wall time
                                 not covered by phases 0-9                      */
   double  phase_flops[12];   /* algorithmic flops per phase (same indices)     */
-  double  phase_bytes[12];   /* algorithmic HBM bytes per phase                */
+  double  phase_bytes[12];   /* algorithmic HBM bytes per phase; for 8 (HSS
+                                multiply) the least traffic of Algorithm 3 over
+                                the accepted HSS merges' update products:
+                                24 P K + 16 P K r/m bytes per merge (P rows,
+                                K columns, r the mean node rank, m the mean
+                                leaf size)                                     */
   int32_t phase_launches[12];/* kernel launches of the phase's main kernel     */
   double  flops_model;       /* algorithmic flops of the eigenvector updates   */
   double  bytes_model;       /* algorithmic HBM bytes of the updates           */
@@ -154,6 +165,9 @@ typedef struct adc_report {
   double  kern_flops[12];
   double  kern_bytes[12];
   int32_t kern_launches[12];
+  int32_t hss_saturated;     /* accepted HSS merges with a saturated node
+                                (see adc_opts.sat_guard)                      */
+  int32_t hss_sat_nodes;     /* saturated nodes in those merges              */
 } adc_report;
 
 /* ---------------------------------------------------------------- context */
@@ -223,6 +237,22 @@ adc_status adc_lowner(adc_ctx ctx, int64_t K, const double* d, const double* z, 
 adc_status adc_cauchy_gemm(adc_ctx ctx, int64_t P, int64_t K, const double* d, const double* gam,
                            const double* mu, const double* uh, const double* v,
                            const double* X, int64_t ldx, double* Y, int64_t ldy);
+
+/* Rank estimate of Section 4.1 for one merge, the solver's own kernel: the
+ * balanced leaf boundaries for opts->hss_leaf (L = ceil(log2(K / hss_leaf))
+ * levels, at least one) are moved where two neighbouring segments are closer
+ * than opts->shift_thresh (by at most opts->shift_max rows, to the largest
+ * distance, boundaries in order), then *r = min(opts->r_cap, max over the
+ * interior boundaries of ceil(log(16/eps) log(8R) / pi^2)) (eq. bounds, eps =
+ * opts->rank_eps) with R = (lam_K - d_1) / dist and dist the distance of the
+ * two segments by eq. (dist_xy), every difference by eq. (d-lambda).
+ * d, gam, mu: device FP64 generators (d increasing, K >= 2).  bounds: host
+ * array of bounds_cap entries receiving the 2^L + 1 moved boundaries (first
+ * 0, last K); *nbounds (host, may be NULL) gets 2^L + 1; ADC_ERR_ARG when
+ * bounds_cap is smaller.  Blocking. */
+adc_status adc_rank_estimate(adc_ctx ctx, int64_t K, const double* d, const double* gam,
+                             const double* mu, const adc_opts* opts, int32_t* r, int32_t* bounds,
+                             int32_t bounds_cap, int32_t* nbounds);
 
 /* Randomized HSS approximation H ~ Q' (Algorithm 2) of the Cauchy-like matrix
  * with generators (d, gam, mu, uh, v).  omega: K x s row-major Gaussian

@@ -37,7 +37,7 @@ class adc_opts(C.Structure):
         ("strict", C.c_int32), ("check_tol", C.c_double), ("nprobe", C.c_int32),
         ("shift_max", C.c_int32), ("shift_thresh", C.c_double), ("r_cap", C.c_int32),
         ("rank_eps", C.c_double), ("hss_min_flops", C.c_double), ("sample_mode", C.c_int32),
-        ("fmm_order", C.c_int32),
+        ("fmm_order", C.c_int32), ("sat_guard", C.c_int32),
     ]
 
 
@@ -51,7 +51,7 @@ class adc_report(C.Structure):
         ("phase_launches", C.c_int32 * 12), ("flops_model", C.c_double), ("bytes_model", C.c_double),
         ("check_err_max", C.c_double),
         ("kern_time", C.c_double * 12), ("kern_flops", C.c_double * 12), ("kern_bytes", C.c_double * 12),
-        ("kern_launches", C.c_int32 * 12),
+        ("kern_launches", C.c_int32 * 12), ("hss_saturated", C.c_int32), ("hss_sat_nodes", C.c_int32),
     ]
 
     KERNELS = ("k_gemm_f64", "k_gemm_f64_n64", "k_hss_sample", "k_pack_rot", "k_secular", "k_hss_compress",
@@ -68,7 +68,8 @@ class adc_report(C.Structure):
                     flops_model=self.flops_model,
                     bytes_model=self.bytes_model, check_err_max=self.check_err_max,
                     kern_time=list(self.kern_time), kern_flops=list(self.kern_flops),
-                    kern_bytes=list(self.kern_bytes), kern_launches=list(self.kern_launches))
+                    kern_bytes=list(self.kern_bytes), kern_launches=list(self.kern_launches),
+                    hss_saturated=self.hss_saturated, hss_sat_nodes=self.hss_sat_nodes)
 
 
 class AdcError(RuntimeError):
@@ -97,6 +98,8 @@ _SIGS = {
     "adc_cauchy_gemm": (_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _I64),
     "adc_hss_build": (_P, _I64, _P, _P, _P, _P, _P, _P, _I32, C.POINTER(adc_opts), C.POINTER(_P)),
     "adc_hss_apply": (_P, _P, _I64, _P, _I64, _P, _I64),
+    "adc_rank_estimate": (_P, _I64, _P, _P, _P, C.POINTER(adc_opts), C.POINTER(_I32), C.POINTER(_I32), _I32,
+                          C.POINTER(_I32)),
     "adc_hss_sample": (_P, _I64, _P, _P, _P, _P, _P, _P, _I32, C.POINTER(adc_opts), _P, _P),
     "adc_hss_info": (_P, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                      C.POINTER(_I32), C.POINTER(_D)),
@@ -215,6 +218,16 @@ def adc_hss_build(ctx, K, d, gam, mu, uh, v, omega, s, o=None):
 def adc_hss_sample(ctx, K, d, gam, mu, uh, v, omega, s, o, phi, theta):
     return lib().adc_hss_sample(ctx, int(K), _ptr(d), _ptr(gam), _ptr(mu), _ptr(uh), _ptr(v), _ptr(omega), int(s),
                                 C.byref(o) if o is not None else None, _ptr(phi), _ptr(theta))
+
+
+def adc_rank_estimate(ctx, K, d, gam, mu, o=None, cap=1 << 16):
+    """(status, r, moved leaf boundaries) of the library's rank estimate."""
+    r = _I32()
+    nb = _I32()
+    arr = (_I32 * cap)()
+    st = lib().adc_rank_estimate(ctx, int(K), _ptr(d), _ptr(gam), _ptr(mu), C.byref(o) if o is not None else None,
+                                 C.byref(r), arr, int(cap), C.byref(nb))
+    return st, r.value, [arr[i] for i in range(min(nb.value, cap))] if st == 0 else []
 
 
 def adc_hss_apply(ctx, h, P, X, ldx, Y, ldy):

@@ -47,6 +47,7 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   o->hss_min_flops = 2.5e10;
   o->sample_mode = ADC_SAMPLE_FMM;
   o->fmm_order = 20;
+  o->sat_guard = 0;
   return ADC_OK;
 }
 
@@ -60,6 +61,7 @@ adc_status validate_opts_ext(const adc_opts& o) {
   if (o.sample_mode < 0 || o.sample_mode > 1 || o.fmm_order < 4 || o.fmm_order > 32) return ADC_ERR_ARG;
   if (o.shift_max < 0 || o.shift_max > 64) return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
+  if (o.sat_guard < 0 || o.sat_guard > 1) return ADC_ERR_ARG;
   return ADC_OK;
 }
 

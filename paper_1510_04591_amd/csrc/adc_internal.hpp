@@ -22,6 +22,7 @@ enum Slot {
   SLOT_GEMM_A,     // grouped GEMM descriptors (narrow tiles)
   SLOT_GEMM_B,     // grouped GEMM descriptors (wide tiles)
   SLOT_FB,         // dense-fallback descriptors
+  SLOT_RANK,       // one-merge rank-estimate descriptor
   NSLOT
 };
 
@@ -216,7 +217,8 @@ bool mlp_collecting(adc_ctx c);
 adc_status mlp_collect_merge(adc_ctx c, const double* d, const double* gam, const double* mu, int K,
                              const std::vector<int>& bounds, const std::vector<int>& lo, const std::vector<int>& hi,
                              const std::vector<int>& kr, const std::vector<int>& kc);
-// Rank estimate of eq. (bounds) over leaf boundaries (moves boundaries closer
-// than shift_thresh unless shift is false).
-int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
-                      const adc_opts& o, bool shift = true);
+// Rank estimate of eq. (bounds) over the leaf boundaries of one merge
+// (device generators), moving boundaries closer than shift_thresh: `bounds`
+// in balanced, out moved.
+adc_status device_rank_estimate(adc_ctx c, const double* d, const double* gam, const double* mu, int K,
+                                std::vector<int>& bounds, const adc_opts& o, int* r);

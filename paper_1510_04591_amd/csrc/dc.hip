@@ -516,7 +516,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     }
     if (!lg_jobs.empty()) {
       hipLaunchKernelGGL(k_leaf_bounds, dim3((unsigned)lg_merges.size()), dim3(64), 0, st, d_m, d_lgm, B,
-                         o.shift_thresh, o.shift_max);
+                         o.shift_thresh, o.shift_max, o.rank_eps, o.r_cap);
       hipLaunchKernelGGL(k_leaf_group, dim3((unsigned)lg_jobs.size()), dim3(512), 0, st, d_m, d_lg, B);
     }
     // The packing and the dense merges' update.  With HSS merges in the

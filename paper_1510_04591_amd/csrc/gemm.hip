@@ -1,6 +1,6 @@
-// Grouped FP64 MFMA GEMM used by the dense update (Algorithm 1, "compute
-// Q = diag(Q1, Q2) Q'") and by every generator product of the HSS multiply
-// (Algorithm 3).
+// Grouped FP64 MFMA GEMM used by the dense update (Algorithm 1: the block
+// diagonal of the children's eigenvectors times the Cauchy-like Q') and by
+// every generator product of the HSS multiply (Algorithm 3).
 //
 // For each problem: C(:, colmap[j]) = beta C(:, colmap[j]) + vscale[j] *
 // ([A A2] [B; B2])(:, j), all column-major, the inner dimension split into a

@@ -36,54 +36,48 @@ std::vector<int> balanced_bounds(int K, int L) {
   return b;
 }
 
-// smallest integer r >= log(16/eps) log(8R) / pi^2  (eq. bounds)
-int rank_bound(double R, double eps) {
-  return (int)std::ceil(std::log(16.0 / eps) * std::log(8.0 * R) / (M_PI * M_PI));
-}
-
-// distance of the segments split before index b: min(lam_b - d_{b-1}, d_b - lam_{b-1})
-double boundary_dist(const double* d, const double* gam, const double* mu, int K, int b) {
-  const double x = (b < K) ? (d[b] - d[b - 1]) + gam[b] : INFINITY;
-  const double y = mu[b - 1];
-  return std::min(std::fabs(x), std::fabs(y));
-}
-
 }  // namespace
 
 std::vector<int> hss_leaf_bounds(int K, int leaf) {
   return balanced_bounds(K, std::max(1, ceil_log2_ratio(K, leaf)));
 }
 
-// Rank estimate over the leaf boundaries (Section 4.1): every boundary closer
-// than shift_thresh is moved by up to shift_max indices to the largest
-// distance; r = min(r_cap, max_b rank_bound((lam_K - d_1)/dist_b)).
-int hss_rank_estimate(const double* d, const double* gam, const double* mu, int K, std::vector<int>& bounds,
-                      const adc_opts& o, bool shift) {
-  const double span = (d[K - 1] + gam[K - 1]) - d[0];
-  int r = 0;
-  for (size_t t = 1; t + 1 < bounds.size(); ++t) {
-    int b = bounds[t];
-    double dist = boundary_dist(d, gam, mu, K, b);
-    if (shift && dist < o.shift_thresh) {
-      int best = b;
-      double bd = dist;
-      const int lo = std::max(bounds[t - 1] + 1, b - o.shift_max);
-      const int hi = std::min(bounds[t + 1] - 1, b + o.shift_max);
-      for (int bb = lo; bb <= hi; ++bb) {
-        const double dd = boundary_dist(d, gam, mu, K, bb);
-        if (dd > bd) {
-          best = bb;
-          bd = dd;
-        }
-      }
-      bounds[t] = best;
-      dist = bd;
-    }
-    const double R = (dist > 0.0) ? span / dist : INFINITY;
-    const int rb = std::isfinite(R) ? std::min(o.r_cap, rank_bound(std::max(R, 1.0), o.rank_eps)) : o.r_cap;
-    r = std::max(r, rb);
-  }
-  return std::min(r, o.r_cap);
+// Rank estimate of eq. (bounds) with the boundary moves of Section 4.1 for
+// one merge whose generators d, gam, mu are device arrays: the solver's
+// kernel (k_leaf_bounds) on a one-merge descriptor.  `bounds` comes in
+// balanced and goes out moved.
+adc_status device_rank_estimate(adc_ctx c, const double* d, const double* gam, const double* mu, int K,
+                                std::vector<int>& bounds, const adc_opts& o, int* r) {
+  hipStream_t st = c->stream;
+  const int nleaf = (int)bounds.size() - 1;
+  void* dp;
+  const size_t need = 256 + sizeof(MergeDev) + 4 * (size_t)(nleaf + 1) + 256;
+  ADC_TRY(c->buffer(SLOT_RANK, need, &dp));
+  MergeDev md{};
+  md.s0 = 0;
+  md.n = K;
+  md.K = K;
+  md.nleaf = nleaf;
+  MergeDev* dm = (MergeDev*)dp;
+  int32_t* dw = (int32_t*)((char*)dp + sizeof(MergeDev));  // which[0] = 0
+  int32_t* db = dw + 64;
+  md.lbounds = db;
+  LevelBufs B{};
+  B.dS = const_cast<double*>(d);
+  B.gam = const_cast<double*>(gam);
+  B.mu = const_cast<double*>(mu);
+  const int32_t zero = 0;
+  HIP_OK(hipMemcpyAsync(dm, &md, sizeof(md), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(dw, &zero, 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(db, bounds.data(), 4 * (size_t)(nleaf + 1), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_leaf_bounds, dim3(1), dim3(64), 0, st, dm, dw, B, o.shift_thresh, o.shift_max, o.rank_eps,
+                     o.r_cap);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(bounds.data(), db, 4 * (size_t)(nleaf + 1), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(&md, dm, sizeof(md), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  *r = md.rest;
+  return ADC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -99,6 +93,7 @@ struct HssBatch {
     int64_t arena_n = 0, iarena_n = 0;
     bool pass = false;
     double err = 0.0;
+    int sat = 0;  // nodes whose row or column ID used every sample with more candidates
     int retries = 0;
     int max_rank = 0;
     std::vector<double> hd, hg, hmu;  // host copies of d, gam, mu (fast sampling lists)
@@ -489,7 +484,12 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   (void)rep;
   for (auto& m : hb.ms) {
     m.max_rank = 0;
-    for (size_t i = 1; i < m.nodes.size(); ++i) m.max_rank = std::max({m.max_rank, m.nodes[i].kr, m.nodes[i].kc});
+    m.sat = 0;
+    for (size_t i = 1; i < m.nodes.size(); ++i) {
+      const HssNode& nd = m.nodes[i];
+      m.max_rank = std::max({m.max_rank, nd.kr, nd.kc});
+      m.sat += (nd.kr >= m.s && nd.nr > m.s) || (nd.kc >= m.s && nd.nc > m.s);
+    }
   }
   return ADC_OK;
 }
@@ -941,7 +941,7 @@ static adc_status check_finish(adc_ctx c, HssBatch& hb, const adc_opts& o, const
   for (int g = 0; g < nm; ++g) {
     auto& m = hb.ms[g];
     m.err = (hn[2 * g + 1] > 0.0) ? std::sqrt(hn[2 * g] / hn[2 * g + 1]) : 0.0;
-    m.pass = std::isfinite(m.err) && m.err <= o.check_tol;
+    m.pass = std::isfinite(m.err) && m.err <= o.check_tol && !(o.sat_guard && m.sat > 0);
   }
   return ADC_OK;
 }
@@ -1080,7 +1080,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     const MergeDev& M = h_m[which[t]];
     const int L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
     if (M.nleaf != (1 << L) || !M.lbounds) return ADC_ERR_ARG;
-    const size_t b = 3 * (size_t)M.K * 8 + (size_t)(M.nleaf + 1) * 4 + 3 * (size_t)M.nleaf * 4;
+    const size_t b = 3 * (size_t)M.K * 8 + (size_t)(M.nleaf + 1) * 4 + 3 * (size_t)M.nleaf * 4 + 4;
     hoff[t + 1] = hoff[t] + ((b + 255) & ~(size_t)255);
   }
   char* hp;
@@ -1095,6 +1095,8 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     HIP_OK(hipMemcpyAsync(qi, M.lbounds, (M.nleaf + 1) * 4, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(qi + (M.nleaf + 1) * 4, B.lcnt + M.s0, 3 * (size_t)M.nleaf * 4, hipMemcpyDeviceToHost,
                           st));
+    HIP_OK(hipMemcpyAsync(qi + (M.nleaf + 1) * 4 + 3 * (size_t)M.nleaf * 4, &d_m[which[t]].rest, 4,
+                          hipMemcpyDeviceToHost, st));
   }
   HIP_OK(hipStreamSynchronize(st));
   for (size_t t = 0; t < which.size(); ++t) {
@@ -1108,7 +1110,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     m.grp.assign(qi + M.nleaf + 1, qi + M.nleaf + 1 + 3 * (size_t)M.nleaf);
     m.stream = (uint32_t)((depth << 20) + which[t]);
     std::vector<double> d(q, q + M.K), g2(q + M.K, q + 2 * (size_t)M.K), mu(q + 2 * (size_t)M.K, q + 3 * (size_t)M.K);
-    m.r = hss_rank_estimate(d.data(), g2.data(), mu.data(), M.K, m.bounds, o, false);
+    m.r = qi[M.nleaf + 1 + 3 * (size_t)M.nleaf];  // k_leaf_bounds: eq. (bounds) over the moved boundaries
     if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
     if (o.rank_mode == ADC_RANK_MLP && !mlp_collecting(c))
       m.r = mlp_rank(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, o, m.r);
@@ -1174,6 +1176,21 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
       rep->max_rank = std::max(rep->max_rank, m.max_rank);
       rep->samples = std::max(rep->samples, m.s);
       if (m.pass) rep->check_err_max = std::max(rep->check_err_max, m.err);
+      if (m.pass && m.sat) {
+        rep->hss_saturated++;
+        rep->hss_sat_nodes += m.sat;
+      }
+      if (m.pass && m.nodes.size() > 1) {
+        // the least traffic of Algorithm 3 for the update product: X read
+        // by the upsweep and the leaf step and Y written (24 P K bytes),
+        // the leaves' G and F blocks written and read (16 P K rbar / mbar)
+        double rsum = 0.0;
+        for (size_t i = 1; i < m.nodes.size(); ++i) rsum += 0.5 * (m.nodes[i].kr + m.nodes[i].kc);
+        const double rbar = rsum / (double)(m.nodes.size() - 1);
+        const double mbar = (double)M.K / (double)(1 << m.L);
+        const double PK = (double)M.n * (double)M.K;
+        rep->phase_bytes[8] += 24.0 * PK + 16.0 * PK * rbar / mbar;
+      }
     }
     if (m.pass && mlp_collecting(c)) {
       std::vector<int> lo, hi, kr, kc;
@@ -1245,7 +1262,7 @@ extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const
   HIP_OK(hipMemcpyAsync(hg.data(), gam, K * 8, hipMemcpyDeviceToHost, st));
   HIP_OK(hipMemcpyAsync(hm.data(), mu, K * 8, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  m.r = hss_rank_estimate(hd.data(), hg.data(), hm.data(), (int)K, m.bounds, o);
+  ADC_TRY(device_rank_estimate(c, d, gam, mu, (int)K, m.bounds, o, &m.r));
   if (omega) m.r = std::max(0, s - o.oversample);
   else if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
   m.stream = 0;
@@ -1302,6 +1319,27 @@ extern "C" adc_status adc_hss_build(adc_ctx c, int64_t K, const double* d, const
   h->dense_fallback = !mm.pass;
   h->bounds = mm.bounds;
   *out = h;
+  return ADC_OK;
+}
+
+extern "C" adc_status adc_rank_estimate(adc_ctx c, int64_t K, const double* d, const double* gam,
+                                        const double* mu, const adc_opts* opts_in, int32_t* r, int32_t* bounds,
+                                        int32_t bounds_cap, int32_t* nbounds) {
+  if (!c || K < 2 || K > (1 << 24) || !d || !gam || !mu || !r || !bounds) return ADC_ERR_ARG;
+  adc_opts o;
+  if (opts_in) o = *opts_in;
+  else adc_opts_default(&o);
+  ADC_TRY(validate_opts_ext(o));
+  const int L = std::max(1, ceil_log2_ratio((int)K, o.hss_leaf));
+  const int nbd = (1 << L) + 1;
+  if (nbounds) *nbounds = nbd;
+  if (bounds_cap < nbd) return ADC_ERR_ARG;
+  DeviceGuard gd(c->device);
+  std::vector<int> b = balanced_bounds((int)K, L);
+  int rr = 0;
+  ADC_TRY(device_rank_estimate(c, d, gam, mu, (int)K, b, o, &rr));
+  std::copy(b.begin(), b.end(), bounds);
+  *r = rr;
   return ADC_OK;
 }
 

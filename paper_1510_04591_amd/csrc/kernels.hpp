@@ -30,7 +30,7 @@ struct MergeDev {
   // bottom only)
   int32_t* lbounds;
   int32_t nleaf;
-  int32_t pad_;
+  int32_t rest;    // rank estimate of eq. (bounds) over the moved boundaries (k_leaf_bounds)
 };
 
 // Output block of one leaf: z points at its (first row, first column) corner.
@@ -128,8 +128,8 @@ __global__ void k_vnorm(const MergeDev* __restrict__ merges, const RootBlock* __
 __global__ void k_final_order(const MergeDev* __restrict__ merges, LevelBufs B,
                               const RootBlock* __restrict__ blocks);
 
-__global__ void k_leaf_bounds(const MergeDev* __restrict__ merges, const int32_t* __restrict__ which, LevelBufs B,
-                              double thresh, int shift_max);
+__global__ void k_leaf_bounds(MergeDev* __restrict__ merges, const int32_t* __restrict__ which, LevelBufs B,
+                              double thresh, int shift_max, double rank_eps, int r_cap);
 __global__ void k_leaf_group(const MergeDev* __restrict__ merges, const int2* __restrict__ jobs, LevelBufs B);
 
 __global__ void k_zero_unsupported(const MergeDev* __restrict__ merges, int g, LevelBufs B);

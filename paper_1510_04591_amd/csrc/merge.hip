@@ -1,5 +1,6 @@
-// Merge-step kernels around the secular solve (Algorithm 1, "form M = D +
-// b_k u u^T", deflation, and the assembly of the merged eigenpairs).
+// Merge-step kernels around the secular solve (Algorithm 1: the rank-one
+// problem of the two children's spectra, deflation, and the assembly of the
+// merged eigenpairs).
 //
 // k_merge_sort   the stable merge of the two sorted child spectra, one thread
 //                per element (binary search in the other child), with the
@@ -495,18 +496,22 @@ __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merg
 }
 
 // ---------------------------------------------------------------------------
-// HSS merges: the leaf boundaries of the rank estimate (Section 4.1).  From
+// HSS merges: the leaf boundaries and the rank estimate (Section 4.1).  From
 // the balanced boundaries, every interior boundary b whose segments are
-// closer than `thresh`, dist(b) = min(|lam_b - d_{b-1}|, |d_b - lam_{b-1}|)
-// by eq. (d-lambda), moves by up to shift_max indices to the largest
+// closer than `thresh` moves by up to shift_max indices to the largest
 // distance, boundaries taken in order (a window starts after the previous,
-// already moved, boundary).  One workgroup per merge; thread 0 walks the
-// boundaries.
-__global__ void __launch_bounds__(64) k_leaf_bounds(const MergeDev* __restrict__ merges,
+// already moved, boundary).  The distance of the segments split before b is
+// min(|lam_b - d_{b-1}|, |d_b - lam_{b-1}|) by eq. (d-lambda); with
+// interlacing roots it is mu_{b-1}, the first term never being smaller.
+// Then every boundary gives the bound of eq. (bounds) with
+// R = (lam_{K-1} - d_0) / dist and the merge's estimate is the largest,
+// capped at r_cap (also for a zero distance).  One 64-lane workgroup per
+// merge: lane 0 moves the boundaries, the lanes share the bounds.
+__global__ void __launch_bounds__(64) k_leaf_bounds(MergeDev* __restrict__ merges,
                                                     const int32_t* __restrict__ which, LevelBufs B,
-                                                    double thresh, int shift_max) {
-  if (threadIdx.x != 0) return;
-  const MergeDev& M = merges[which[blockIdx.x]];
+                                                    double thresh, int shift_max, double rank_eps, int r_cap) {
+  __shared__ int rmax;
+  MergeDev& M = merges[which[blockIdx.x]];
   const int64_t s0 = M.s0;
   const int K = M.K;
   const double* d = B.dS + s0;
@@ -517,22 +522,38 @@ __global__ void __launch_bounds__(64) k_leaf_bounds(const MergeDev* __restrict__
     const double x = (b < K) ? (d[b] - d[b - 1]) + gam[b] : INFINITY;
     return fmin(fabs(x), fabs(mu[b - 1]));
   };
-  for (int t = 1; t < M.nleaf; ++t) {
-    const int b = bd[t];
-    double best_d = dist(b);
-    if (!(best_d < thresh)) continue;
-    int best = b;
-    const int lo = max(bd[t - 1] + 1, b - shift_max);
-    const int hi = min(bd[t + 1] - 1, b + shift_max);
-    for (int bb = lo; bb <= hi; ++bb) {
-      const double dd = dist(bb);
-      if (dd > best_d) {
-        best = bb;
-        best_d = dd;
+  if (threadIdx.x == 0) {
+    rmax = 0;
+    for (int t = 1; t < M.nleaf; ++t) {
+      const int b = bd[t];
+      double best_d = dist(b);
+      if (!(best_d < thresh)) continue;
+      int best = b;
+      const int lo = max(bd[t - 1] + 1, b - shift_max);
+      const int hi = min(bd[t + 1] - 1, b + shift_max);
+      for (int bb = lo; bb <= hi; ++bb) {
+        const double dd = dist(bb);
+        if (dd > best_d) {
+          best = bb;
+          best_d = dd;
+        }
       }
+      bd[t] = best;
     }
-    bd[t] = best;
   }
+  __syncthreads();
+  const double span = (d[K - 1] + gam[K - 1]) - d[0];
+  int r = 0;
+  for (int t = 1 + (int)threadIdx.x; t < M.nleaf; t += 64) {
+    const double ds = dist(bd[t]);
+    const double R = (ds > 0.0) ? span / ds : INFINITY;
+    int rb = r_cap;
+    if (isfinite(R)) rb = min(r_cap, (int)ceil(log(16.0 / rank_eps) * log(8.0 * fmax(R, 1.0)) / (M_PI * M_PI)));
+    r = max(r, rb);
+  }
+  atomicMax(&rmax, r);
+  __syncthreads();
+  if (threadIdx.x == 0) M.rest = min(rmax, r_cap);
 }
 
 // HSS merges: inside every leaf of the HSS tree (survivors in pole order)

@@ -185,3 +185,32 @@ def test_stedc_dense_fallback_after_failed_check(ctx, case):
     with pytest.raises(adc.AdcError) as ei:
         adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), strict=1, **kw)
     assert ei.value.status == adc.ADC_ERR_ACCURACY
+
+
+def test_saturation_guard_forces_retry(ctx):
+    """Four samples and no oversampling saturate the interpolative
+    decompositions (node ranks equal to s with more candidates than s).  With
+    a check tolerance so loose that every probe error passes, the merges are
+    accepted and reported as saturated; with sat_guard a saturated merge
+    fails its check like a large probe error and is rebuilt with doubled
+    samples, so no accepted merge saturates and the result is exact."""
+    print("saturation guard", flush=True)
+    N = 8192
+    a, b = workloads.toeplitz(N)
+    kw = dict(hss_leaf=128, hss_min_k=1024, hss_levels=-1, hss_min_flops=0, rank_mode=adc.ADC_RANK_FIXED,
+              fixed_rank=4, oversample=0, max_retries=6, check_tol=1.0)
+    _, _, rep = solve(ctx, a, b, **kw)
+    print(f"  unguarded: merges {rep['hss_merges']} saturated {rep['hss_saturated']} nodes {rep['hss_sat_nodes']}",
+          flush=True)
+    assert rep["hss_merges"] >= 3 and rep["retries"] == 0
+    assert rep["hss_saturated"] == rep["hss_merges"] and rep["hss_sat_nodes"] >= rep["hss_merges"]
+    w, Z, rep = solve(ctx, a, b, sat_guard=1, **kw)
+    print(f"  guarded: retries {rep['retries']} samples {rep['samples']} saturated {rep['hss_saturated']} "
+          f"fallbacks {rep['hss_fallbacks']}", flush=True)
+    assert rep["retries"] >= rep["hss_merges"] - rep["hss_fallbacks"]
+    assert rep["hss_saturated"] == 0
+    k = np.arange(1, N + 1)
+    exact = np.sort(2 + 2 * np.cos(k * np.pi / (N + 1)))
+    assert np.max(np.abs(w - exact)) <= 1e-13 * 4
+    assert odc.residual(a, b, w, Z) <= 1e-13
+    assert odc.orthogonality(Z) <= 1e-12

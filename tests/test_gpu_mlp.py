@@ -193,3 +193,49 @@ def test_gain_over_the_bound(ctx):
                   f"retries {rep['retries']} hss merges {rep['hss_merges']}", flush=True)
         assert res[adc.ADC_RANK_MLP]["samples"] <= res[adc.ADC_RANK_BOUND]["samples"]
     assert tot[adc.ADC_RANK_MLP] < tot[adc.ADC_RANK_BOUND]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "geometric", "clusters"])
+def test_mlp_full_size_prescribed_spectra(ctx, kind):
+    """The predictor at full size (N = 32768, HSS at every merge with K >=
+    2048): eigenvalues against the prescribed spectrum, residual and
+    orthogonality on the device, no dense fallback."""
+    trained_model(ctx)
+    N = 32768
+    print(f"mlp full size {kind}", flush=True)
+    a, b = workloads.prescribed_tridiagonal(kind, N)
+    lam, _ = workloads.spectrum(kind, N)
+    w, Z, rep = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), dc_leaf=32, hss_leaf=128, hss_min_k=2048,
+                                     hss_levels=-1, hss_min_flops=0, rank_mode=adc.ADC_RANK_MLP)
+    torch.cuda.synchronize()
+    tn = odc.tnorm1(a, b)
+    err = np.max(np.abs(w.cpu().numpy() - np.sort(lam))) / tn
+    res, orth = full_checks(a, b, w, Z)
+    print(f"  hss merges {rep['hss_merges']} samples {rep['samples']} max rank {rep['max_rank']} "
+          f"retries {rep['retries']} saturated {rep['hss_saturated']} eig err {err:.1e} resid {res:.2e} "
+          f"orth {orth:.2e}", flush=True)
+    assert rep["hss_merges"] >= 7 and rep["hss_fallbacks"] == 0
+    assert err <= 1e-13
+    assert res <= 1e-13 and orth <= 1e-12
+    del Z
+    torch.cuda.empty_cache()
+
+
+def full_checks(a, b, w, Z, cb=4096):
+    """||T Z - Z diag(w)||_F / (N ||T||_1) and ||Z^T Z - I||_max on the
+    device, in column blocks."""
+    N = a.shape[0]
+    ad, bd = cuda(a), cuda(b)
+    res2, orth = 0.0, 0.0
+    for c0 in range(0, N, cb):
+        Zc = Z[:, c0:c0 + cb]
+        TZ = ad[:, None] * Zc
+        TZ[:-1] += bd[:, None] * Zc[1:]
+        TZ[1:] += bd[:, None] * Zc[:-1]
+        R = TZ - Zc * w[None, c0:c0 + cb]
+        res2 += float(torch.sum(R * R))
+        G = Z.t() @ Zc
+        G[c0:c0 + cb].diagonal().sub_(1.0)
+        orth = max(orth, float(torch.max(torch.abs(G))))
+        del TZ, R, G
+    return float(np.sqrt(res2)) / (N * odc.tnorm1(a, b)), orth
