@@ -7,11 +7,19 @@ levels here; HSS leaf 128, p = 16, adaptive oversampling), compared
 with the plain dense FP64 MFMA update on the same GPU.
 
 A step is one complete eigendecomposition (all eigenvalues and eigenvectors)
-through adc_stedc with the inputs resident in HBM.  The JSON line reports
-the HSS-ADC seconds per step as `value`, the dense-DC time beside it, the
-roofline of the dominant kernel (HIP-event durations recorded by the library
-on its stream inside the timed steps) and the CPU oracle timed on a bounded
-sample.
+through adc_stedc with the inputs resident in HBM.  Each step is bracketed by
+device synchronisation and timed on the host clock; after each step (outside
+the timed spans) its result is validated: eigenvalues against the closed
+form, the residual on the device and, for the first step, the orthogonality;
+every later step must reproduce the first step's eigenvectors bit for bit,
+or it is validated in full as well.  The JSON line reports the HSS-ADC
+seconds per step as `value`, the dense-DC time beside it (warmed up like the
+headline), the roofline of the dominant kernel (HIP-event durations recorded
+by the library on its stream inside the timed steps), Algorithm 3 against its
+least-traffic model, the other configurations (random N = 8192, the headline
+with HSS at exactly the top three levels, the learned rank predictor on a
+prescribed spectrum, the 256-matrix batch) and the CPU oracle timed on a
+bounded sample, with the GPU time at the same size.
 """
 import argparse
 import json
@@ -48,6 +56,7 @@ TRAFFIC_DENSE = {
 }
 
 
+HEADLINE = dict(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=2.5e10, oversample=16)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 METRIC = "N=32768 tridiag eig wall time: HSS-ADC vs dense DC, 1 GPU, resid≤1e-13"
@@ -59,7 +68,11 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=32768)
-    p.add_argument("--dense-steps", type=int, default=1)
+    p.add_argument("--hss-leaf", type=int, default=128, help="HSS leaf size of the headline options")
+    p.add_argument("--dense-steps", type=int, default=3)
+    p.add_argument("--dense-warmup", type=int, default=1)
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the other configurations (random 8192, top three levels, predictor)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-validate", action="store_true")
     p.add_argument("--mode", choices=["both", "hss", "dense"], default="both")
@@ -99,13 +112,31 @@ def validate(torch, a, b, w, Z, exact):
     return dict(resid=float(np.sqrt(res2)) / (N * tn), orth=orth, eig_err_rel=werr)
 
 
-def cpu_baseline():
-    """The oracle (plain fp64 numpy DC) on a bounded sample: the dense DC of
-    the same Toeplitz family at N = 4096, scaled to N = 32768 by the cube of
-    the size ratio (the dense update's O(N^3) term dominates)."""
+def host_info():
+    """Host cores visible to this process and the CPU model name."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return nproc, model
+
+
+def cpu_baseline(n=5120):
+    """The oracle (plain fp64 numpy DC) timed on a bounded sample: the full
+    dense DC of the same Toeplitz family at order n on the host cores.  The
+    value in the metric's unit is that measurement times (32768/n)^3 (the
+    dense update's O(N^3) term dominates), an estimate; the measured seconds
+    and the sample are reported beside it."""
     from oracle import dc as odc
     from paper_1510_04591_amd import workloads
-    n = 4096
     a, b = workloads.toeplitz(n)
     t = time.perf_counter()
     odc.stedc(a, b, leaf=32)
@@ -116,9 +147,12 @@ def cpu_baseline():
         threads = max((x.get("num_threads", 1) for x in threadpool_info()), default=1)
     except Exception:
         threads = os.cpu_count()
+    nproc, model = host_info()
     scale = (32768 / n) ** 3
     return {"value": dt * scale, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle dense DC of Toeplitz N={n} took {dt:.2f} s; x{scale:.0f} (N^3) to N=32768"}
+            "sample": f"oracle dense DC of Toeplitz N={n}, measured {dt:.2f} s on the host; value = that x{scale:.0f} "
+                      f"(N^3) to N=32768, an estimate",
+            "measured_s": dt, "measured_n": n, "nproc": nproc, "cpu_model": model}
 
 
 def run_batched(torch, adc, ctx, steps, warmup, sequential=True):
@@ -200,67 +234,25 @@ def run_c5(torch, adc, ctx, steps):
     seed 2, four matrices of the 256-matrix batch) with HSS forced on every
     merge, train the MLP on the GPU, then solve N = 32768 matrices with
     prescribed spectra (uniform, geometric, clusters; not seen in training)
-    with the sample count from eq. (bounds) and from the MLP."""
+    with the sample count from eq. (bounds) and from the MLP, the latter also
+    with the rank-saturation guard."""
     from paper_1510_04591_amd import workloads
-    Xs, ys = [], []
-    train = [workloads.toeplitz(4096), workloads.toeplitz(32768), workloads.random_uniform(8192, 2)]
-    train += [workloads.batched(8, 4)[i] for i in (0, 1, 5, 6)]
-    for a, b in train:
-        n = len(a)
-        w = torch.empty(n, dtype=torch.float64, device="cuda")
-        Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
-        for leaf in ((32, 64, 128) if n <= 8192 else (128,)):
-            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=max(2 * leaf, 256 if n > 8192 else 0), hss_levels=-1, hss_min_flops=0)
-            cap = 1 << 17
-            X = torch.empty((cap, 16), dtype=torch.float32, device="cuda")
-            y = torch.empty(cap, dtype=torch.float32, device="cuda")
-            st, rows = adc.adc_mlp_collect(ctx.h, n, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), w, Z, n,
-                                           o, cap, X, y)
-            if st != adc.ADC_OK:
-                raise adc.AdcError(st, "adc_mlp_collect")
-            Xs.append(X[:rows].clone())
-            ys.append(y[:rows].clone())
-        del Z
-    X = torch.cat(Xs)
-    y = torch.cat(ys)
-    perm = torch.from_numpy(np.random.default_rng(0).permutation(X.shape[0])).cuda()
-    X, y = X[perm].contiguous(), y[perm].contiguous()
-    if adc.adc_mlp_init(ctx.h, 7) != adc.ADC_OK:
-        raise RuntimeError("adc_mlp_init")
-    t0 = time.perf_counter()
-    st, loss = adc.adc_mlp_train(ctx.h, X.shape[0], X, y, 150, 64, 1e-3)
-    t_train = time.perf_counter() - t0
-    out = {"training_rows": int(X.shape[0]), "train_loss": loss, "target_var": float(torch.var(y)),
-           "train_s": t_train, "spectra": {}}
+    out = train_predictor(torch, adc, ctx, full=True)
+    out["spectra"] = {}
     N = 32768
-    w = torch.empty(N, dtype=torch.float64, device="cuda")
-    Zt = torch.empty((N, N), dtype=torch.float64, device="cuda")
     for kind in ("uniform", "geometric", "clusters"):
         a, b = workloads.prescribed_tridiagonal(kind, N)
         lam, _ = workloads.spectrum(kind, N)
-        ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
         res = {}
-        for name, mode in (("bound", adc.ADC_RANK_BOUND), ("mlp", adc.ADC_RANK_MLP)):
-            o = adc.opts(dc_leaf=32, hss_leaf=128, hss_min_k=2048, hss_levels=-1, hss_min_flops=0, rank_mode=mode)
-            times = []
-            for it in range(steps + 1):
-                rep = adc.adc_report()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st = adc.adc_stedc(ctx.h, N, ad, bd, w, Zt, N, None, 0, o, rep)
-                torch.cuda.synchronize()
-                if st != adc.ADC_OK:
-                    raise adc.AdcError(st, "adc_stedc", rep.as_dict())
-                if it > 0:
-                    times.append(time.perf_counter() - t0)
-            r = rep.as_dict()
-            v = validate(torch, a, b, w, Zt.t(), np.sort(lam))
-            res[name] = {"s": float(np.median(times)), "samples": r["samples"], "max_rank": r["max_rank"],
-                         "retries": r["retries"], "hss_merges": r["hss_merges"], "fallbacks": r["hss_fallbacks"],
-                         "hss_sampling_s": r["t_phase"][5] / 1.0, "validation": v}
+        for name, mode, sg in (("bound", adc.ADC_RANK_BOUND, 0), ("mlp", adc.ADC_RANK_MLP, 0),
+                               ("mlp_sat_guard", adc.ADC_RANK_MLP, 1)):
+            o = adc.opts(dc_leaf=32, hss_leaf=128, hss_min_k=2048, hss_levels=-1, hss_min_flops=0, rank_mode=mode,
+                         sat_guard=sg)
+            res[name] = timed_config(torch, adc, ctx, a, b, o, steps=max(steps, 1), exact=np.sort(lam))
         out["spectra"][kind] = res
-        print(f"# C5 {kind}: bound {res['bound']['s']:.4f} s (s={res['bound']['samples']}), "
-              f"mlp {res['mlp']['s']:.4f} s (s={res['mlp']['samples']})", flush=True)
+        print(f"# C5 {kind}: " + ", ".join(f"{k} {v['median_s']:.4f} s (s={v['samples']}, retries {v['retries']}, "
+                                           f"saturated {v['saturated_merges']}, orth {v['validation']['orth']:.1e})"
+                                           for k, v in res.items()), flush=True)
     return out
 
 
@@ -286,7 +278,7 @@ def run_families(torch, adc, ctx, sizes, steps):
     headline HSS options and with the dense update; median seconds of
     `steps` timed solves after one untimed one, residual and orthogonality of
     the HSS result, eigenvalue error where the spectrum has a closed form."""
-    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=2.5e10, oversample=16)
+    hss_opts = adc.opts(**HEADLINE)
     dense_opts = adc.opts(dc_leaf=32, force_dense=1)
     out = {}
     for kind in FAMILIES:
@@ -322,6 +314,141 @@ def run_families(torch, adc, ctx, sizes, steps):
                   f"x{row['speedup']:.2f}, K top {row['K_top']}, rank {row['max_rank']}, "
                   f"resid {v['resid']:.1e} orth {v['orth']:.1e}", flush=True)
             del Zt
+    return out
+
+
+def timed_config(torch, adc, ctx, a, b, o, steps=3, warm=1, exact=None):
+    """Median seconds of `steps` synchronised solves after `warm` untimed ones,
+    the last report, and the validation of every timed result (residual,
+    orthogonality, and eigenvalues against `exact`, or else against Sturm
+    counts at sampled indices)."""
+    from oracle import sturm
+    n = len(a)
+    ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    Zt = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    tn = float(np.max(np.abs(a) + np.concatenate([[0], np.abs(b)]) + np.concatenate([np.abs(b), [0]])))
+    if exact is None:
+        ks = np.unique(np.array([0, 1, n // 7, n // 3, n // 2, 2 * n // 3, n - 2, n - 1]))
+        ref_ks = sturm.eigenvalues_by_index(a, b, ks)
+    times, vals, r = [], [], None
+    for it in range(warm + steps):
+        rep = adc.adc_report()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = adc.adc_stedc(ctx.h, n, ad, bd, w, Zt, n, None, 0, o, rep)
+        torch.cuda.synchronize()
+        if st != adc.ADC_OK:
+            raise adc.AdcError(st, "adc_stedc", rep.as_dict())
+        if it < warm:
+            continue
+        times.append(time.perf_counter() - t0)
+        r = rep.as_dict()
+        if exact is not None:
+            v = validate(torch, a, b, w, Zt.t(), exact)
+        else:
+            v = validate(torch, a, b, w, Zt.t(), w.cpu().numpy())
+            v["eig_err_rel"] = float(np.max(np.abs(w.cpu().numpy()[ks] - ref_ks))) / tn
+        vals.append(v)
+    del Zt
+    torch.cuda.empty_cache()
+    v = {key: max(x[key] for x in vals) for key in vals[0]}
+    v["steps_validated"] = len(vals)
+    return {"median_s": float(np.median(times)), "steps": steps, "warmup": warm, "hss_merges": r["hss_merges"],
+            "hss_per_level": r["hss_per_level"], "K_top": r["K_per_level"][0], "samples": r["samples"],
+            "max_rank": r["max_rank"], "retries": r["retries"], "fallbacks": r["hss_fallbacks"],
+            "saturated_merges": r["hss_saturated"],
+            "hss_compress_s": r["t_phase"][6], "hss_multiply_s": r["t_phase"][8], "validation": v}
+
+
+def gpu_time_at(torch, adc, ctx, n):
+    """HSS-ADC (headline options) and dense DC at order n: the GPU beside the
+    CPU sample of the same size."""
+    from paper_1510_04591_amd import workloads
+    a, b = workloads.toeplitz(n)
+    exact = np.sort(2 + 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    h = timed_config(torch, adc, ctx, a, b, adc.opts(**HEADLINE), exact=exact)
+    d = timed_config(torch, adc, ctx, a, b, adc.opts(dc_leaf=32, force_dense=1), exact=exact)
+    return {"hss_adc_s": h["median_s"], "dense_dc_s": d["median_s"], "n": n}
+
+
+def train_predictor(torch, adc, ctx, full=False):
+    """Collect boundary ranks from the training families with HSS forced on
+    every merge (Toeplitz N = 4096, random uniform N = 4096 seed 2, four
+    matrices of the batch; with `full` also Toeplitz 32768 and random 8192)
+    and train the MLP on the GPU."""
+    from paper_1510_04591_amd import workloads
+    Xs, ys = [], []
+    if full:
+        train = [workloads.toeplitz(4096), workloads.toeplitz(32768), workloads.random_uniform(8192, 2)]
+    else:
+        train = [workloads.toeplitz(4096), workloads.random_uniform(4096, 2)]
+    train += [workloads.batched(8, 4)[i] for i in (0, 1, 5, 6)]
+    for a, b in train:
+        n = len(a)
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        for leaf in ((32, 64, 128) if n <= 8192 else (128,)):
+            o = adc.opts(dc_leaf=32, hss_leaf=leaf, hss_min_k=max(2 * leaf, 256 if n > 8192 else 0), hss_levels=-1,
+                         hss_min_flops=0)
+            cap = 1 << 17
+            X = torch.empty((cap, 16), dtype=torch.float32, device="cuda")
+            y = torch.empty(cap, dtype=torch.float32, device="cuda")
+            st, rows = adc.adc_mlp_collect(ctx.h, n, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), w, Z, n,
+                                           o, cap, X, y)
+            if st != adc.ADC_OK:
+                raise adc.AdcError(st, "adc_mlp_collect")
+            Xs.append(X[:rows].clone())
+            ys.append(y[:rows].clone())
+        del Z
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    perm = torch.from_numpy(np.random.default_rng(0).permutation(X.shape[0])).cuda()
+    X, y = X[perm].contiguous(), y[perm].contiguous()
+    if adc.adc_mlp_init(ctx.h, 7) != adc.ADC_OK:
+        raise RuntimeError("adc_mlp_init")
+    t0 = time.perf_counter()
+    st, loss = adc.adc_mlp_train(ctx.h, X.shape[0], X, y, 150, 64, 1e-3)
+    if st != adc.ADC_OK:
+        raise adc.AdcError(st, "adc_mlp_train")
+    torch.cuda.empty_cache()
+    return {"training_rows": int(X.shape[0]), "train_loss": loss, "target_var": float(torch.var(y)),
+            "train_s": time.perf_counter() - t0}
+
+
+def run_extra(torch, adc, ctx, args):
+    """The other configurations, each timed (median of 3 after one untimed
+    solve) and every timed result validated."""
+    from paper_1510_04591_amd import workloads
+    out = {}
+    N = 32768
+    # random N = 8192, HSS leaf 64, ID tolerance 1e-14, HSS at K >= 2048
+    a, b = workloads.random_uniform(8192, 2)
+    out["random_8192_leaf64"] = timed_config(
+        torch, adc, ctx, a, b, adc.opts(dc_leaf=32, hss_leaf=64, id_tol=1e-14, hss_min_k=2048, hss_levels=-1,
+                                        hss_min_flops=0))
+    print(f"# random 8192: {out['random_8192_leaf64']['median_s']:.4f} s", flush=True)
+    # the headline matrix with HSS at exactly the top three merge levels
+    a, b = workloads.toeplitz(N)
+    exact = np.sort(2 + 2 * np.cos(np.arange(1, N + 1) * np.pi / (N + 1)))
+    out["toeplitz_32768_top3"] = timed_config(
+        torch, adc, ctx, a, b, adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=3, hss_min_k=2048, hss_min_flops=0,
+                                        oversample=16), exact=exact)
+    print(f"# toeplitz 32768, HSS at the top three levels: {out['toeplitz_32768_top3']['median_s']:.4f} s",
+          flush=True)
+    # the learned rank predictor on the prescribed uniform spectrum
+    tr = train_predictor(torch, adc, ctx)
+    a, b = workloads.prescribed_tridiagonal("uniform", N)
+    lam, _ = workloads.spectrum("uniform", N)
+    c5 = {"training": tr}
+    for name, kw in (("bound", dict(rank_mode=adc.ADC_RANK_BOUND)), ("mlp", dict(rank_mode=adc.ADC_RANK_MLP)),
+                     ("mlp_sat_guard", dict(rank_mode=adc.ADC_RANK_MLP, sat_guard=1))):
+        o = adc.opts(dc_leaf=32, hss_leaf=128, hss_min_k=2048, hss_levels=-1, hss_min_flops=0, **kw)
+        c5[name] = timed_config(torch, adc, ctx, a, b, o, exact=np.sort(lam))
+        print(f"# prescribed uniform 32768, {name}: {c5[name]['median_s']:.4f} s, s={c5[name]['samples']}, "
+              f"retries {c5[name]['retries']}, saturated {c5[name]['saturated_merges']}, "
+              f"orth {c5[name]['validation']['orth']:.1e}", flush=True)
+    out["prescribed_uniform_32768"] = c5
     return out
 
 
@@ -369,47 +496,72 @@ def main():
     ctx = adc.Context(0)
     w = torch.empty(N, dtype=torch.float64, device="cuda")
     Zt = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    hss_opts = adc.opts(dc_leaf=32, hss_leaf=128, hss_levels=-1, hss_min_k=2048, hss_min_flops=2.5e10, oversample=16)
+    hss_opts = adc.opts(**dict(HEADLINE, hss_leaf=args.hss_leaf))
     dense_opts = adc.opts(dc_leaf=32, force_dense=1)
 
+    def solve(o):
+        rep = adc.adc_report()
+        st = adc.adc_stedc(ctx.h, N, ad, bd, w, Zt, N, None, 0, o, rep)
+        if st != adc.ADC_OK:
+            raise adc.AdcError(st, "adc_stedc", rep.as_dict())
+        return rep.as_dict()
+
     def run(o, steps, warm):
+        """warm untimed solves, then `steps` solves each bracketed by device
+        synchronisation; every step's result validated outside its span."""
         for _ in range(warm):
-            rep = adc.adc_report()
-            st = adc.adc_stedc(ctx.h, N, ad, bd, w, Zt, N, None, 0, o, rep)
-            if st != adc.ADC_OK:
-                raise adc.AdcError(st, "adc_stedc", rep.as_dict())
+            solve(o)
         torch.cuda.synchronize()
-        reps = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            rep = adc.adc_report()
-            st = adc.adc_stedc(ctx.h, N, ad, bd, w, Zt, N, None, 0, o, rep)
-            if st != adc.ADC_OK:
-                raise adc.AdcError(st, "adc_stedc", rep.as_dict())
-            reps.append(rep.as_dict())
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, reps
+        times, reps, vals = [], [], []
+        ref = None
+        identical = 0
+        for i in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = solve(o)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            reps.append(r)
+            if args.no_validate:
+                continue
+            if i == 0:
+                vals.append(validate(torch, a, b, w, Zt.t(), exact))
+                ref = (w.clone(), Zt.clone())
+            elif torch.equal(w, ref[0]) and torch.equal(Zt, ref[1]):
+                identical += 1
+            else:
+                vals.append(validate(torch, a, b, w, Zt.t(), exact))
+        v = None
+        if vals:
+            v = {key: max(x[key] for x in vals) for key in vals[0]}
+            v["steps_validated"] = steps
+            v["steps_bit_identical_to_first"] = identical
+            v["steps_validated_in_full"] = len(vals)
+        del ref
+        torch.cuda.empty_cache()
+        return float(np.sum(times)) / steps, times, reps, v
 
     out = {}
     val = {}
     if args.mode in ("both", "dense"):
-        t_dense, reps_d = run(dense_opts, args.dense_steps, 0 if args.mode == "both" else args.warmup)
-        out["dense"] = (t_dense, reps_d)
-        if not args.no_validate:
-            val["dense"] = validate(torch, a, b, w, Zt.t(), exact)
-        print(f"# dense DC: {t_dense:.4f} s/step {val.get('dense', '')}", flush=True)
+        t_dense, times_d, reps_d, v = run(dense_opts, args.dense_steps, args.dense_warmup)
+        out["dense"] = (t_dense, reps_d, times_d)
+        if v:
+            val["dense"] = v
+        print(f"# dense DC: {t_dense:.4f} s/step (median {np.median(times_d):.4f}) {val.get('dense', '')}", flush=True)
     if args.mode in ("both", "hss"):
-        t_hss, reps_h = run(hss_opts, args.steps, args.warmup)
-        out["hss"] = (t_hss, reps_h)
-        if not args.no_validate:
-            val["hss"] = validate(torch, a, b, w, Zt.t(), exact)
-        print(f"# HSS-ADC: {t_hss:.4f} s/step {val.get('hss', '')}", flush=True)
+        t_hss, times_h, reps_h, v = run(hss_opts, args.steps, args.warmup)
+        out["hss"] = (t_hss, reps_h, times_h)
+        if v:
+            val["hss"] = v
+        print(f"# HSS-ADC: {t_hss:.4f} s/step (median {np.median(times_h):.4f}) {val.get('hss', '')}", flush=True)
 
     head = "hss" if "hss" in out else "dense"
-    t_head, reps = out[head]
+    t_head, reps, times_head = out[head]
     names = ["leaves", "deflation", "secular", "loewner_v", "dense_gemm", "hss_sampling", "hss_compress",
              "hss_check", "hss_multiply", "order_pack"]
     ph = np.sum([r["t_phase"] for r in reps], axis=0)
+    pb = np.sum([r["phase_bytes"] for r in reps], axis=0)
     # dominant kernel: the largest total time among the kernels whose
     # algorithmic flops or bytes the library counts; each launch is
     # bracketed by HIP events on the library's stream
@@ -434,6 +586,14 @@ def main():
     roof["kernel"] = kn[dom]
     roof["launches_per_step"] = launches / len(reps)
     roof["avg_launch_ms"] = 1e3 * avg_dur
+    if head == "hss" and ph[8] > 0 and pb[8] > 0:
+        # the whole HSS multiply phase (Algorithm 3 with the check's probe
+        # products) against the least traffic of the update products
+        roof["alg3_phase"] = {"model_bytes_per_step": float(pb[8] / len(reps)),
+                              "ms_per_step": float(1e3 * ph[8] / len(reps)),
+                              "achieved_gbs": float(pb[8] / ph[8] / 1e9),
+                              "frac": float(pb[8] / ph[8] / 1e9 / PEAK_HBM_GBS),
+                              "kernel_bytes_per_step": float(sum(kb[i] for i in (0, 1, 7)) / len(reps))}
     kernels = {kn[i]: {"ms_per_step": 1e3 * kt[i] / len(reps), "launches_per_step": kl[i] / len(reps),
                        "avg_launch_us": 1e6 * kt[i] / max(kl[i], 1),
                        "tflops": (kf[i] / kt[i] / 1e12) if kf[i] > 0 else None,
@@ -447,29 +607,39 @@ def main():
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps if head == "hss" else args.dense_steps,
-        "warmup": args.warmup,
+        "warmup": args.warmup if head == "hss" else args.dense_warmup,
         "ms_per_step": 1e3 * t_head,
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=2.5e10 flops, HSS leaf 128, p=16",
+        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=2.5e10 flops, HSS leaf {args.hss_leaf}, p=16",
                    "update": head, "n": N, "K_per_level": r0["K_per_level"],
                    "hss_per_level": r0["hss_per_level"], "max_rank": r0["max_rank"],
-                   "samples": r0["samples"], "retries": r0["retries"], "fallbacks": r0["hss_fallbacks"]},
+                   "samples": r0["samples"], "retries": r0["retries"], "fallbacks": r0["hss_fallbacks"],
+                   "saturated_merges": r0["hss_saturated"]},
+        "median_step_s": float(np.median(times_head)),
         "dense_dc_s": out["dense"][0] if "dense" in out else None,
+        "dense_dc_median_s": float(np.median(out["dense"][2])) if "dense" in out else None,
+        "dense_dc_steps": args.dense_steps if "dense" in out else None,
         "speedup_vs_dense": (out["dense"][0] / out["hss"][0]) if ("dense" in out and "hss" in out) else None,
         "phases_s": {n_: float(ph[i] / len(reps)) for i, n_ in enumerate(names)},
         "validation": val,
         "roofline": roof,
         "kernels": kernels,
     }
+    del Zt
+    torch.cuda.empty_cache()
+    if not args.no_extra and args.mode == "both":
+        res["configs"] = run_extra(torch, adc, ctx, args)
     if not args.no_batched:
         res["batched"] = run_batched(torch, adc, ctx, max(args.steps, 3), 1)
         print(f"# batched: {res['batched']['value']:.1f} matrices/s", flush=True)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline()
+        cb = cpu_baseline()
+        cb["gpu_s_same_size"] = gpu_time_at(torch, adc, ctx, cb["measured_n"])
+        res["cpu_baseline"] = cb
     ctx.close()
     print(json.dumps(res), flush=True)
 
