@@ -238,6 +238,22 @@ adc_status adc_cauchy_gemm(adc_ctx ctx, int64_t P, int64_t K, const double* d, c
                            const double* mu, const double* uh, const double* v,
                            const double* X, int64_t ldx, double* Y, int64_t ldy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as adc_cauchy_gemm, same kernels, with no allocation of any kind.
+ * The explicit Cauchy-like matrix and the launch descriptors live in one
+ * static device array of 32 MiB + 64 KiB per GPU, held while the library is
+ * loaded; hence K <= 2048 (larger K: ADC_ERR_UNSUPPORTED; nothing launched).
+ * Every call on a GPU shares that array: calls ordered on one stream are
+ * safe, calls that overlap on one GPU (other streams or contexts) race.
+ * ADC_ERR_HIP when the array's device address could not be taken at
+ * adc_create.  Asynchronous on the context stream (X, Y and the generators
+ * must stay valid until the stream reaches the call). */
+adc_status adc_cauchy_gemm_noalloc(adc_ctx ctx, int64_t P, int64_t K, const double* d,
+                                   const double* gam, const double* mu, const double* uh,
+                                   const double* v, const double* X, int64_t ldx, double* Y,
+                                   int64_t ldy);
+
 /* Rank estimate of Section 4.1 for one merge, the solver's own kernel: the
  * balanced leaf boundaries for opts->hss_leaf (L = ceil(log2(K / hss_leaf))
  * levels, at least one) are moved where two neighbouring segments are closer

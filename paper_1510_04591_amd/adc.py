@@ -96,6 +96,7 @@ _SIGS = {
     "adc_secular": (_P, _I64, _P, _P, _D, _P, _P, _P),
     "adc_lowner": (_P, _I64, _P, _P, _D, _P, _P, _P, _P),
     "adc_cauchy_gemm": (_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _I64),
+    "adc_cauchy_gemm_noalloc": (_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _I64),
     "adc_hss_build": (_P, _I64, _P, _P, _P, _P, _P, _P, _I32, C.POINTER(adc_opts), C.POINTER(_P)),
     "adc_hss_apply": (_P, _P, _I64, _P, _I64, _P, _I64),
     "adc_rank_estimate": (_P, _I64, _P, _P, _P, C.POINTER(adc_opts), C.POINTER(_I32), C.POINTER(_I32), _I32,
@@ -206,6 +207,11 @@ def adc_lowner(ctx, K, d, z, rho, gam, mu, uh, v):
 def adc_cauchy_gemm(ctx, P, K, d, gam, mu, uh, v, X, ldx, Y, ldy):
     return lib().adc_cauchy_gemm(ctx, int(P), int(K), _ptr(d), _ptr(gam), _ptr(mu), _ptr(uh), _ptr(v),
                                  _ptr(X), int(ldx), _ptr(Y), int(ldy))
+
+
+def adc_cauchy_gemm_noalloc(ctx, P, K, d, gam, mu, uh, v, X, ldx, Y, ldy):
+    return lib().adc_cauchy_gemm_noalloc(ctx, int(P), int(K), _ptr(d), _ptr(gam), _ptr(mu), _ptr(uh), _ptr(v),
+                                         _ptr(X), int(ldx), _ptr(Y), int(ldy))
 
 
 def adc_hss_build(ctx, K, d, gam, mu, uh, v, omega, s, o=None):

@@ -3,10 +3,43 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "adc_internal.hpp"
+
+// ---------------------------------------------------------------- static scratch
+// Scratch of adc_cauchy_gemm_noalloc: the explicit Cauchy-like matrix
+// (K x K, K <= NOALLOC_KMAX) followed by its launch descriptors.  One copy
+// per GPU, held while the library is loaded.  Host code never passes the
+// array's name to a kernel or a copy: it uses the device address taken once
+// per device by hipGetSymbolAddress (noalloc_scratch_init).
+namespace {
+constexpr int64_t NOALLOC_KMAX = 2048;
+constexpr size_t NOALLOC_QBYTES = (size_t)NOALLOC_KMAX * NOALLOC_KMAX * sizeof(double);
+constexpr size_t NOALLOC_DBYTES = 64 * 1024;
+constexpr size_t NOALLOC_BYTES = NOALLOC_QBYTES + NOALLOC_DBYTES;
+constexpr int NOALLOC_MAXDEV = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAXDEV] = {};
+bool g_noalloc_tried[NOALLOC_MAXDEV] = {};
+}  // namespace
+
+__device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+// Device address of `scratch` on the current device `device` (taken once).
+static void* noalloc_scratch_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAXDEV) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_tried[device]) {
+    g_noalloc_tried[device] = true;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_noalloc_ptr[device] = ptr;
+    else (void)hipGetLastError();
+  }
+  return g_noalloc_ptr[device];
+}
 
 // ---------------------------------------------------------------- status
 extern "C" const char* adc_status_string(adc_status s) {
@@ -76,6 +109,10 @@ extern "C" adc_status adc_create(adc_ctx* out, int device, void* stream) {
   if (!c) return ADC_ERR_NOMEM;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  {
+    DeviceGuard g(device);
+    c->noalloc_scratch = noalloc_scratch_init(device);  // null: the no-alloc entry reports ADC_ERR_HIP
+  }
   *out = c;
   return ADC_OK;
 }
@@ -326,5 +363,76 @@ extern "C" adc_status adc_cauchy_gemm(adc_ctx c, int64_t P, int64_t K, const dou
   hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, dg, 1);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(c->stream));
+  return ADC_OK;
+}
+
+// Descriptors of the allocation-free Cauchy update, written on the device
+// into the static scratch: the one-merge descriptor of k_cauchy, its column
+// tiles of 8 and the GEMM problem.
+__global__ void k_noalloc_desc(MergeDev* md, int32_t* tm, int32_t* tc, int ntile, GemmProb* gp, int64_t P,
+                               int64_t K, double* qc, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                               const double* v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntile) {
+    tm[t] = 0;
+    tc[t] = 8 * t;
+  }
+  if (t == 0) {
+    MergeDev m{};
+    m.n = (int32_t)K;
+    m.K = (int32_t)K;
+    m.zoff = 0;
+    *md = m;
+    GemmProb g{};
+    g.A = X;
+    g.B = qc;
+    g.C = Y;
+    g.colmap = nullptr;
+    g.vscale = v;
+    g.lda = ldx;
+    g.ldb = K;
+    g.ldc = ldy;
+    g.M = (int32_t)P;
+    g.N = (int32_t)K;
+    g.K = (int32_t)K;
+    g.tile0 = 0;
+    g.tiles_m = (int32_t)((P + 255) / 256);
+    *gp = g;
+  }
+}
+
+extern "C" adc_status adc_cauchy_gemm_noalloc(adc_ctx c, int64_t P, int64_t K, const double* d,
+                                              const double* gam, const double* mu, const double* uh,
+                                              const double* v, const double* X, int64_t ldx, double* Y,
+                                              int64_t ldy) {
+  if (!c || P < 0 || K < 0 || P > (int64_t)INT32_MAX) return ADC_ERR_ARG;
+  if (K > NOALLOC_KMAX) return ADC_ERR_UNSUPPORTED;
+  if (P == 0 || K == 0) return ADC_OK;
+  if (!d || !gam || !mu || !uh || !v || !X || !Y || ldx < P || ldy < P) return ADC_ERR_ARG;
+  if (!c->noalloc_scratch) return ADC_ERR_HIP;
+  DeviceGuard g(c->device);
+  char* base = (char*)c->noalloc_scratch;
+  double* qc = (double*)base;
+  char* desc = base + NOALLOC_QBYTES;
+  MergeDev* dm = (MergeDev*)desc;
+  GemmProb* dg = (GemmProb*)(desc + 256);
+  int32_t* dtm = (int32_t*)(desc + 1024);
+  const int ntile = (int)((K + 7) / 8);
+  int32_t* dtc = dtm + ntile;
+  // 1024 + 2 * 4 * 256 bytes of descriptors at most, inside NOALLOC_DBYTES
+  static_assert(1024 + 8 * ((NOALLOC_KMAX + 7) / 8) <= NOALLOC_DBYTES, "descriptor space");
+  LevelBufs B{};
+  B.dS = const_cast<double*>(d);
+  B.gam = const_cast<double*>(gam);
+  B.mu = const_cast<double*>(mu);
+  B.uh = const_cast<double*>(uh);
+  B.qc = qc;
+  hipLaunchKernelGGL(k_noalloc_desc, dim3((unsigned)((ntile + 255) / 256)), dim3(256), 0, c->stream, dm, dtm, dtc,
+                     ntile, dg, P, K, qc, X, ldx, Y, ldy, v);
+  hipLaunchKernelGGL(k_cauchy, dim3((unsigned)ntile), dim3(256), 0, c->stream, (const MergeDev*)dm, dtm, dtc, B, 8,
+                     0);
+  const int tiles = (int)((P + 255) / 256) * (int)((K + 127) / 128);
+  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, (const GemmProb*)dg, 1);
+  HIP_OK(hipGetLastError());
   return ADC_OK;
 }

@@ -153,6 +153,7 @@ struct adc_ctx_s {
   size_t host_stage2_bytes = 0;
   MlpState* mlp = nullptr;
   void* batch_cache = nullptr;  // graph cache of the batched solver
+  void* noalloc_scratch = nullptr;  // device address of the static scratch on `device`
   PhaseTimer timer;
   KernTimer ktimer;
   // second stream (default priority) for work that overlaps the HSS
