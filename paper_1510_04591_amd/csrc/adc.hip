@@ -110,6 +110,11 @@ extern "C" adc_status adc_create(adc_ctx* out, int device, void* stream) {
   c->device = device;
   c->stream = (hipStream_t)stream;
   {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+      c->num_cu = ncu;
+  }
+  {
     DeviceGuard g(device);
     c->noalloc_scratch = noalloc_scratch_init(device);  // null: the no-alloc entry reports ADC_ERR_HIP
   }

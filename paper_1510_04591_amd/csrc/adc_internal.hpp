@@ -145,6 +145,7 @@ struct adc_ctx_s {
     size_t bytes = 0;
   };
   int device = 0;
+  int num_cu = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   Buf bufs[NSLOT];
   void* host_stage = nullptr;

@@ -23,6 +23,7 @@
 #include "kernels.hpp"
 
 namespace {
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 constexpr int BK = 16;
 constexpr int PAD = 4;
 
@@ -229,6 +230,55 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   }
 
   }
+  if constexpr (BM == 128) {
+    // Epilogue through LDS: the tile goes out 32 columns at a time, each
+    // column as 128 contiguous rows, one wave per column (two rows of 16
+    // bytes per lane) instead of the MFMA result layout's 16 columns of 4
+    // rows per store instruction.  The operand buffer As is free by now.
+    constexpr int CW = 32;                 // columns per pass
+    constexpr int LDC = BM + PAD;          // 132 doubles per staged column
+    static_assert(CW * LDC <= 2 * BK * (BM + PAD), "staging fits in As");
+    double* Cs = &As[0][0][0];
+    gdouble* const gC = gmem(P.C);
+    const bool vec = ((reinterpret_cast<uintptr_t>(P.C) | (uintptr_t)(P.ldc * 8)) & 15) == 0;
+    #pragma unroll
+    for (int pass = 0; pass < BN / CW; ++pass) {
+      __syncthreads();
+      #pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int cl = wn * WTN + b * 16;  // first tile column of the block
+        if (cl / CW != pass) continue;
+        #pragma unroll
+        for (int a = 0; a < TM; ++a)
+          #pragma unroll
+          for (int r = 0; r < 4; ++r) Cs[(cl - pass * CW + li) * LDC + wm * WTM + a * 16 + lk + 4 * r] = acc[a][b][r];
+      }
+      __syncthreads();
+      #pragma unroll
+      for (int q = 0; q < CW * (BM / 2) / NT; ++q) {
+        const int e = tid + NT * q;
+        const int rp = e % (BM / 2), cl = e / (BM / 2);
+        const int col = n0 + pass * CW + cl;
+        const int row = m0 + 2 * rp;
+        if (col >= N || row >= M) continue;
+        const double vs = P.vscale ? gmem(P.vscale)[col] : 1.0;
+        const int64_t cc = (int64_t)(P.colmap ? gmem(P.colmap)[col] : col) * P.ldc;
+        double x0 = Cs[cl * LDC + 2 * rp] * vs, x1 = Cs[cl * LDC + 2 * rp + 1] * vs;
+        gdouble* cp = gC + row + cc;
+        if (vec && row + 1 < M) {
+          if (P.beta != 0.0) {
+            const dbl2 o = *(const __attribute__((address_space(1))) dbl2*)cp;
+            x0 += P.beta * o.x;
+            x1 += P.beta * o.y;
+          }
+          *(__attribute__((address_space(1))) dbl2*)cp = dbl2{x0, x1};
+        } else {
+          cp[0] = (P.beta != 0.0) ? (P.beta * cp[0] + x0) : x0;
+          if (row + 1 < M) cp[1] = (P.beta != 0.0) ? (P.beta * cp[1] + x1) : x1;
+        }
+      }
+    }
+  } else {
   #pragma unroll
   for (int b = 0; b < TN; ++b) {
     const int col = n0 + wn * WTN + b * 16 + li;
@@ -249,6 +299,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
       }
     }
   }
+  }
 }
 
 __device__ __forceinline__ int find_prob(const GemmProb* __restrict__ probs, int nprobs, int bid) {
@@ -261,11 +312,41 @@ __device__ __forceinline__ int find_prob(const GemmProb* __restrict__ probs, int
 }
 }  // namespace
 
-template <int BM, int BN, int WM, int WN, bool PF2 = false>
+// Workgroups are handed to the eight XCDs round-robin by index.  With
+// XCD_GROUPED the flat tile index is first renumbered so that every XCD
+// works on one contiguous range of tiles, and inside a problem the tiles are
+// walked in groups of GROUP_M row tiles (all column tiles of a group before
+// the next group): the workgroups resident on one XCD at a time then share a
+// few A row panels and B column panels, which stay in that XCD's L2.
+constexpr int NXCD = 8;
+constexpr int GROUP_M = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int bid, int nblk) {
+  const int per = nblk / NXCD, rem = nblk % NXCD;
+  const int x = bid % NXCD, i = bid / NXCD;
+  return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+template <int BM, int BN, int WM, int WN, bool PF2 = false, bool XCD_GROUPED = false>
 __device__ __forceinline__ void gemm_dispatch(const GemmProb* __restrict__ probs, int nprobs) {
-  const GemmProb P = probs[find_prob(probs, nprobs, blockIdx.x)];
-  const int local = blockIdx.x - P.tile0;
-  const int m0 = (local % P.tiles_m) * BM, n0 = (local / P.tiles_m) * BN;
+  const int bid = XCD_GROUPED ? xcd_contiguous((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const GemmProb P = probs[find_prob(probs, nprobs, bid)];
+  const int local = bid - P.tile0;
+  int mt, nt;
+  if constexpr (XCD_GROUPED) {
+    const int tiles_n = (P.N + BN - 1) / BN;
+    if (local >= P.tiles_m * tiles_n) return;  // problems sized for a larger N (batched solver)
+    const int gsize = GROUP_M * tiles_n;
+    const int g = local / gsize, first = g * GROUP_M;
+    const int gm = min(P.tiles_m - first, GROUP_M);
+    const int in = local - g * gsize;
+    mt = first + in % gm;
+    nt = in / gm;
+  } else {
+    mt = local % P.tiles_m;
+    nt = local / P.tiles_m;
+  }
+  const int m0 = mt * BM, n0 = nt * BN;
   if (m0 >= P.M || n0 >= P.N) return;
   gemm_tile<BM, BN, WM, WN, PF2>(P, m0, n0);
 }
@@ -283,5 +364,5 @@ __global__ void __launch_bounds__(512) k_gemm_f64_n96(const GemmProb* __restrict
 }
 
 __global__ void __launch_bounds__(1024) k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs) {
-  gemm_dispatch<256, 128, 4, 4, true>(probs, nprobs);
+  gemm_dispatch<256, 128, 4, 4, true, true>(probs, nprobs);
 }

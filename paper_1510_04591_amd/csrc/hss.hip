@@ -635,15 +635,34 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       }
     }
   }
+  // W_q = B_sib(q) V_q^T (kr(sib) x nc_q, column-major) for every node q
+  // strictly between the root and the leaves, once per merge: the downsweep
+  // then forms the blocks its children receive from above in one product,
+  // E_c = [G_sib(q) E_q] [W_q; V_q^T] (columns of c), where E_q is what q
+  // received (zero below the root)
+  std::vector<std::vector<int64_t>> woff(hb.ms.size());
+  int64_t wtotal = 0;
+  for (size_t t = 0; t < jobs.size(); ++t) {
+    const auto& m = hb.ms[jobs[t].g];
+    auto& wo = woff[jobs[t].g];
+    if (!wo.empty()) continue;
+    wo.assign(m.nodes.size(), -1);
+    for (int q = 1; q < (1 << m.L) - 1; ++q) {
+      const int sib = (q & 1) ? q + 1 : q - 1;
+      wo[q] = wtotal;
+      wtotal += (int64_t)m.nodes[sib].kr * m.nodes[q].nc;
+    }
+  }
   void* wp;
   auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t lj_bytes = rup(lj[0].size() * sizeof(int2)) + rup(lj[1].size() * sizeof(int2));
   const size_t of_bytes = rup(doff[0].size() * 8) + rup(doff[1].size() * 8) + rup(uoff.size() * 8);
-  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal + utotal) * 8 + lj_bytes + of_bytes + 1024, &wp));
+  ADC_TRY(c->buffer(SLOT_HSS2, (size_t)(total + dtotal + utotal + wtotal) * 8 + lj_bytes + of_bytes + 1024, &wp));
   double* work = (double*)wp;
   double* dmat = work + total;
   double* uperm = dmat + dtotal;
-  char* tail = (char*)(uperm + utotal);
+  double* wmat = uperm + utotal;
+  char* tail = (char*)(wmat + wtotal);
   int2* d_lj[2];
   int64_t* d_doff[2];
   d_lj[0] = (int2*)tail;
@@ -684,8 +703,8 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
     Lmax = std::max(Lmax, hb.ms[j.g].L);
     nodes_all += hb.ms[j.g].nodes.size();
   }
-  // every node appears in at most one problem of the upsweep, two of the
-  // downsweep and one of the leaf step
+  // every node appears in at most one W product, one problem of the
+  // upsweep, one of the downsweep and one of the leaf step
   ProbArena ar;
   ar.cap = 4 * nodes_all + 64;
   {
@@ -709,9 +728,35 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
     while ((1 << (l + 1)) - 1 <= node) ++l;
     return work + lays[t].lev_f[l] + lays[t].foff[node] * jobs[t].P;
   };
+  // the W_q products, in the first launch group
+  probs.clear();
+  for (size_t g = 0; g < hb.ms.size(); ++g) {
+    if (woff[g].empty()) continue;
+    const auto& m = hb.ms[g];
+    for (int q = 1; q < (1 << m.L) - 1; ++q) {
+      const int sib = (q & 1) ? q + 1 : q - 1;
+      const HssNode& nd = m.nodes[q];
+      const HssNode& sj = m.nodes[sib];
+      GemmProb p{};
+      p.M = sj.kr;
+      p.N = nd.nc;
+      p.K = nd.kc;
+      p.A = m.dev.arena + sj.offB;  // kr(sib) x kc(q)
+      p.lda = std::max(sj.kr, 1);
+      p.B = m.dev.arena + nd.offV;  // nc x kc, read transposed
+      p.ldb = std::max(nd.nc, 1);
+      p.transB = 1;
+      p.C = wmat + woff[g][q];
+      p.ldc = std::max(sj.kr, 1);
+      push_prob(probs, p);
+    }
+  }
+  std::vector<GemmProb> wprobs;
+  wprobs.swap(probs);
   // upsweep
   for (int l = Lmax; l >= 1; --l) {
     probs.clear();
+    if (l == Lmax) probs.swap(wprobs);
     for (size_t t = 0; t < jobs.size(); ++t) {
       const auto& m = hb.ms[jobs[t].g];
       if (l > m.L) continue;
@@ -748,7 +793,10 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
     }
     ADC_TRY(launch_probs(c, probs, flops, ar));
   }
-  // downsweep: H_i = G_j B_j (+ F_i); then [F_i1 F_i2] = H_i V_i^T
+  // downsweep, one launch per level l: for every node q at level l above
+  // the leaves, its children's incoming blocks [E_c1 E_c2] = [G_sib(q) E_q]
+  // [W_q; V_q^T] (E_q = 0 at level 1); at the leaf level, F_i = G_sib(i)
+  // B_sib(i) + E_i, which the leaf step multiplies by V_i^T
   for (int l = 1; l <= Lmax; ++l) {
     probs.clear();
     for (size_t t = 0; t < jobs.size(); ++t) {
@@ -761,36 +809,29 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         const HssNode& sj = m.nodes[sib];
         GemmProb p{};
         p.M = J.P;
-        p.N = nd.kc;
-        p.K = sj.kr;
         p.A = G(t, sib);
         p.lda = J.P;
-        p.B = m.dev.arena + sj.offB;  // kr(sib) x kc(i)
-        p.ldb = std::max(sj.kr, 1);
-        p.C = F(t, q);
-        p.ldc = J.P;
-        p.beta = (l > 1) ? 1.0 : 0.0;
-        push_prob(probs, p);
-      }
-    }
-    ADC_TRY(launch_probs(c, probs, flops, ar));
-    probs.clear();
-    for (size_t t = 0; t < jobs.size(); ++t) {
-      const auto& m = hb.ms[jobs[t].g];
-      if (l >= m.L) continue;
-      const ApplyJob& J = jobs[t];
-      for (int q = (1 << l) - 1; q < (1 << (l + 1)) - 1; ++q) {
-        const HssNode& nd = m.nodes[q];
-        GemmProb p{};
-        p.M = J.P;
-        p.N = nd.nc;  // kc(i1) + kc(i2)
-        p.K = nd.kc;
-        p.A = F(t, q);
-        p.lda = J.P;
-        p.B = m.dev.arena + nd.offV;  // nc x kc, read transposed
-        p.ldb = std::max(nd.nc, 1);
-        p.transB = 1;
-        p.C = F(t, 2 * q + 1);
+        p.K = sj.kr;
+        if (l < m.L) {
+          p.N = nd.nc;  // kc(c1) + kc(c2)
+          p.B = wmat + woff[J.g][q];
+          p.ldb = std::max(sj.kr, 1);
+          if (l > 1) {
+            p.A2 = F(t, q);
+            p.lda2 = J.P;
+            p.K2 = nd.kc;
+            p.B2 = m.dev.arena + nd.offV;  // nc x kc, read transposed
+            p.ldb2 = std::max(nd.nc, 1);
+            p.transB2 = 1;
+          }
+          p.C = F(t, 2 * q + 1);  // [E_c1 E_c2] are adjacent
+        } else {
+          p.N = nd.kc;
+          p.B = m.dev.arena + sj.offB;  // kr(sib) x kc(i)
+          p.ldb = std::max(sj.kr, 1);
+          p.C = F(t, q);
+          p.beta = (l > 1) ? 1.0 : 0.0;
+        }
         p.ldc = J.P;
         push_prob(probs, p);
       }

@@ -135,7 +135,7 @@ __global__ void k_leaf_group(const MergeDev* __restrict__ merges, const int2* __
 __global__ void k_zero_unsupported(const MergeDev* __restrict__ merges, int g, LevelBufs B);
 
 __global__ void k_pack_rot(const MergeDev* __restrict__ merges, const int32_t* __restrict__ col_merge,
-                           const int32_t* __restrict__ col_idx, LevelBufs B);
+                           const int32_t* __restrict__ col_idx, LevelBufs B, int njob);
 
 __global__ void k_cauchy(const MergeDev* __restrict__ merges, const int32_t* __restrict__ tile_merge,
                          const int32_t* __restrict__ tile_col0, LevelBufs B, int ncols, int grouped);

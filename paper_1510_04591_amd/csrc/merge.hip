@@ -619,14 +619,14 @@ __global__ void __launch_bounds__(256) k_zero_unsupported(const MergeDev* __rest
 // the merged block and the last (surviving) column into the packed operand;
 // the other chain members do nothing.  Rows outside a column's original
 // support are the zeros of diag(Q1, Q2).
-__global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
-                                                  const int32_t* __restrict__ col_merge,
-                                                  const int32_t* __restrict__ col_idx, LevelBufs B) {
+__device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges,
+                                             const int32_t* __restrict__ col_merge,
+                                             const int32_t* __restrict__ col_idx, const LevelBufs& B, int job) {
   constexpr int CHMAX = 8;  // rotation steps held in registers
-  const MergeDev& M = merges[col_merge[blockIdx.x]];
+  const MergeDev& M = merges[col_merge[job]];
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1;
-  const int p = col_idx[blockIdx.x];
+  const int p = col_idx[job];
   const int bs = blockDim.x, tid = threadIdx.x;
   if (B.rot_j_of[s0 + p] >= 0) return;  // inside a chain: done by its head
   auto dst_of = [&](int pos) -> double* {
@@ -753,6 +753,15 @@ __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ m
     }
     dst_of(B.rot_j[s0 + t1])[r] = a;
   }
+}
+
+// Jobs strided over the grid: with fewer workgroups than jobs the packing
+// leaves room on every CU for a kernel that needs a whole CU's LDS (the node
+// compression, which runs beside the packing at HSS levels).
+__global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
+                                                  const int32_t* __restrict__ col_merge,
+                                                  const int32_t* __restrict__ col_idx, LevelBufs B, int njob) {
+  for (int job = blockIdx.x; job < njob; job += gridDim.x) pack_rot_job(merges, col_merge, col_idx, B, job);
 }
 
 // ---------------------------------------------------------------------------
