@@ -69,6 +69,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=32768)
     p.add_argument("--hss-leaf", type=int, default=128, help="HSS leaf size of the headline options")
+    p.add_argument("--id-tol", type=float, default=1e-14, help="ID truncation tolerance of the headline options")
     p.add_argument("--dense-steps", type=int, default=3)
     p.add_argument("--dense-warmup", type=int, default=1)
     p.add_argument("--no-extra", action="store_true",
@@ -496,7 +497,7 @@ def main():
     ctx = adc.Context(0)
     w = torch.empty(N, dtype=torch.float64, device="cuda")
     Zt = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    hss_opts = adc.opts(**dict(HEADLINE, hss_leaf=args.hss_leaf))
+    hss_opts = adc.opts(**dict(HEADLINE, hss_leaf=args.hss_leaf, id_tol=args.id_tol))
     dense_opts = adc.opts(dc_leaf=32, force_dense=1)
 
     def solve(o):
@@ -614,7 +615,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=2.5e10 flops, HSS leaf {args.hss_leaf}, p=16",
+        "config": {"workload": f"toeplitz(2,1) N={N}, DC leaf 32, HSS on merges with K>=2048 and dense update >=2.5e10 flops, HSS leaf {args.hss_leaf}, p=16, ID tolerance {args.id_tol:g}",
                    "update": head, "n": N, "K_per_level": r0["K_per_level"],
                    "hss_per_level": r0["hss_per_level"], "max_rank": r0["max_rank"],
                    "samples": r0["samples"], "retries": r0["retries"], "fallbacks": r0["hss_fallbacks"],

@@ -165,6 +165,9 @@ void adc_ctx_s::release() {
   host_stage_bytes = 0;
   if (host_stage2) hipHostFree(host_stage2);
   host_stage2 = nullptr;
+  if (host_up) hipHostFree(host_up);
+  host_up = nullptr;
+  host_up_bytes = host_up_used = 0;
   host_stage2_bytes = 0;
   timer.destroy();
   ktimer.destroy();
@@ -206,6 +209,30 @@ adc_status adc_ctx_s::stage(size_t bytes, void** p) {
     host_stage_bytes = want;
   }
   *p = host_stage;
+  return ADC_OK;
+}
+
+adc_status adc_ctx_s::upload(void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return ADC_OK;
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  if (host_up_used + need > host_up_bytes) {
+    // the regions handed out so far may still be read by queued copies:
+    // wait for them, then grow
+    HIP_OK(hipStreamSynchronize(stream));
+    host_up_used = 0;
+    if (need > host_up_bytes) {
+      if (host_up) hipHostFree(host_up);
+      host_up = nullptr;
+      host_up_bytes = 0;
+      const size_t want = std::max(need, (size_t)(4 << 20));
+      if (hipHostMalloc((void**)&host_up, want, hipHostMallocDefault) != hipSuccess) return ADC_ERR_NOMEM;
+      host_up_bytes = want;
+    }
+  }
+  char* h = host_up + host_up_used;
+  std::memcpy(h, src, bytes);
+  host_up_used += need;
+  HIP_OK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, stream));
   return ADC_OK;
 }
 

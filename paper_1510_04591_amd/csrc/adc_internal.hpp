@@ -152,6 +152,12 @@ struct adc_ctx_s {
   size_t host_stage_bytes = 0;
   void* host_stage2 = nullptr;  // pinned staging of GEMM problem lists
   size_t host_stage2_bytes = 0;
+  // pinned bump arena for small host-to-device uploads on `stream` (launch
+  // lists, node tables): a copy from pageable memory blocks the host, one
+  // from pinned memory is queued.  Regions are not reused until up_reset,
+  // which callers invoke only right after synchronising `stream`.
+  char* host_up = nullptr;
+  size_t host_up_bytes = 0, host_up_used = 0;
   MlpState* mlp = nullptr;
   void* batch_cache = nullptr;  // graph cache of the batched solver
   void* noalloc_scratch = nullptr;  // device address of the static scratch on `device`
@@ -165,6 +171,8 @@ struct adc_ctx_s {
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);
   adc_status stage2(size_t bytes, void** p);
+  adc_status upload(void* dst, const void* src, size_t bytes);  // queued on `stream`
+  void up_reset() { host_up_used = 0; }
   void release();
 };
 

@@ -173,9 +173,9 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   GemmProb* dg = (GemmProb*)dp;
   int32_t* dtm = (int32_t*)((char*)dp + 256);
   int32_t* dtc = dtm + nt;
-  HIP_OK(hipMemcpyAsync(dg, &P, sizeof(P), hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(dtm, tm.data(), nt * 4, hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(dtc, tc.data(), nt * 4, hipMemcpyHostToDevice, st));
+  ADC_TRY(c->upload(dg, &P, sizeof(P)));
+  ADC_TRY(c->upload(dtm, tm.data(), nt * 4));
+  ADC_TRY(c->upload(dtc, tc.data(), nt * 4));
   // rows of qc in the packed order of the merge's columns; the packed
   // columns' unsupported halves zeroed, since this product reads all n rows
   hipLaunchKernelGGL(k_zero_unsupported, dim3((unsigned)M.K), dim3(256), 0, st, d_m, g, B);
@@ -565,6 +565,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       ADC_TRY(hs);
     }
     HIP_OK(hipStreamSynchronize(st));  // staging buffer reused by the next level
+    c->up_reset();
     c->timer.collect(rep);
     c->ktimer.collect(rep);
 

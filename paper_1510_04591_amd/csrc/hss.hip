@@ -204,15 +204,14 @@ static adc_status batch_upload(adc_ctx c, HssBatch& hb) {
     std::vector<int32_t> lo(m.K);
     for (size_t t = 0; t + 1 < m.bounds.size(); ++t)
       for (int i = m.bounds[t]; i < m.bounds[t + 1]; ++i) lo[i] = (int32_t)t;
-    HIP_OK(hipMemcpyAsync((void*)m.dev.leafof, lo.data(), m.K * 4, hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync((void*)m.dev.bounds, m.bounds.data(), m.bounds.size() * 4, hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(m.dev.nodes, m.nodes.data(), m.nodes.size() * sizeof(HssNode), hipMemcpyHostToDevice, st));
+    ADC_TRY(c->upload((void*)m.dev.leafof, lo.data(), m.K * 4));
+    ADC_TRY(c->upload((void*)m.dev.bounds, m.bounds.data(), m.bounds.size() * 4));
+    ADC_TRY(c->upload(m.dev.nodes, m.nodes.data(), m.nodes.size() * sizeof(HssNode)));
   }
   std::vector<HssMerge> hm;
   for (auto& m : hb.ms) hm.push_back(m.dev);
-  HIP_OK(hipMemcpyAsync(hb.d_ms, hm.data(), hm.size() * sizeof(HssMerge), hipMemcpyHostToDevice, st));
-  // the host vectors above are released on return: make the copies complete
-  HIP_OK(hipStreamSynchronize(st));
+  ADC_TRY(c->upload(hb.d_ms, hm.data(), hm.size() * sizeof(HssMerge)));
+  (void)st;
   return ADC_OK;
 }
 
@@ -246,7 +245,7 @@ static adc_status sample_direct(adc_ctx c, HssBatch& hb) {
   void* dj;
   ADC_TRY(c->buffer(SLOT_SAMPLE_JOBS, sj.size() * sizeof(SampleJob) + 256, &dj));
   hb.sample_host.assign((const char*)sj.data(), (const char*)(sj.data() + sj.size()));
-  HIP_OK(hipMemcpyAsync(dj, hb.sample_host.data(), hb.sample_host.size(), hipMemcpyHostToDevice, st));
+  ADC_TRY(c->upload(dj, hb.sample_host.data(), hb.sample_host.size()));
   // algorithmic flops of one sampling pass: the off-diagonal-block part of
   // Q' times s columns; bytes: Omega read, the samples written
   double sfl = 0.0, sby = 0.0;
@@ -350,7 +349,7 @@ static adc_status fmm_run(adc_ctx c, HssBatch& hb, std::vector<FmmIo>& io, int s
   void* dp;
   ADC_TRY(c->buffer(SLOT_SAMPLE_JOBS, host.size() + 256, &dp));
   char* dj = (char*)dp;
-  HIP_OK(hipMemcpyAsync(dj, host.data(), host.size(), hipMemcpyHostToDevice, st));
+  ADC_TRY(c->upload(dj, host.data(), host.size()));
   const FmmIo* d_io = (const FmmIo*)(dj + o_io);
   const int32_t* d_lists = (const int32_t*)(dj + o_lists);
   if (!p2m.empty())
@@ -442,7 +441,7 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
   std::vector<size_t> o_lj(Lmax + 1), o_bj(Lmax + 1);
   for (int l = 0; l <= Lmax; ++l) o_lj[l] = put(lj[l].data(), lj[l].size() * sizeof(NodeJob));
   for (int l = 0; l <= Lmax; ++l) o_bj[l] = put(bj[l].data(), bj[l].size() * sizeof(NodeJob));
-  HIP_OK(hipMemcpyAsync(dj, hj.data(), off, hipMemcpyHostToDevice, st));
+  ADC_TRY(c->upload(dj, hj.data(), off));
   // dynamic LDS of every node job: its ID matrix when it fits (odd leading
   // dimension sp + 1), else the staging of its small products
   (void)ncand_max;
@@ -523,7 +522,7 @@ struct ProbArena {
     int count, tiles;
     double flops, bytes;
   };
-  std::vector<Launch> launches;  // recorded in order, issued by flush_probs
+  std::vector<Launch> launches;  // in order of issue
 };
 
 static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops, ProbArena& ar) {
@@ -544,6 +543,7 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
   }
   hipStream_t st = c->stream;
   static const int BN[3] = {64, 96, 128};
+  const size_t first = ar.used, nl0 = ar.launches.size();
   for (int w = 0; w < 3; ++w) {
     auto& L = cls[w];
     if (L.empty()) continue;
@@ -559,16 +559,11 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
     ar.launches.push_back(ProbArena::Launch{w, ar.used, (int)L.size(), tiles, pf[w], pb[w]});
     ar.used += L.size();
   }
-  (void)st;
-  return ADC_OK;
-}
-
-// One upload of every recorded problem list, then the launches back to back.
-static adc_status flush_probs(adc_ctx c, ProbArena& ar) {
-  hipStream_t st = c->stream;
-  if (ar.used == 0) return ADC_OK;
-  HIP_OK(hipMemcpyAsync(ar.d, ar.h, ar.used * sizeof(GemmProb), hipMemcpyHostToDevice, st));
-  for (const auto& l : ar.launches) {
+  // issued at once (the descriptors through the pinned upload arena, so the
+  // host goes on building the next level's lists while these run)
+  ADC_TRY(c->upload(ar.d + first, ar.h + first, (ar.used - first) * sizeof(GemmProb)));
+  for (size_t li = nl0; li < ar.launches.size(); ++li) {
+    const auto& l = ar.launches[li];
     const GemmProb* dp = ar.d + l.off;
     c->ktimer.pre(st);
     if (l.cls == 0)
@@ -674,13 +669,13 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
   // D_i of both flavours and the grouped U_i
   for (int f = 0; f < 2; ++f) {
     if (lj[f].empty()) continue;
-    HIP_OK(hipMemcpyAsync(d_lj[f], lj[f].data(), lj[f].size() * sizeof(int2), hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(d_doff[f], doff[f].data(), doff[f].size() * 8, hipMemcpyHostToDevice, st));
+    ADC_TRY(c->upload(d_lj[f], lj[f].data(), lj[f].size() * sizeof(int2)));
+    ADC_TRY(c->upload(d_doff[f], doff[f].data(), doff[f].size() * 8));
     hipLaunchKernelGGL(k_hss_dmat, dim3((unsigned)lj[f].size()), dim3(256), 0, st, hb.d_ms, d_lj[f], dmat,
                        d_doff[f], f);
   }
   if (!lj[1].empty()) {
-    HIP_OK(hipMemcpyAsync(d_uoff, uoff.data(), uoff.size() * 8, hipMemcpyHostToDevice, st));
+    ADC_TRY(c->upload(d_uoff, uoff.data(), uoff.size() * 8));
     hipLaunchKernelGGL(k_hss_urows, dim3((unsigned)lj[1].size()), dim3(256), 0, st, hb.d_ms, d_lj[1], uperm,
                        d_uoff);
   }
@@ -706,13 +701,13 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
   // every node appears in at most one W product, one problem of the
   // upsweep, one of the downsweep and one of the leaf step
   ProbArena ar;
+  std::vector<GemmProb> hprobs;
   ar.cap = 4 * nodes_all + 64;
   {
-    void* hpin;
     void* dbuf;
-    ADC_TRY(c->stage2(ar.cap * sizeof(GemmProb), &hpin));
     ADC_TRY(c->buffer(SLOT_GEMM_A, ar.cap * sizeof(GemmProb) + 256, &dbuf));
-    ar.h = (GemmProb*)hpin;
+    hprobs.resize(ar.cap);
+    ar.h = hprobs.data();
     ar.d = (GemmProb*)dbuf;
   }
   std::vector<GemmProb> probs;
@@ -881,9 +876,6 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
     }
   }
   ADC_TRY(launch_probs(c, probs, flops, ar));
-  ADC_TRY(flush_probs(c, ar));
-  // the pinned problem lists are reused by the next run
-  HIP_OK(hipStreamSynchronize(st));
   return ADC_OK;
 }
 
@@ -1140,6 +1132,7 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
                           hipMemcpyDeviceToHost, st));
   }
   HIP_OK(hipStreamSynchronize(st));
+  c->up_reset();  // every earlier upload on the stream has completed
   for (size_t t = 0; t < which.size(); ++t) {
     const MergeDev& M = h_m[which[t]];
     HssBatch::One m;
