@@ -30,13 +30,122 @@ constexpr int PAD = 4;
 // PF2: the operand tiles of two K steps ahead in flight (two register sets);
 // otherwise one step ahead.  The deeper prefetch costs registers and pays
 // only where occupancy is not the limit (the 256 x 128 tiles).
+// Operand loads of one K step.  Lane mapping (fixed for the tile):
+//   A (column-major, BM x BK): row tid % BM, columns tid / BM + (NT / BM) q;
+//   B (BK x BN): k index kb, columns cb0 + (NT / BK) q, with kb = tid % BK,
+//     cb0 = tid / BK when B is read as stored (k fastest in memory), and
+//     kb = (tid / 32) % BK, cb0 = tid % 32 + 32 (tid / (32 BK)) when it is
+//     read transposed (n fastest in memory), so that a wave reads whole
+//     128- or 256-byte runs in both cases.
+// The pointers advance by one K step per call; rows, columns and the K
+// range of the segment are checked only where a step can leave them.
+template <int BM, int BN, int NT>
+struct TileLoader {
+  static constexpr int ALOADS = BM * BK / NT, BLOADS = BK * BN / NT;
+  static constexpr int AST = NT / BM, BST = NT / BK;
+  static_assert(NT % BM == 0 && NT % BK == 0 && NT % (32 * BK) == 0 && BN % 32 == 0, "loader layout");
+  int ar, ac0, kb, cb0;
+  bool row_ok, interior;
+  bool col_ok[BLOADS];
+  // current segment
+  gcdouble* pa;
+  gcdouble* pb;
+  int64_t a_q, a_step, b_q, b_step;
+  int kpos, kend;  // step start and end of the segment's K range
+  bool trans;
+  int seg;         // 0: first segment, 1: second, 2: done
+
+  __device__ __forceinline__ void start_segment(const GemmProb& P, int m0, int n0, int s) {
+    seg = s;
+    const int K = s == 0 ? P.K : P.K2;
+    if (K <= 0) {
+      if (s == 0) start_segment(P, m0, n0, 1);
+      else seg = 2;
+      return;
+    }
+    const double* A = s == 0 ? P.A : P.A2;
+    const double* B = s == 0 ? P.B : P.B2;
+    const int64_t lda = s == 0 ? P.lda : P.lda2, ldb = s == 0 ? P.ldb : P.ldb2;
+    trans = (s == 0 ? P.transB : P.transB2) != 0;
+    const int tid = threadIdx.x;
+    kb = trans ? (tid / 32) % BK : tid % BK;
+    cb0 = trans ? tid % 32 + 32 * (tid / (32 * BK)) : tid / BK;
+    kpos = 0;
+    kend = K;
+    pa = gmem(A) + (m0 + ar) + (int64_t)ac0 * lda;
+    a_q = (int64_t)AST * lda;
+    a_step = (int64_t)BK * lda;
+    if (trans) {
+      pb = gmem(B) + (n0 + cb0) + (int64_t)kb * ldb;
+      b_q = BST;
+      b_step = (int64_t)BK * ldb;
+    } else {
+      pb = gmem(B) + kb + (int64_t)(n0 + cb0) * ldb;
+      b_q = (int64_t)BST * ldb;
+      b_step = BK;
+    }
+    interior = row_ok;
+#pragma unroll
+    for (int q = 0; q < BLOADS; ++q) {
+      col_ok[q] = n0 + cb0 + BST * q < P.N;
+      interior = interior && col_ok[q];
+    }
+  }
+
+  __device__ __forceinline__ void init(const GemmProb& P, int m0, int n0) {
+    const int tid = threadIdx.x;
+    ar = tid % BM;
+    ac0 = tid / BM;
+    row_ok = m0 + ar < P.M;
+    start_segment(P, m0, n0, 0);
+  }
+
+  // One step's operands in registers, with the B lane mapping they were
+  // loaded with (the two segments may read B differently).
+  struct Regs {
+    double a[ALOADS], b[BLOADS];
+    int kb, cb0;
+  };
+
+  // loads of the step at kpos into r; then one step on (next segment when
+  // this one is used up)
+  __device__ __forceinline__ void load(const GemmProb& P, int m0, int n0, Regs& r) {
+    double* ra = r.a;
+    double* rb = r.b;
+    r.kb = kb;
+    r.cb0 = cb0;
+    const bool full = kpos + BK <= kend;
+    // the wave-uniform fast case: every row, column and k index inside
+    if (__builtin_amdgcn_readfirstlane((int)(full && interior)) && full && interior) {
+#pragma unroll
+      for (int q = 0; q < ALOADS; ++q) ra[q] = pa[q * a_q];
+#pragma unroll
+      for (int q = 0; q < BLOADS; ++q) rb[q] = pb[q * b_q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < ALOADS; ++q) ra[q] = (row_ok && kpos + ac0 + AST * q < kend) ? pa[q * a_q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < BLOADS; ++q) rb[q] = (col_ok[q] && kpos + kb < kend) ? pb[q * b_q] : 0.0;
+    }
+    kpos += BK;
+    pa += a_step;
+    pb += b_step;
+    if (kpos >= kend && seg == 0) start_segment(P, m0, n0, 1);
+  }
+};
+
+// PF2: the operand tiles of two K steps ahead in flight (two register sets);
+// otherwise one step ahead.  The deeper prefetch costs registers and pays
+// only where occupancy is not the limit (the 256 x 128 tiles).
 template <int BM, int BN, int WM, int WN, bool PF2>
 __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   constexpr int NT = 64 * WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN;  // rows / columns per wave
   constexpr int TM = WTM / 16, TN = WTN / 16;  // 16 x 16 tiles per wave
-  constexpr int ALOADS = BM * BK / NT, BLOADS = BK * BN / NT;
-  static_assert(ALOADS * NT == BM * BK && BLOADS * NT == BK * BN, "tile / lane mismatch");
+  using LD = TileLoader<BM, BN, NT>;
+  constexpr int ALOADS = LD::ALOADS, BLOADS = LD::BLOADS;
+  (void)ALOADS;
+  (void)BLOADS;
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
 
@@ -45,7 +154,6 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
   const int wm = wv % WM, wn = wv / WM;
   const int li = lane & 15, lk = lane >> 4;
   const int M = P.M, N = P.N;
-  const int Kt = P.K + P.K2;
 
   dbl4 acc[TM][TN];
   #pragma unroll
@@ -53,165 +161,18 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
     #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  gcdouble* const gA = gmem(P.A);
-  gcdouble* const gA2 = gmem(P.A2);
-  gcdouble* const gB = gmem(P.B);
-  gcdouble* const gB2 = gmem(P.B2);
-  if constexpr (PF2) {
-    // Two register sets of operand loads: the tile two K steps ahead is in
-    // flight while the next one is stored to LDS and the current one feeds
-    // the matrix cores (set indices are compile-time: the loop is unrolled
-    // by two).
-    double ra0[ALOADS], rb0[BLOADS], ra1[ALOADS], rb1[BLOADS];
-    // A K step lies entirely in one segment: steps of the first segment start
-    // at multiples of BK below P.K and stop at P.K; those of the second start
-    // at P.K + multiples of BK.
-    auto gload = [&](int k0, double* ra, double* rb) {
-      const bool s1 = k0 < P.K;
-      const int lim = s1 ? P.K : Kt;
-      #pragma unroll
-      for (int q = 0; q < ALOADS; ++q) {
-        const int e = tid + NT * q;
-        const int r = e % BM, c = e / BM;
-        const int gr = m0 + r, gk = k0 + c;
-        double x = 0.0;
-        if (gr < M && gk < lim) x = s1 ? gA[gr + (int64_t)gk * P.lda] : gA2[gr + (int64_t)(gk - P.K) * P.lda2];
-        ra[q] = x;
-      }
-      const bool tr = s1 ? P.transB : P.transB2;
-      #pragma unroll
-      for (int q = 0; q < BLOADS; ++q) {
-        const int e = tid + NT * q;
-        const int kr = tr ? e / BN : (e % BK);
-        const int cc = tr ? e % BN : (e / BK);
-        const int gk = k0 + kr, gn = n0 + cc;
-        double x = 0.0;
-        if (gk < lim && gn < N) {
-          if (s1) x = tr ? gB[gn + (int64_t)gk * P.ldb] : gB[gk + (int64_t)gn * P.ldb];
-          else {
-            const int g2 = gk - P.K;
-            x = tr ? gB2[gn + (int64_t)g2 * P.ldb2] : gB2[g2 + (int64_t)gn * P.ldb2];
-          }
-        }
-        rb[q] = x;
-      }
-    };
-    auto sstore = [&](int buf, int k0, const double* ra, const double* rb) {
-      #pragma unroll
-      for (int q = 0; q < ALOADS; ++q) {
-        const int e = tid + NT * q;
-        As[buf][e / BM][e % BM] = ra[q];
-      }
-      const bool tr = (k0 < P.K) ? P.transB : P.transB2;
-      #pragma unroll
-      for (int q = 0; q < BLOADS; ++q) {
-        const int e = tid + NT * q;
-        if (tr) Bs[buf][e / BN][e % BN] = rb[q];
-        else Bs[buf][e % BK][e / BK] = rb[q];
-      }
-    };
-
-    const int nk1 = (P.K + BK - 1) / BK;
-    const int nk2 = (P.K2 + BK - 1) / BK;
-    const int nk = nk1 + nk2;
-    auto kstart = [&](int kt) { return kt < nk1 ? kt * BK : P.K + (kt - nk1) * BK; };
-    auto mfma_step = [&](int buf) {
-      #pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        const int k = kk * 4 + lk;
-        double av[TM], bv[TN];
-        #pragma unroll
-        for (int t = 0; t < TM; ++t) av[t] = As[buf][k][wm * WTM + t * 16 + li];
-        #pragma unroll
-        for (int t = 0; t < TN; ++t) bv[t] = Bs[buf][k][wn * WTN + t * 16 + li];
-        #pragma unroll
-        for (int a = 0; a < TM; ++a)
-          #pragma unroll
-          for (int b = 0; b < TN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-      }
-    };
-    // step kt: LDS buffer kt & 1 holds tile kt; the set `nx` holds tile kt + 1
-    // (stored at the end of the step), the set `fr` is free and receives tile
-    // kt + 2
-    auto step = [&](int kt, const double* nxa, const double* nxb, double* fra, double* frb) {
-      if (kt + 2 < nk) gload(kstart(kt + 2), fra, frb);
-      mfma_step(kt & 1);
-      if (kt + 1 < nk) sstore((kt + 1) & 1, kstart(kt + 1), nxa, nxb);
-      __syncthreads();
-    };
-    if (nk > 0) {
-      gload(kstart(0), ra0, rb0);
-      sstore(0, kstart(0), ra0, rb0);
-    }
-    if (nk > 1) gload(kstart(1), ra1, rb1);
-    __syncthreads();
-    for (int kt = 0; kt < nk; kt += 2) {
-      step(kt, ra1, rb1, ra0, rb0);
-      if (kt + 1 < nk) step(kt + 1, ra0, rb0, ra1, rb1);
-    }
-  } else {
-    double ra[ALOADS], rb[BLOADS];
-    // A K step lies entirely in one segment: steps of the first segment start
-    // at multiples of BK below P.K and stop at P.K; those of the second start
-    // at P.K + multiples of BK.
-    auto gload = [&](int k0) {
-      const bool s1 = k0 < P.K;
-      const int lim = s1 ? P.K : Kt;
-      #pragma unroll
-      for (int q = 0; q < ALOADS; ++q) {
-        const int e = tid + NT * q;
-        const int r = e % BM, c = e / BM;
-        const int gr = m0 + r, gk = k0 + c;
-        double x = 0.0;
-        if (gr < M && gk < lim) x = s1 ? gA[gr + (int64_t)gk * P.lda] : gA2[gr + (int64_t)(gk - P.K) * P.lda2];
-        ra[q] = x;
-      }
-      const bool tr = s1 ? P.transB : P.transB2;
-      #pragma unroll
-      for (int q = 0; q < BLOADS; ++q) {
-        const int e = tid + NT * q;
-        const int kr = tr ? e / BN : (e % BK);
-        const int cc = tr ? e % BN : (e / BK);
-        const int gk = k0 + kr, gn = n0 + cc;
-        double x = 0.0;
-        if (gk < lim && gn < N) {
-          if (s1) x = tr ? gB[gn + (int64_t)gk * P.ldb] : gB[gk + (int64_t)gn * P.ldb];
-          else {
-            const int g2 = gk - P.K;
-            x = tr ? gB2[gn + (int64_t)g2 * P.ldb2] : gB2[g2 + (int64_t)gn * P.ldb2];
-          }
-        }
-        rb[q] = x;
-      }
-    };
-    auto sstore = [&](int buf, int k0) {
-      #pragma unroll
-      for (int q = 0; q < ALOADS; ++q) {
-        const int e = tid + NT * q;
-        As[buf][e / BM][e % BM] = ra[q];
-      }
-      const bool tr = (k0 < P.K) ? P.transB : P.transB2;
-      #pragma unroll
-      for (int q = 0; q < BLOADS; ++q) {
-        const int e = tid + NT * q;
-        if (tr) Bs[buf][e / BN][e % BN] = rb[q];
-        else Bs[buf][e % BK][e / BK] = rb[q];
-      }
-    };
-
-    const int nk1 = (P.K + BK - 1) / BK;
-    const int nk2 = (P.K2 + BK - 1) / BK;
-    const int nk = nk1 + nk2;
-    auto kstart = [&](int kt) { return kt < nk1 ? kt * BK : P.K + (kt - nk1) * BK; };
-    if (nk > 0) {
-      gload(kstart(0));
-      sstore(0, kstart(0));
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload(kstart(kt + 1));
+  LD ld;
+  ld.init(P, m0, n0);
+  const int nk = (P.K + BK - 1) / BK + (P.K2 + BK - 1) / BK;
+  using Regs = typename LD::Regs;
+  // LDS places of a register set's loads
+  auto sstore = [&](int buf, const Regs& r) {
+    #pragma unroll
+    for (int q = 0; q < ALOADS; ++q) As[buf][ld.ac0 + LD::AST * q][ld.ar] = r.a[q];
+    #pragma unroll
+    for (int q = 0; q < BLOADS; ++q) Bs[buf][r.kb][r.cb0 + LD::BST * q] = r.b[q];
+  };
+  auto mfma_step = [&](int buf) {
     #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int k = kk * 4 + lk;
@@ -223,12 +184,50 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int m0, int n0) {
       #pragma unroll
       for (int a = 0; a < TM; ++a)
         #pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1, kstart(kt + 1));
+  };
+  if constexpr (PF2) {
+    // Two register sets of operand loads: the tile two K steps ahead is in
+    // flight while the next one is stored to LDS and the current one feeds
+    // the matrix cores (set indices are compile-time: the loop is unrolled
+    // by two).  The per-step segment bookkeeping is in the loader; the B
+    // layout of a step does not depend on the segment (LDS is [k][n]).
+    Regs r0, r1;
+    // step kt: LDS buffer kt & 1 holds tile kt; the set `nx` holds tile kt + 1
+    // (stored at the end of the step), the set `fr` is free and receives tile
+    // kt + 2
+    auto step = [&](int kt, const Regs& nx, Regs& fr) {
+      if (kt + 2 < nk) ld.load(P, m0, n0, fr);
+      mfma_step(kt & 1);
+      if (kt + 1 < nk) sstore((kt + 1) & 1, nx);
+      __syncthreads();
+    };
+    if (nk > 0) {
+      ld.load(P, m0, n0, r0);
+      sstore(0, r0);
+    }
+    if (nk > 1) ld.load(P, m0, n0, r1);
     __syncthreads();
-  }
-
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, r1, r0);
+      if (kt + 1 < nk) step(kt + 1, r0, r1);
+    }
+  } else {
+    Regs r;
+    if (nk > 0) {
+      ld.load(P, m0, n0, r);
+      sstore(0, r);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) ld.load(P, m0, n0, r);
+      mfma_step(buf);
+      if (kt + 1 < nk) sstore(buf ^ 1, r);
+      __syncthreads();
+    }
   }
   if constexpr (BM == 128) {
     // Epilogue through LDS: the tile goes out 32 columns at a time, each

@@ -623,6 +623,7 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
                                              const int32_t* __restrict__ col_merge,
                                              const int32_t* __restrict__ col_idx, const LevelBufs& B, int job) {
   constexpr int CHMAX = 8;  // rotation steps held in registers
+  constexpr int RU = 4;     // rows per lane and iteration (loads in flight)
   const MergeDev& M = merges[col_merge[job]];
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1;
@@ -656,12 +657,12 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
       for (int r = hi + tid; r < n; r += bs) dc[r] = 0.0;
     }
     int r = lo + tid;
-    for (; r + 3 * bs < hi; r += 4 * bs) {
-      const double x0 = sc[r], x1 = sc[r + bs], x2 = sc[r + 2 * bs], x3 = sc[r + 3 * bs];
-      dc[r] = x0;
-      dc[r + bs] = x1;
-      dc[r + 2 * bs] = x2;
-      dc[r + 3 * bs] = x3;
+    for (; r + (RU - 1) * bs < hi; r += RU * bs) {
+      double x[RU];
+#pragma unroll
+      for (int v = 0; v < RU; ++v) x[v] = sc[r + v * bs];
+#pragma unroll
+      for (int v = 0; v < RU; ++v) dc[r + v * bs] = x[v];
     }
     for (; r < hi; r += bs) dc[r] = sc[r];
     return;
@@ -704,27 +705,27 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
 #pragma unroll
       for (int u = 0; u < CHMAX; ++u) hj[u] = (u < L) && (fj[u] & bit) != 0;
       int r = r0 + tid;
-      for (; r + 3 * bs < r1; r += 4 * bs) {
-        double a[4];
+      for (; r + (RU - 1) * bs < r1; r += RU * bs) {
+        double a[RU];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) a[v] = ha ? sa[r + v * bs] : 0.0;
+        for (int v = 0; v < RU; ++v) a[v] = ha ? sa[r + v * bs] : 0.0;
 #pragma unroll
         for (int u = 0; u < CHMAX; ++u) {
           if (u < L) {
             const double* __restrict__ su = sj[u];
             double* __restrict__ du = di[u];
-            double b[4];
+            double b[RU];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) b[v] = hj[u] ? su[r + v * bs] : 0.0;
+            for (int v = 0; v < RU; ++v) b[v] = hj[u] ? su[r + v * bs] : 0.0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < RU; ++v) {
               du[r + v * bs] = cs[u] * a[v] + sn[u] * b[v];
               a[v] = -sn[u] * a[v] + cs[u] * b[v];
             }
           }
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dlast[r + v * bs] = a[v];
+        for (int v = 0; v < RU; ++v) dlast[r + v * bs] = a[v];
       }
       for (; r < r1; r += bs) {
         double a = ha ? sa[r] : 0.0;
