@@ -34,25 +34,26 @@ sys.path.insert(0, ROOT)
 
 # HBM traffic per launch from rocprofv3 counter passes (FETCH_SIZE, then
 # WRITE_SIZE, each in its own run over `--mode hss --steps 1 --warmup 0
-# --no-cpu --no-validate --no-batched`), scaled by what the same counters
+# --no-cpu --no-validate --no-batched --no-extra`, and the same with
+# `--mode dense --dense-steps 1 --dense-warmup 0`), scaled by what the same counters
 # read for a 1 GiB device copy (`--calibrate-copy`: FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  A record holds only while the sources that define the
 # kernel and its launches are unchanged (first 16 hex digits of their
 # SHA-256); otherwise the traffic is reported as null.
 TRAFFIC = {
-    "k_gemm_f64_n64": {"bytes_per_launch": 719.6e6,
-                       "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "7278b19ea3154e7e"}},
-    "k_gemm_f64": {"bytes_per_launch": 2045.1e6,
-                   "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "7278b19ea3154e7e"}},
-    "k_gemm_f64_n96": {"bytes_per_launch": 273.8e6,
-                       "sources": {"gemm.hip": "87b930b274babbc4", "hss.hip": "7278b19ea3154e7e"}},
-    "k_pack_rot": {"bytes_per_launch": 2301.7e6,
-                   "sources": {"merge.hip": "1f400c597a1f5ad8", "dc.hip": "469bfa54635284c3"}},
+    "k_gemm_f64": {"bytes_per_launch": 1657.5e6,
+                   "sources": {"gemm.hip": "9610f870382e35e7", "hss.hip": "a4937ee8bbf0ad9a"}},
+    "k_gemm_f64_n64": {"bytes_per_launch": 841.0e6,
+                       "sources": {"gemm.hip": "9610f870382e35e7", "hss.hip": "a4937ee8bbf0ad9a"}},
+    "k_gemm_f64_n96": {"bytes_per_launch": 356.2e6,
+                       "sources": {"gemm.hip": "9610f870382e35e7", "hss.hip": "a4937ee8bbf0ad9a"}},
+    "k_pack_rot": {"bytes_per_launch": 2302.9e6,
+                   "sources": {"merge.hip": "f2b55955ab0de7a1", "dc.hip": "a5fcdd6c937bbfbc"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 35894.9e6,
-                       "sources": {"gemm.hip": "87b930b274babbc4", "dc.hip": "469bfa54635284c3"}},
+    "k_gemm_f64_big": {"bytes_per_launch": 29035.4e6,
+                       "sources": {"gemm.hip": "9610f870382e35e7", "dc.hip": "a5fcdd6c937bbfbc"}},
 }
 
 
