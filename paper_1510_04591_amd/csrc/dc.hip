@@ -527,7 +527,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     // the packed operand.
     auto pack = [&](hipStream_t sp) {
       c->ktimer.pre(sp);
-      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)std::min(njob, 4 * c->num_cu)), dim3(256), 0, sp, d_m, d_cm,
+      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)std::min(njob, 2 * c->num_cu)), dim3(256), 0, sp, d_m, d_cm,
                          d_cc, B, njob);
       c->ktimer.post(sp, KT_PACK, 0.0, pack_by);
       if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, sp, d_m, d_tm, d_tc, B, ncols, 1);

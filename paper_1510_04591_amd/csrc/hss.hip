@@ -1161,20 +1161,24 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     hb.ms.push_back(std::move(m));
   }
   hb.fmm_p = o.sample_mode == ADC_SAMPLE_FMM ? o.fmm_order : 0;
-  // Once the first sampling pass is queued: the caller's work for the side
-  // stream (packing, dense merges), then the first check's probes (W and
-  // W^T Q', which read only the generators) on the same stream, so that they
-  // overlap the compression; the main stream waits for them (ev_probe)
-  // before the products that read W.
+  // Once the first sampling pass is queued: on the side stream, the first
+  // check's probes (W and W^T Q', which read only the generators), then the
+  // caller's work (packing, dense merges), all overlapping the compression;
+  // the main stream waits for the probes (ev_probe) before the products that
+  // read W, and for the packing before those that read the packed operand.
+  // The probes go first: they are short, and the main stream's wait for
+  // them then ends before the packing does.
   CheckBufs cb;
   std::vector<ApplyJob> aj0;
   bool probes_queued = false;
   adc_status probe_st = ADC_OK;
   hb.after_sampling = [&]() {
+    if (c->side && c->ev_probe && c->ev_fork && hipEventRecord(c->ev_fork, st) == hipSuccess &&
+        hipStreamWaitEvent(c->side, c->ev_fork, 0) == hipSuccess) {
+      probe_st = check_prepare(c, hb, o, cb, aj0, c->side);
+      if (probe_st == ADC_OK && hipEventRecord(c->ev_probe, c->side) == hipSuccess) probes_queued = true;
+    }
     if (after_sampling) after_sampling();
-    if (!c->side || !c->ev_probe) return;
-    probe_st = check_prepare(c, hb, o, cb, aj0, c->side);
-    if (probe_st == ADC_OK && hipEventRecord(c->ev_probe, c->side) == hipSuccess) probes_queued = true;
   };
   // First attempt.  Its accuracy check shares the launches of the update
   // product: the probe products W H and the products of the packed operand

@@ -757,8 +757,9 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
 }
 
 // Jobs strided over the grid: with fewer workgroups than jobs the packing
-// leaves room on every CU for a kernel that needs a whole CU's LDS (the node
-// compression, which runs beside the packing at HSS levels).
+// leaves room on the CUs for a kernel that needs a whole CU's LDS (the node
+// compression, which runs beside the packing at HSS levels; the solver
+// launches two workgroups per CU).
 __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
                                                   const int32_t* __restrict__ col_merge,
                                                   const int32_t* __restrict__ col_idx, LevelBufs B, int njob) {
