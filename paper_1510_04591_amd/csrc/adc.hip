@@ -224,7 +224,7 @@ adc_status adc_ctx_s::upload(void* dst, const void* src, size_t bytes) {
       if (host_up) hipHostFree(host_up);
       host_up = nullptr;
       host_up_bytes = 0;
-      const size_t want = std::max(need, (size_t)(4 << 20));
+      const size_t want = std::max(need, (size_t)(16 << 20));
       if (hipHostMalloc((void**)&host_up, want, hipHostMallocDefault) != hipSuccess) return ADC_ERR_NOMEM;
       host_up_bytes = want;
     }
@@ -392,7 +392,7 @@ extern "C" adc_status adc_cauchy_gemm(adc_ctx c, int64_t P, int64_t K, const dou
   HIP_OK(hipMemcpyAsync(dtm, tm.data(), tm.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_OK(hipMemcpyAsync(dtc, tc.data(), tc.size() * 4, hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(k_cauchy, dim3((unsigned)tm.size()), dim3(256), 0, c->stream, dm, dtm, dtc, B, ncols, 0);
-  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, dg, 1);
+  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, dg, 1, (const int*)nullptr);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(c->stream));
   return ADC_OK;
@@ -464,7 +464,8 @@ extern "C" adc_status adc_cauchy_gemm_noalloc(adc_ctx c, int64_t P, int64_t K, c
   hipLaunchKernelGGL(k_cauchy, dim3((unsigned)ntile), dim3(256), 0, c->stream, (const MergeDev*)dm, dtm, dtc, B, 8,
                      0);
   const int tiles = (int)((P + 255) / 256) * (int)((K + 127) / 128);
-  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, (const GemmProb*)dg, 1);
+  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, c->stream, (const GemmProb*)dg, 1,
+                     (const int*)nullptr);
   HIP_OK(hipGetLastError());
   return ADC_OK;
 }

@@ -30,44 +30,54 @@ struct MlpState;
 
 // Phase timing with HIP events on the context stream: start() opens an
 // interval, mark(p) closes it as phase p and opens the next; collect() (after
-// a stream synchronisation) adds the closed intervals to the report.
+// a stream synchronisation) adds the closed intervals to the report.  A
+// start() before the previous intervals were collected keeps them: the time
+// from their last mark to the new start is not attributed to any phase.
 struct PhaseTimer {
-  static constexpr int NEV = 24;
-  hipEvent_t ev[NEV] = {};
-  int phase[NEV] = {};
-  int n = 0;
-  bool ready = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  size_t n = 0;
   bool on = false;
-  void start(hipStream_t s, bool enable) {
-    on = enable;
-    n = 0;
-    if (!on) return;
-    if (!ready) {
-      for (int i = 0; i < NEV; ++i) hipEventCreate(&ev[i]);
-      ready = true;
+  void record(hipStream_t s, int p) {
+    if (n == ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      ev.push_back(e);
+      phase.push_back(-1);
     }
-    hipEventRecord(ev[0], s);
-    n = 1;
-  }
-  void mark(hipStream_t s, int p) {
-    if (!on || n >= NEV) return;
     hipEventRecord(ev[n], s);
     phase[n] = p;
     ++n;
   }
-  void collect(adc_report* rep) {
-    if (!on || !rep) return;
-    for (int i = 1; i < n; ++i) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) == hipSuccess && phase[i] >= 0)
-        rep->t_phase[phase[i]] += 1e-3 * ms;
+  void reset() { n = 0; }
+  void start(hipStream_t s, bool enable) {
+    on = enable;
+    if (!on) {
+      n = 0;
+      return;
     }
+    record(s, -1);
+  }
+  void mark(hipStream_t s, int p) {
+    if (on) record(s, p);
+  }
+  void collect(adc_report* rep) {
+    if (on && rep)
+      for (size_t i = 1; i < n; ++i) {
+        float ms = 0.f;
+        if (phase[i] >= 0 && hipEventElapsedTime(&ms, ev[i - 1], ev[i]) == hipSuccess)
+          rep->t_phase[phase[i]] += 1e-3 * ms;
+      }
     n = 0;
   }
   void destroy() {
-    if (ready)
-      for (int i = 0; i < NEV; ++i) hipEventDestroy(ev[i]);
-    ready = false;
+    for (auto e : ev) hipEventDestroy(e);
+    ev.clear();
+    phase.clear();
+    n = 0;
   }
 };
 
@@ -116,6 +126,14 @@ struct KernTimer {
     kid.push_back(k);
     fl.push_back(flops);
     by.push_back(bytes);
+  }
+  // index of the last recorded launch, and its work figures set afterwards
+  // (launches sized on the device, whose work is known once read back)
+  size_t last() const { return kid.empty() ? 0 : kid.size() - 1; }
+  void set_work(size_t i, double flops, double bytes) {
+    if (!on || i >= kid.size()) return;
+    fl[i] = flops;
+    by[i] = bytes;
   }
   // the stream must have been synchronised
   void collect(adc_report* rep) {

@@ -29,6 +29,40 @@
 #include "adc_internal.hpp"
 #include "hss.hpp"
 
+// The two block products of each merge's dense update (rows of the first
+// child against survivors of rows top-only and both, rows of the second
+// child against both and bottom-only), from the deflation results.  tile0
+// and tiles_m were set by the host for the worst case N = n.  One to three
+// arrays (one per tile class); a null array is skipped.
+__global__ void k_build_probs(const MergeDev* __restrict__ ms, int nm, GemmProb* __restrict__ pa,
+                              GemmProb* __restrict__ pb, GemmProb* __restrict__ pc, const double* __restrict__ pk,
+                              const double* __restrict__ qc, const double* __restrict__ v,
+                              const int32_t* __restrict__ posR) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nm) return;
+  const MergeDev& M = ms[g];
+  for (int which = 0; which < 3; ++which) {
+    GemmProb* arr = (which == 0) ? pa : (which == 1) ? pb : pc;
+    if (!arr) continue;
+    for (int half = 0; half < 2; ++half) {
+      GemmProb& P = arr[2 * g + half];
+      P.N = M.K;
+      P.K = half ? (M.k2 + M.k3) : (M.k1 + M.k2);
+      P.K2 = 0;
+      P.A = pk + M.zoff + (half ? (M.n1 + (int64_t)M.k1 * M.n) : 0);
+      P.lda = M.n;
+      P.B = qc + M.zoff + (half ? M.k1 : 0);
+      P.ldb = (M.K > 0) ? M.K : 1;
+      P.C = M.zn + (half ? M.n1 : 0);
+      P.ldc = M.ldn;
+      P.colmap = posR + M.s0;
+      P.vscale = v + M.s0;
+      P.beta = 0.0;
+      P.transB = 0;
+    }
+  }
+}
+
 namespace {
 
 // concatenate the inputs: din = [diag_0, diag_1, ...], offg likewise with a
@@ -56,38 +90,6 @@ __global__ void k_scatter_w(int count, const double* __restrict__ wg, double* co
   for (int64_t r = threadIdx.x; r < n; r += blockDim.x) o[r] = wg[base + r];
 }
 
-// The two block products of each merge's dense update (rows of the first
-// child against survivors of rows top-only and both, rows of the second
-// child against both and bottom-only), from the deflation results.  tile0
-// and tiles_m were set by the host for the worst case N = n.
-__global__ void k_build_probs(const MergeDev* __restrict__ ms, int nm, GemmProb* __restrict__ pa,
-                              GemmProb* __restrict__ pb, GemmProb* __restrict__ pc, const double* __restrict__ pk,
-                              const double* __restrict__ qc, const double* __restrict__ v,
-                              const int32_t* __restrict__ posR) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nm) return;
-  const MergeDev& M = ms[g];
-  for (int which = 0; which < 3; ++which) {
-    GemmProb* arr = (which == 0) ? pa : (which == 1) ? pb : pc;
-    for (int half = 0; half < 2; ++half) {
-      GemmProb& P = arr[2 * g + half];
-      P.N = M.K;
-      P.K = half ? (M.k2 + M.k3) : (M.k1 + M.k2);
-      P.K2 = 0;
-      P.A = pk + M.zoff + (half ? (M.n1 + (int64_t)M.k1 * M.n) : 0);
-      P.lda = M.n;
-      P.B = qc + M.zoff + (half ? M.k1 : 0);
-      P.ldb = (M.K > 0) ? M.K : 1;
-      P.C = M.zn + (half ? M.n1 : 0);
-      P.ldc = M.ldn;
-      P.colmap = posR + M.s0;
-      P.vscale = v + M.s0;
-      P.beta = 0.0;
-      P.transB = 0;
-    }
-  }
-}
-
 struct Node {
   int64_t s0;
   int32_t n;
@@ -96,7 +98,7 @@ struct Node {
 
 struct BLevel {
   int nm = 0, nmax = 0;
-  size_t o_m = 0, o_rb = 0, o_ob = 0, o_cm = 0, o_cc = 0, o_tm = 0, o_tc = 0, o_ga = 0, o_gb = 0, o_gc = 0;
+  size_t o_m = 0, o_rb = 0, o_ob = 0, o_cm = 0, o_cc = 0, o_tm = 0, o_tc = 0, o_ga = 0, o_gb = 0, o_gc = 0, o_gt = 0;
   int nrb = 0, nob = 0, njob = 0, ntile = 0, tiles[3] = {0, 0, 0};
   int W = 1;      // waves per secular / Loewner block
   int gv = 0;     // GEMM tile shape: 0 128x128, 1 128x64, 2 256x128
@@ -265,6 +267,7 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
     L.o_ga = dtake(2 * (size_t)L.nm * sizeof(GemmProb));
     L.o_gb = dtake(2 * (size_t)L.nm * sizeof(GemmProb));
     L.o_gc = dtake(2 * (size_t)L.nm * sizeof(GemmProb));
+    L.o_gt = dtake(sizeof(int));  // working tiles of the wide-tile problems (k_gemm_compact)
   }
   const size_t o_desc = take(doff);
   e->dev_bytes = off;
@@ -449,7 +452,7 @@ void launch_gemm(BEntry* e, const BLevel& L, int gv, hipStream_t st) {
                        2 * L.nm);
   else
     hipLaunchKernelGGL(k_gemm_f64_big, dim3(L.tiles[2]), dim3(1024), 0, st, (const GemmProb*)(e->desc + L.o_gc),
-                       2 * L.nm);
+                       2 * L.nm, (const int*)(e->desc + L.o_gt));
 }
 
 // The whole device sequence.  With tune, every level times its candidate
@@ -550,6 +553,8 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
     hipLaunchKernelGGL(k_build_probs, dim3((L.nm + 63) / 64), dim3(64), 0, st, dm, L.nm,
                        (GemmProb*)(d + L.o_ga), (GemmProb*)(d + L.o_gb), (GemmProb*)(d + L.o_gc), e->pk, e->qc,
                        e->v, e->posR);
+    hipLaunchKernelGGL(k_gemm_compact, dim3(1), dim3(1024), 0, st, (GemmProb*)(d + L.o_gc), 2 * L.nm, 128,
+                       (int*)(d + L.o_gt));
     if (tune_here) {
       // every tile shape writes the same values (same summation order)
       float best = 1e30f;

@@ -44,7 +44,42 @@ __global__ void k_tear(const double* __restrict__ diag, const double* __restrict
   a[i] = x;
 }
 
+// Counts of one level sequenced on the device, for the report: [0]
+// survivors, [1] dense-update flops, [2] its operand bytes, [3] packing
+// bytes, [4] merges with survivors.  One workgroup, fixed summation order.
+__global__ void __launch_bounds__(256) k_level_stats(const MergeDev* __restrict__ ms, int nm,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[5][256];
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < nm; g += 256) {
+    const MergeDev& M = ms[g];
+    const double n1 = M.n1, n2 = M.n - M.n1, K = M.K;
+    a[0] += K;
+    if (M.K > 0) {
+      for (int half = 0; half < 2; ++half) {
+        const double rows = half ? n2 : n1;
+        const double kk = half ? (double)(M.k2 + M.k3) : (double)(M.k1 + M.k2);
+        a[1] += 2.0 * rows * K * kk;
+        a[2] += 8.0 * (rows * kk + kk * K + rows * K);
+      }
+      a[4] += 1.0;
+    }
+    a[3] += 8.0 * (2.0 * ((double)M.k1 * n1 + (double)M.k2 * M.n + (double)M.k3 * n2) +
+                   (double)(M.n - M.K) * (0.5 * M.n + M.n));
+  }
+  for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = a[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
 namespace {
+
+constexpr int LSTAT = 8;  // doubles of per-level counts
 
 struct Node {
   int64_t s0;
@@ -97,6 +132,7 @@ struct WsLayout {
   int32_t *pidx, *ginv, *rot_i_of, *rot_j_of, *lcnt;
   double *pk, *qc;
   int* noconv;
+  double* lstat;  // per-level counts of the levels sequenced on the device
   size_t bytes;
 };
 
@@ -133,6 +169,7 @@ WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
   L.rot_j_of = ar.take<int32_t>(N);
   L.lcnt = ar.take<int32_t>(N);
   L.noconv = ar.take<int>(64);
+  L.lstat = ar.take<double>(64 * LSTAT);
   L.Zb = need_zb ? ar.take<double>((size_t)N * N) : nullptr;
   L.pk = ar.take<double>((size_t)N * N);
   L.qc = ar.take<double>((size_t)N * N);
@@ -180,7 +217,7 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
   // columns' unsupported halves zeroed, since this product reads all n rows
   hipLaunchKernelGGL(k_zero_unsupported, dim3((unsigned)M.K), dim3(256), 0, st, d_m, g, B);
   hipLaunchKernelGGL(k_cauchy, dim3((unsigned)nt), dim3(256), 0, st, d_m, dtm, dtc, B, ncols, 1);
-  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, st, dg, 1);
+  hipLaunchKernelGGL(k_gemm_f64_big, dim3(tiles), dim3(1024), 0, st, dg, 1, (const int*)nullptr);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(st));
   if (flops) *flops += 2.0 * P.M * (double)P.N * P.K;
@@ -244,13 +281,17 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
                             (size_t)n * 8 + 2 * ((size_t)n / 8 + max_merges + 8) * 4 + 32 * 256 +
                             12 * ((size_t)n / 8 + 2 * max_merges) + 256 * (max_merges + 4);
   char* hs;
-  ADC_TRY(c->stage(desc_bytes * 2, (void**)&hs));
+  const size_t lstat_off = (desc_bytes * 2 + 255) & ~(size_t)255;
+  ADC_TRY(c->stage(lstat_off + 64 * LSTAT * 8, (void**)&hs));
+  double* h_lstat = (double*)(hs + lstat_off);
   char* dd;
   ADC_TRY(c->buffer(SLOT_DESC, desc_bytes, (void**)&dd));
 
   // --- tear all splits and solve the leaves
+  std::vector<char> img;
   {
-    Arena ha{hs, 0, 0}, da{dd, 0, 0};
+    img.assign(desc_bytes, 0);
+    Arena ha{img.data(), 0, 0}, da{dd, 0, 0};
     int64_t* h_sp = ha.take<int64_t>(plan.splits.size() + 1);
     int64_t* d_sp = da.take<int64_t>(plan.splits.size() + 1);
     int64_t* h_ls = ha.take<int64_t>(nleaf);
@@ -275,8 +316,10 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     std::memcpy(h_lm + n0, lm[1].data(), lm[1].size() * 4);
     for (size_t i = 0; i < n0; ++i) h_lo[i] = LeafOut{Z + ls[0][i] + ls[0][i] * ldz, ldz};
     for (size_t i = 0; i < ls[1].size(); ++i) h_lo[n0 + i] = LeafOut{L.Zb + ls[1][i] + ls[1][i] * n, n};
-    HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
+    if (ha.off > desc_bytes) return ADC_ERR_UNSUPPORTED;
+    ADC_TRY(c->upload(dd, img.data(), ha.off));
     c->ktimer.begin(rep != nullptr);
+    c->timer.reset();
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_tear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag, offdiag, d_sp,
                        (int)plan.splits.size(), L.a, n);
@@ -286,13 +329,62 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     HIP_OK(hipGetLastError());
     c->timer.mark(st, 0);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, L.noconv, INT32_MAX);
-    HIP_OK(hipStreamSynchronize(st));  // staging buffer is reused below
-    c->timer.collect(rep);
-    c->ktimer.collect(rep);
   }
 
   if (rep) rep->levels = nlev;
   double flops = 0.0, bytes = 0.0;
+
+  // A level on which no merge can take the HSS route (every merge below
+  // hss_min_k, or its dense update below hss_min_flops even with no
+  // deflation, or HSS not allowed at that depth) is sequenced on the device
+  // alone, as the batched solver does: every launch is sized for the worst
+  // case K = n (the kernels read K from the merge descriptors and skip the
+  // blocks beyond it), the dense products are filled in on the device, and
+  // the level's counts stay in device memory until the next synchronisation.
+  auto hss_possible = [&](int t) {
+    if (o.force_dense || (o.hss_levels >= 0 && t >= o.hss_levels)) return false;
+    const int min_k = std::max(o.hss_min_k, 8);
+    for (const Node& nd : plan.merge_levels[t]) {
+      const double nn = nd.n;
+      // the dense update costs at most 2 K^2 n <= 2 n^3 flops
+      if (nd.n >= min_k && 2.0 * nn * nn * nn >= o.hss_min_flops) return true;
+    }
+    return false;
+  };
+  struct Pending {
+    int t, nm;
+    int64_t nsum;
+    size_t k_pack, k_gemm;
+  };
+  std::vector<Pending> pend;
+  // before a synchronisation: queue the copy of the pending levels' counts
+  auto fetch_pending = [&]() -> adc_status {
+    if (!pend.empty())
+      HIP_OK(hipMemcpyAsync(h_lstat, L.lstat, 64 * LSTAT * 8, hipMemcpyDeviceToHost, st));
+    return ADC_OK;
+  };
+  // after it: the counts into the report and the kernel timings
+  auto resolve_pending = [&]() {
+    for (const Pending& p : pend) {
+      const double* v = h_lstat + (size_t)(p.t % 64) * LSTAT;
+      flops += v[1];
+      bytes += v[2];
+      c->ktimer.set_work(p.k_pack, 0.0, v[3]);
+      c->ktimer.set_work(p.k_gemm, v[1], v[2]);
+      if (rep) {
+        rep->phase_flops[4] += v[1];
+        rep->phase_bytes[4] += v[2];
+        if (v[4] > 0.0) rep->phase_launches[4] += 1;
+        if (p.t < 64) {
+          rep->n_per_level[p.t] = p.nsum;
+          rep->K_per_level[p.t] = (int64_t)v[0];
+          rep->hss_per_level[p.t] = 0;
+        }
+        rep->merges += p.nm;
+      }
+    }
+    pend.clear();
+  };
 
   // --- merge levels, deepest first
   for (int t = nlev - 1; t >= 0; --t) {
@@ -336,6 +428,121 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     B.rot_j_of = L.rot_j_of;
     B.lcnt = L.lcnt;
 
+    if (!hss_possible(t) && t < 64) {
+      // descriptors fixed by the tree alone, in one upload
+      int nob = 0, nrb = 0, njob = 0, ntile = 0, gtiles = 0;
+      int32_t nmax = 0;
+      int64_t nsum = 0;
+      for (const Node& nd : lev) {
+        nob += (nd.n + 255) / 256;
+        nrb += (nd.n + 63) / 64;
+        njob += nd.n;
+        ntile += (nd.n + 7) / 8;
+        nmax = std::max(nmax, nd.n);
+        nsum += nd.n;
+      }
+      size_t off = 0;
+      auto take = [&](size_t b) {
+        const size_t r = off;
+        off += (b + 255) & ~(size_t)255;
+        return r;
+      };
+      const size_t om = take(nm * sizeof(MergeDev)), oob = take(nob * sizeof(RootBlock)),
+                   orb = take(nrb * sizeof(RootBlock)), ocm = take((size_t)njob * 4), occ = take((size_t)njob * 4),
+                   otm = take((size_t)ntile * 4), otc = take((size_t)ntile * 4),
+                   ogp = take(2 * (size_t)nm * sizeof(GemmProb)), ogt = take(sizeof(int));
+      if (off > desc_bytes) return ADC_ERR_UNSUPPORTED;  // descriptor space sized too small
+      img.assign(off, 0);
+      char* h = img.data();
+      MergeDev* hm = (MergeDev*)(h + om);
+      RootBlock* hob = (RootBlock*)(h + oob);
+      RootBlock* hrb = (RootBlock*)(h + orb);
+      int32_t* hcm = (int32_t*)(h + ocm);
+      int32_t* hcc = (int32_t*)(h + occ);
+      int32_t* htm = (int32_t*)(h + otm);
+      int32_t* htc = (int32_t*)(h + otc);
+      GemmProb* hgp = (GemmProb*)(h + ogp);
+      int iob = 0, irb = 0, ij = 0, it = 0;
+      for (int g2 = 0; g2 < nm; ++g2) {
+        MergeDev& M = hm[g2];
+        M.s0 = lev[g2].s0;
+        M.gbase = lev[g2].s0;
+        M.n = lev[g2].n;
+        M.n1 = lev[g2].n / 2;
+        M.zo = Zold + M.s0 + M.s0 * ldo;
+        M.zn = Znew + M.s0 + M.s0 * ldn;
+        M.ldo = ldo;
+        M.ldn = ldn;
+        M.zoff = M.s0 * (int64_t)nmax;
+        M.mode = 0;
+        for (int i0 = 0; i0 < M.n; i0 += 256) hob[iob++] = RootBlock{g2, i0};
+        for (int i0 = 0; i0 < M.n; i0 += 64) hrb[irb++] = RootBlock{g2, i0};
+        for (int c2 = 0; c2 < M.n; ++c2) {
+          hcm[ij] = g2;
+          hcc[ij] = c2;
+          ++ij;
+        }
+        for (int j0 = 0; j0 < M.n; j0 += 8) {
+          htm[it] = g2;
+          htc[it] = j0;
+          ++it;
+        }
+        const int rows[2] = {M.n1, M.n - M.n1};
+        for (int half = 0; half < 2; ++half) {
+          GemmProb& P = hgp[2 * g2 + half];
+          P.M = rows[half];
+          P.tiles_m = (rows[half] + 255) / 256;
+          P.tile0 = gtiles;
+          gtiles += P.tiles_m * ((M.n + 127) / 128);
+        }
+      }
+      ADC_TRY(c->upload(dd, h, off));
+      MergeDev* d_m = (MergeDev*)(dd + om);
+      const RootBlock* d_ob = (const RootBlock*)(dd + oob);
+      const RootBlock* d_rb = (const RootBlock*)(dd + orb);
+      const int32_t* d_cm = (const int32_t*)(dd + ocm);
+      const int32_t* d_cc = (const int32_t*)(dd + occ);
+      const int32_t* d_tm = (const int32_t*)(dd + otm);
+      const int32_t* d_tc = (const int32_t*)(dd + otc);
+      GemmProb* d_gp = (GemmProb*)(dd + ogp);
+      int* d_gt = (int*)(dd + ogt);
+      const int W = pick_waves(nmax);
+      HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      c->timer.start(st, rep != nullptr);
+      hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);
+      hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
+      hipLaunchKernelGGL(k_level_stats, dim3(1), dim3(256), 0, st, d_m, nm, L.lstat + (size_t)t * LSTAT);
+      c->timer.mark(st, 1);
+      c->ktimer.pre(st);
+      hipLaunchKernelGGL(k_secular, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.lam, L.gam, L.mu,
+                         o.max_iter, L.noconv);
+      c->ktimer.post(st, KT_SECULAR, 0.0, 0.0);
+      c->timer.mark(st, 2);
+      hipLaunchKernelGGL(k_lowner, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.gam, L.mu, L.uh);
+      hipLaunchKernelGGL(k_vnorm, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.gam, L.mu, L.uh, L.v);
+      c->timer.mark(st, 3);
+      hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
+      Pending p{t, nm, nsum, 0, 0};
+      c->ktimer.pre(st);
+      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)std::min(njob, 2 * c->num_cu)), dim3(256), 0, st, d_m, d_cm,
+                         d_cc, B, njob);
+      c->ktimer.post(st, KT_PACK, 0.0, 0.0);
+      p.k_pack = c->ktimer.last();
+      hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, 8, 1);
+      hipLaunchKernelGGL(k_build_probs, dim3((nm + 63) / 64), dim3(64), 0, st, d_m, nm, d_gp, (GemmProb*)nullptr,
+                         (GemmProb*)nullptr, L.pk, L.qc, L.v, L.posR);
+      hipLaunchKernelGGL(k_gemm_compact, dim3(1), dim3(1024), 0, st, d_gp, 2 * nm, 128, d_gt);
+      c->timer.mark(st, 9);
+      c->ktimer.pre(st);
+      hipLaunchKernelGGL(k_gemm_f64_big, dim3(gtiles), dim3(1024), 0, st, d_gp, 2 * nm, (const int*)d_gt);
+      c->ktimer.post(st, KT_GEMMBIG, 0.0, 0.0);
+      p.k_gemm = c->ktimer.last();
+      c->timer.mark(st, 4);
+      HIP_OK(hipGetLastError());
+      pend.push_back(p);
+      continue;
+    }
+
     Arena ha{hs, 0, 0}, da{dd, 0, 0};
     MergeDev* h_m = ha.take<MergeDev>(nm);
     MergeDev* d_m = da.take<MergeDev>(nm);
@@ -369,7 +576,9 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     HIP_OK(hipGetLastError());
     c->timer.mark(st, 1);
     HIP_OK(hipMemcpyAsync(h_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));
+    ADC_TRY(fetch_pending());
     HIP_OK(hipStreamSynchronize(st));
+    resolve_pending();
     c->timer.collect(rep);
     c->ktimer.collect(rep);
 
@@ -535,7 +744,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     auto dense = [&](hipStream_t sp) {
       if (!gtiles) return;
       c->ktimer.pre(sp);
-      hipLaunchKernelGGL(k_gemm_f64_big, dim3(gtiles), dim3(1024), 0, sp, d_gp, ngp);
+      hipLaunchKernelGGL(k_gemm_f64_big, dim3(gtiles), dim3(1024), 0, sp, d_gp, ngp, (const int*)nullptr);
       c->ktimer.post(sp, KT_GEMMBIG, lvl_gf, lvl_gb);
     };
     if (!hss_here) {
@@ -580,7 +789,12 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
 
   int nc = INT32_MAX;
   HIP_OK(hipMemcpyAsync(&nc, L.noconv, sizeof(int), hipMemcpyDeviceToHost, st));
+  ADC_TRY(fetch_pending());
   HIP_OK(hipStreamSynchronize(st));
+  resolve_pending();
+  c->up_reset();
+  c->timer.collect(rep);
+  c->ktimer.collect(rep);
   c->ktimer.begin(false);
   if (rep) {
     rep->flops_model += flops;

@@ -326,9 +326,19 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int nblk) {
   return (x < rem) ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
+// ntiles (optional): the number of tiles that carry work, for a launch sized
+// for the worst case whose problems were compacted by k_gemm_compact; the
+// workgroups past it leave at once, and the XCD ranges cover only the
+// working tiles.
 template <int BM, int BN, int WM, int WN, bool PF2 = false, bool XCD_GROUPED = false>
-__device__ __forceinline__ void gemm_dispatch(const GemmProb* __restrict__ probs, int nprobs) {
-  const int bid = XCD_GROUPED ? xcd_contiguous((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+__device__ __forceinline__ void gemm_dispatch(const GemmProb* __restrict__ probs, int nprobs,
+                                              const int* __restrict__ ntiles = nullptr) {
+  int nblk = (int)gridDim.x;
+  if (ntiles) {
+    nblk = min(*ntiles, nblk);
+    if ((int)blockIdx.x >= nblk) return;
+  }
+  const int bid = XCD_GROUPED ? xcd_contiguous((int)blockIdx.x, nblk) : (int)blockIdx.x;
   const GemmProb P = probs[find_prob(probs, nprobs, bid)];
   const int local = bid - P.tile0;
   int mt, nt;
@@ -362,6 +372,37 @@ __global__ void __launch_bounds__(512) k_gemm_f64_n96(const GemmProb* __restrict
   gemm_dispatch<128, 96, 4, 2>(probs, nprobs);
 }
 
-__global__ void __launch_bounds__(1024) k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs) {
-  gemm_dispatch<256, 128, 4, 4, true, true>(probs, nprobs);
+__global__ void __launch_bounds__(1024) k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs,
+                                                      const int* __restrict__ ntiles) {
+  gemm_dispatch<256, 128, 4, 4, true, true>(probs, nprobs, ntiles);
+}
+
+// Tile offsets of a grouped product built on the device, made compact: each
+// problem's tile0 becomes the number of tiles (tiles_m x ceil(N / bn)) of
+// the problems before it at their actual sizes, and the total goes to
+// *ntiles.  One workgroup: a chunk of problems per lane, a scan of the chunk
+// sums in LDS.
+__global__ void __launch_bounds__(1024) k_gemm_compact(GemmProb* __restrict__ probs, int nprobs, int bn,
+                                                       int* __restrict__ ntiles) {
+  __shared__ int part[1024];
+  const int T = (int)blockDim.x, tid = (int)threadIdx.x;
+  const int per = (nprobs + T - 1) / T;
+  const int b = min(nprobs, tid * per), e = min(nprobs, b + per);
+  auto tiles = [&](const GemmProb& P) { return P.N > 0 ? P.tiles_m * ((P.N + bn - 1) / bn) : 0; };
+  int s = 0;
+  for (int i = b; i < e; ++i) s += tiles(probs[i]);
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;
+  for (int i = b; i < e; ++i) {
+    probs[i].tile0 = run;
+    run += tiles(probs[i]);
+  }
+  if (tid == T - 1) *ntiles = part[T - 1];
 }

@@ -89,7 +89,7 @@ struct HssBatch {
     std::vector<int> bounds;
     std::vector<HssNode> nodes;  // host copy
     HssMerge dev{};
-    int64_t node_off = 0, arena_off = 0, iarena_off = 0, vec_off = 0;
+    int64_t node_off = 0, map_off = 0, arena_off = 0, iarena_off = 0, vec_off = 0;
     int64_t arena_n = 0, iarena_n = 0;
     bool pass = false;
     double err = 0.0;
@@ -102,6 +102,7 @@ struct HssBatch {
   std::vector<One> ms;
   char* mem = nullptr;
   HssMerge* d_ms = nullptr;
+  int64_t nodes_end = 0, host_end = 0;  // ends of the node tables and of the host-written range in mem
   int fmm_p = 0;                   // Chebyshev points per node; 0: direct sampling
   std::function<void()> after_sampling;  // called once, after the first sampling pass is queued
   std::vector<char> sample_host;   // launch lists of the last sampling pass
@@ -167,11 +168,17 @@ static adc_status batch_alloc(adc_ctx c, HssBatch& hb, int slot) {
     return o;
   };
   const int nm = (int)hb.ms.size();
+  // what the host writes (merge table, node tables, leaf maps and bounds)
+  // first, in one range: one upload; the node tables in one range: one
+  // read-back of the ranks
+  for (auto& m : hb.ms) layout_merge(m);
   const int64_t off_ms = take(nm * sizeof(HssMerge));
+  for (auto& m : hb.ms) m.node_off = take((int64_t)m.nodes.size() * sizeof(HssNode));
+  hb.nodes_end = bytes;
+  for (auto& m : hb.ms) m.map_off = take((int64_t)m.K * 4 + ((int64_t)m.bounds.size()) * 4);
+  hb.host_end = bytes;
   for (auto& m : hb.ms) {
-    layout_merge(m);
-    m.vec_off = take((int64_t)3 * m.K * m.sp * 8 + (int64_t)m.K * 4 + ((int64_t)m.bounds.size()) * 4 + 64);
-    m.node_off = take((int64_t)m.nodes.size() * sizeof(HssNode));
+    m.vec_off = take((int64_t)3 * m.K * m.sp * 8);
     m.arena_off = take(m.arena_n * 8);
     m.iarena_off = take(m.iarena_n * 4);
   }
@@ -184,7 +191,7 @@ static adc_status batch_alloc(adc_ctx c, HssBatch& hb, int slot) {
     m.dev.omega = (double*)v;
     m.dev.phi = m.dev.omega + (int64_t)m.K * m.sp;
     m.dev.theta = m.dev.phi + (int64_t)m.K * m.sp;
-    int32_t* lo = (int32_t*)(m.dev.theta + (int64_t)m.K * m.sp);
+    int32_t* lo = (int32_t*)(hb.mem + m.map_off);
     m.dev.leafof = lo;
     m.dev.bounds = lo + m.K;
     m.dev.nodes = (HssNode*)(hb.mem + m.node_off);
@@ -199,20 +206,20 @@ static adc_status batch_alloc(adc_ctx c, HssBatch& hb, int slot) {
 }
 
 static adc_status batch_upload(adc_ctx c, HssBatch& hb) {
-  hipStream_t st = c->stream;
-  for (auto& m : hb.ms) {
-    std::vector<int32_t> lo(m.K);
+  // the host-written range of the batch memory, imaged and uploaded at once
+  std::vector<char> img((size_t)hb.host_end, 0);
+  char* h = img.data();
+  const int64_t off_ms = (char*)hb.d_ms - hb.mem;
+  for (size_t g = 0; g < hb.ms.size(); ++g) {
+    const auto& m = hb.ms[g];
+    std::memcpy(h + off_ms + g * sizeof(HssMerge), &m.dev, sizeof(HssMerge));
+    std::memcpy(h + m.node_off, m.nodes.data(), m.nodes.size() * sizeof(HssNode));
+    int32_t* lo = (int32_t*)(h + m.map_off);
     for (size_t t = 0; t + 1 < m.bounds.size(); ++t)
       for (int i = m.bounds[t]; i < m.bounds[t + 1]; ++i) lo[i] = (int32_t)t;
-    ADC_TRY(c->upload((void*)m.dev.leafof, lo.data(), m.K * 4));
-    ADC_TRY(c->upload((void*)m.dev.bounds, m.bounds.data(), m.bounds.size() * 4));
-    ADC_TRY(c->upload(m.dev.nodes, m.nodes.data(), m.nodes.size() * sizeof(HssNode)));
+    std::memcpy(lo + m.K, m.bounds.data(), m.bounds.size() * 4);
   }
-  std::vector<HssMerge> hm;
-  for (auto& m : hb.ms) hm.push_back(m.dev);
-  ADC_TRY(c->upload(hb.d_ms, hm.data(), hm.size() * sizeof(HssMerge)));
-  (void)st;
-  return ADC_OK;
+  return c->upload(hb.mem, h, img.size());
 }
 
 // Sampling and compression of every merge in the batch (omega already drawn).
@@ -464,22 +471,15 @@ static adc_status batch_construct(adc_ctx c, HssBatch& hb, adc_report* rep) {
     HIP_OK(hipGetLastError());
   }
   c->timer.mark(st, 6);
-  // ranks back to the host, through one pinned buffer
-  size_t nb = 0;
-  for (auto& m : hb.ms) nb += m.nodes.size() * sizeof(HssNode);
+  // ranks back to the host: the node tables of every merge in one copy
+  // through a pinned buffer
+  const int64_t n0 = hb.ms.empty() ? 0 : hb.ms[0].node_off;
   char* hp;
-  ADC_TRY(c->stage2(nb, (void**)&hp));
-  size_t ro = 0;
-  for (auto& m : hb.ms) {
-    HIP_OK(hipMemcpyAsync(hp + ro, m.dev.nodes, m.nodes.size() * sizeof(HssNode), hipMemcpyDeviceToHost, st));
-    ro += m.nodes.size() * sizeof(HssNode);
-  }
+  ADC_TRY(c->stage2((size_t)(hb.nodes_end - n0) + 256, (void**)&hp));
+  if (hb.nodes_end > n0)
+    HIP_OK(hipMemcpyAsync(hp, hb.mem + n0, (size_t)(hb.nodes_end - n0), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  ro = 0;
-  for (auto& m : hb.ms) {
-    std::memcpy(m.nodes.data(), hp + ro, m.nodes.size() * sizeof(HssNode));
-    ro += m.nodes.size() * sizeof(HssNode);
-  }
+  for (auto& m : hb.ms) std::memcpy(m.nodes.data(), hp + (m.node_off - n0), m.nodes.size() * sizeof(HssNode));
   (void)rep;
   for (auto& m : hb.ms) {
     m.max_rank = 0;
@@ -1106,45 +1106,55 @@ adc_status hss_level_update(adc_ctx c, const adc_opts& o, MergeDev* h_m, MergeDe
     if (h_m[g].mode == 1) which.push_back(g);
   if (which.empty()) return ADC_OK;
   // the host inputs of every merge (leaf bounds moved on the device, d, gam,
-  // mu, the column groups of every leaf of the packed operand) in one pinned
-  // buffer: all copies queued, one synchronisation
-  std::vector<size_t> hoff(which.size() + 1, 0);
-  for (size_t t = 0; t < which.size(); ++t) {
-    const MergeDev& M = h_m[which[t]];
+  // mu, the column groups of every leaf of the packed operand, the rank
+  // estimate) read back through one pinned buffer: each kind of array is
+  // copied once over the range that holds every merge's part, so that the
+  // number of copies does not grow with the number of merges
+  int64_t lo = INT64_MAX, hi = 0, lhi = 0;
+  const char *blo = nullptr, *bhi = nullptr;
+  for (int g : which) {
+    const MergeDev& M = h_m[g];
     const int L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
     if (M.nleaf != (1 << L) || !M.lbounds) return ADC_ERR_ARG;
-    const size_t b = 3 * (size_t)M.K * 8 + (size_t)(M.nleaf + 1) * 4 + 3 * (size_t)M.nleaf * 4 + 4;
-    hoff[t + 1] = hoff[t] + ((b + 255) & ~(size_t)255);
+    lo = std::min(lo, M.s0);
+    hi = std::max(hi, M.s0 + M.K);
+    lhi = std::max(lhi, M.s0 + 3 * (int64_t)M.nleaf);
+    const char* b0 = (const char*)M.lbounds;
+    const char* b1 = b0 + (size_t)(M.nleaf + 1) * 4;
+    blo = blo ? std::min(blo, b0) : b0;
+    bhi = bhi ? std::max(bhi, b1) : b1;
   }
+  const size_t nv = (size_t)(hi - lo), nl = (size_t)(lhi - lo), nbd = (size_t)(bhi - blo);
+  const size_t o_gam = ((nv * 8 + 255) & ~(size_t)255), o_mu = 2 * o_gam, o_l = 3 * o_gam;
+  const size_t o_b = o_l + ((nl * 4 + 255) & ~(size_t)255);
+  const size_t o_m = o_b + ((nbd + 255) & ~(size_t)255);
   char* hp;
-  ADC_TRY(c->stage2(hoff.back(), (void**)&hp));
-  for (size_t t = 0; t < which.size(); ++t) {
-    const MergeDev& M = h_m[which[t]];
-    char* q = hp + hoff[t];
-    HIP_OK(hipMemcpyAsync(q, B.dS + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(q + (size_t)M.K * 8, B.gam + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(q + 2 * (size_t)M.K * 8, B.mu + M.s0, M.K * 8, hipMemcpyDeviceToHost, st));
-    char* qi = q + 3 * (size_t)M.K * 8;
-    HIP_OK(hipMemcpyAsync(qi, M.lbounds, (M.nleaf + 1) * 4, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(qi + (M.nleaf + 1) * 4, B.lcnt + M.s0, 3 * (size_t)M.nleaf * 4, hipMemcpyDeviceToHost,
-                          st));
-    HIP_OK(hipMemcpyAsync(qi + (M.nleaf + 1) * 4 + 3 * (size_t)M.nleaf * 4, &d_m[which[t]].rest, 4,
-                          hipMemcpyDeviceToHost, st));
-  }
+  ADC_TRY(c->stage2(o_m + nm * sizeof(MergeDev), (void**)&hp));
+  HIP_OK(hipMemcpyAsync(hp, B.dS + lo, nv * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hp + o_gam, B.gam + lo, nv * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hp + o_mu, B.mu + lo, nv * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hp + o_l, B.lcnt + lo, nl * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hp + o_b, blo, nbd, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(hp + o_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   c->up_reset();  // every earlier upload on the stream has completed
+  const MergeDev* hm_dev = (const MergeDev*)(hp + o_m);
   for (size_t t = 0; t < which.size(); ++t) {
     const MergeDev& M = h_m[which[t]];
     HssBatch::One m;
     m.K = M.K;
     m.L = std::max(1, ceil_log2_ratio(M.K, o.hss_leaf));
-    const double* q = (const double*)(hp + hoff[t]);
-    const int32_t* qi = (const int32_t*)(q + 3 * (size_t)M.K);
-    m.bounds.assign(qi, qi + M.nleaf + 1);
-    m.grp.assign(qi + M.nleaf + 1, qi + M.nleaf + 1 + 3 * (size_t)M.nleaf);
+    const size_t e0 = (size_t)(M.s0 - lo);
+    const double* qd = (const double*)hp + e0;
+    const double* qg = (const double*)(hp + o_gam) + e0;
+    const double* qm = (const double*)(hp + o_mu) + e0;
+    const int32_t* ql = (const int32_t*)(hp + o_l) + e0;
+    const int32_t* qb = (const int32_t*)(hp + o_b + ((const char*)M.lbounds - blo));
+    m.bounds.assign(qb, qb + M.nleaf + 1);
+    m.grp.assign(ql, ql + 3 * (size_t)M.nleaf);
     m.stream = (uint32_t)((depth << 20) + which[t]);
-    std::vector<double> d(q, q + M.K), g2(q + M.K, q + 2 * (size_t)M.K), mu(q + 2 * (size_t)M.K, q + 3 * (size_t)M.K);
-    m.r = qi[M.nleaf + 1 + 3 * (size_t)M.nleaf];  // k_leaf_bounds: eq. (bounds) over the moved boundaries
+    std::vector<double> d(qd, qd + M.K), g2(qg, qg + M.K), mu(qm, qm + M.K);
+    m.r = hm_dev[which[t]].rest;  // k_leaf_bounds: eq. (bounds) over the moved boundaries
     if (o.rank_mode == ADC_RANK_FIXED) m.r = std::max(1, o.fixed_rank);
     if (o.rank_mode == ADC_RANK_MLP && !mlp_collecting(c))
       m.r = mlp_rank(c, B.dS + M.s0, B.gam + M.s0, B.mu + M.s0, M.K, m.bounds, o, m.r);

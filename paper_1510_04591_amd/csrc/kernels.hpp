@@ -140,7 +140,16 @@ __global__ void k_pack_rot(const MergeDev* __restrict__ merges, const int32_t* _
 __global__ void k_cauchy(const MergeDev* __restrict__ merges, const int32_t* __restrict__ tile_merge,
                          const int32_t* __restrict__ tile_col0, LevelBufs B, int ncols, int grouped);
 
+// The dense update's two block products per merge from its deflation results
+// (sizes, operand offsets); row counts and tile offsets are the host's, for
+// the worst case N = n.  pb and pc may be null.
+__global__ void k_build_probs(const MergeDev* __restrict__ ms, int nm, GemmProb* __restrict__ pa,
+                              GemmProb* __restrict__ pb, GemmProb* __restrict__ pc, const double* __restrict__ pk,
+                              const double* __restrict__ qc, const double* __restrict__ v,
+                              const int32_t* __restrict__ posR);
+
 __global__ void k_gemm_f64(const GemmProb* __restrict__ probs, int nprobs);
 __global__ void k_gemm_f64_n64(const GemmProb* __restrict__ probs, int nprobs);
 __global__ void k_gemm_f64_n96(const GemmProb* __restrict__ probs, int nprobs);
-__global__ void k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs);
+__global__ void k_gemm_f64_big(const GemmProb* __restrict__ probs, int nprobs, const int* __restrict__ ntiles);
+__global__ void k_gemm_compact(GemmProb* __restrict__ probs, int nprobs, int bn, int* __restrict__ ntiles);
