@@ -145,6 +145,15 @@ adc_status adc_ctx_s::side_stream() {
   return ADC_OK;
 }
 
+adc_status adc_ctx_s::meta_event(hipEvent_t* e) {
+  if (!ev_meta && hipEventCreateWithFlags(&ev_meta, hipEventDisableTiming) != hipSuccess) {
+    ev_meta = nullptr;
+    return ADC_ERR_HIP;
+  }
+  *e = ev_meta;
+  return ADC_OK;
+}
+
 void adc_ctx_s::release() {
   if (side) {
     hipStreamSynchronize(side);
@@ -154,7 +163,8 @@ void adc_ctx_s::release() {
   if (ev_fork) hipEventDestroy(ev_fork);
   if (ev_join) hipEventDestroy(ev_join);
   if (ev_probe) hipEventDestroy(ev_probe);
-  ev_fork = ev_join = ev_probe = nullptr;
+  if (ev_meta) hipEventDestroy(ev_meta);
+  ev_fork = ev_join = ev_probe = ev_meta = nullptr;
   for (auto& b : bufs) {
     if (b.ptr) hipFree(b.ptr);
     b.ptr = nullptr;

@@ -186,6 +186,10 @@ struct adc_ctx_s {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_probe = nullptr;
   adc_status side_stream();
+  // event after a level's merge descriptors are copied back (the host waits
+  // on it while the roots of the level are computed)
+  hipEvent_t ev_meta = nullptr;
+  adc_status meta_event(hipEvent_t* e);
   adc_status buffer(int slot, size_t bytes, void** p);
   adc_status stage(size_t bytes, void** p);
   adc_status stage2(size_t bytes, void** p);

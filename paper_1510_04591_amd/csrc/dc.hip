@@ -280,8 +280,13 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
                             3 * blocks64 * sizeof(RootBlock) + 2 * max_merges * sizeof(GemmProb) +
                             (size_t)n * 8 + 2 * ((size_t)n / 8 + max_merges + 8) * 4 + 32 * 256 +
                             12 * ((size_t)n / 8 + 2 * max_merges) + 256 * (max_merges + 4);
+  // pinned staging of the host-sequenced levels: one half per level parity
+  // (no synchronisation ends a level, so the copies queued from one level's
+  // half may still be pending while the next level fills the other half),
+  // then the per-level counts of the levels sequenced on the device
   char* hs;
-  const size_t lstat_off = (desc_bytes * 2 + 255) & ~(size_t)255;
+  const size_t desc_half = (desc_bytes + 255) & ~(size_t)255;
+  const size_t lstat_off = 2 * desc_half;
   ADC_TRY(c->stage(lstat_off + 64 * LSTAT * 8, (void**)&hs));
   double* h_lstat = (double*)(hs + lstat_off);
   char* dd;
@@ -543,15 +548,20 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       continue;
     }
 
-    Arena ha{hs, 0, 0}, da{dd, 0, 0};
+    Arena ha{hs + (size_t)(t & 1) * desc_half, 0, 0}, da{dd, 0, 0};
     MergeDev* h_m = ha.take<MergeDev>(nm);
     MergeDev* d_m = da.take<MergeDev>(nm);
     // blocks of 256 elements over every merge (the merged order, later the
-    // final order)
+    // final order) and of 64 roots for the secular solver, Loewner and v,
+    // for the worst case K = n: those launches are queued before the host
+    // reads the deflation results (their blocks past K exit)
     RootBlock* h_ob = ha.take<RootBlock>(blocks64);
     RootBlock* d_ob = da.take<RootBlock>(blocks64);
-    int nob = 0;
+    RootBlock* h_rb = ha.take<RootBlock>(blocks64);
+    RootBlock* d_rb = da.take<RootBlock>(blocks64);
+    int nob = 0, nrb = 0;
     int32_t nmax = 0;
+    for (int g2 = 0; g2 < nm; ++g2) nmax = std::max(nmax, lev[g2].n);
     for (int g2 = 0; g2 < nm; ++g2) {
       MergeDev& M = h_m[g2];
       std::memset(&M, 0, sizeof(M));
@@ -563,13 +573,15 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       M.zn = Znew + M.s0 + M.s0 * ldn;
       M.ldo = ldo;
       M.ldn = ldn;
-      nmax = std::max(nmax, M.n);
+      M.zoff = M.s0 * (int64_t)nmax;
     }
-    for (int g2 = 0; g2 < nm; ++g2)
+    for (int g2 = 0; g2 < nm; ++g2) {
       for (int i0 = 0; i0 < h_m[g2].n; i0 += 256) h_ob[nob++] = RootBlock{g2, i0};
+      for (int i0 = 0; i0 < h_m[g2].n; i0 += 64) h_rb[nrb++] = RootBlock{g2, i0};
+    }
+    const size_t first_bytes = ha.off;
     HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIP_OK(hipMemcpyAsync(d_m, h_m, nm * sizeof(MergeDev), hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(d_ob, h_ob, nob * sizeof(RootBlock), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(dd, ha.base, first_bytes, hipMemcpyHostToDevice, st));
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);
     hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
@@ -577,13 +589,27 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     c->timer.mark(st, 1);
     HIP_OK(hipMemcpyAsync(h_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));
     ADC_TRY(fetch_pending());
-    HIP_OK(hipStreamSynchronize(st));
+    hipEvent_t ev_meta;
+    ADC_TRY(c->meta_event(&ev_meta));
+    HIP_OK(hipEventRecord(ev_meta, st));
+
+    // --- secular, Loewner, v, final order: queued before the host waits
+    const int W = pick_waves(nmax);
+    c->ktimer.pre(st);
+    hipLaunchKernelGGL(k_secular, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.lam, L.gam, L.mu,
+                       o.max_iter, L.noconv);
+    c->ktimer.post(st, KT_SECULAR, 0.0, 0.0);
+    c->timer.mark(st, 2);
+    hipLaunchKernelGGL(k_lowner, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.gam, L.mu, L.uh);
+    hipLaunchKernelGGL(k_vnorm, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.gam, L.mu, L.uh, L.v);
+    c->timer.mark(st, 3);
+    hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventSynchronize(ev_meta));
     resolve_pending();
-    c->timer.collect(rep);
-    c->ktimer.collect(rep);
 
     // --- host decisions and launch lists
-    int64_t Kmax = 0, Ksum = 0, nsum = 0;
+    int64_t Ksum = 0, nsum = 0;
     int hss_here = 0;
     // HSS on a merge whose dense update reaches hss_min_flops; once the
     // level takes the HSS route, merges of a quarter of that join it, since
@@ -598,10 +624,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       level_hss |= level_ok && h_m[g2].K >= min_k && dense_flops(h_m[g2]) >= o.hss_min_flops;
     for (int g2 = 0; g2 < nm; ++g2) {
       MergeDev& M = h_m[g2];
-      M.zoff = M.s0 * (int64_t)nmax;
       M.mode = (level_hss && M.K >= min_k && dense_flops(M) >= 0.25 * o.hss_min_flops) ? 1 : 0;
       hss_here += M.mode == 1;
-      Kmax = std::max<int64_t>(Kmax, M.K);
       Ksum += M.K;
       nsum += M.n;
     }
@@ -629,11 +653,6 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     int32_t* h_lgm = ha.take<int32_t>(lg_merges.size() + 1);
     int32_t* d_lgm = da.take<int32_t>(lg_merges.size() + 1);
     std::copy(lg_merges.begin(), lg_merges.end(), h_lgm);
-    RootBlock* h_rb = ha.take<RootBlock>(blocks64);
-    RootBlock* d_rb = da.take<RootBlock>(blocks64);
-    int nrb = 0;
-    for (int g2 = 0; g2 < nm; ++g2)
-      for (int i0 = 0; i0 < h_m[g2].K; i0 += 64) h_rb[nrb++] = RootBlock{g2, i0};
     int32_t* h_cm = ha.take<int32_t>(n);
     int32_t* d_cm = da.take<int32_t>(n);
     int32_t* h_cc = ha.take<int32_t>(n);
@@ -697,22 +716,8 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     }
     if (rep && gtiles) rep->phase_launches[4] += 1;
     if (ha.off > desc_bytes) return ADC_ERR_UNSUPPORTED;  // descriptor space sized too small
-    HIP_OK(hipMemcpyAsync(dd, hs, ha.off, hipMemcpyHostToDevice, st));
-
-    // --- secular, Loewner, v
-    const int W = pick_waves(Kmax);
-    c->timer.start(st, rep != nullptr);
-    if (nrb) {
-      c->ktimer.pre(st);
-      hipLaunchKernelGGL(k_secular, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.lam, L.gam, L.mu,
-                         o.max_iter, L.noconv);
-      c->ktimer.post(st, KT_SECULAR, 0.0, 0.0);
-      c->timer.mark(st, 2);
-      hipLaunchKernelGGL(k_lowner, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.zS, L.gam, L.mu, L.uh);
-      hipLaunchKernelGGL(k_vnorm, dim3(nrb), dim3(64 * W), 0, st, d_m, d_rb, L.dS, L.gam, L.mu, L.uh, L.v);
-      c->timer.mark(st, 3);
-    }
-    hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
+    // the merge descriptors with the host's decisions, and the launch lists
+    HIP_OK(hipMemcpyAsync(dd, ha.base, ha.off, hipMemcpyHostToDevice, st));
     // packing: a survivor column reads and writes its support rows (top
     // half, bottom half or both), a deflated column reads its child's half
     // and writes all n rows of its final place
@@ -767,16 +772,12 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
         dense(c->side);
         hipEventRecord(c->ev_join, c->side);
       };
-      adc_status hs = hss_level_update(c, o, h_m, d_m, nm, B, t, rep, &flops, &bytes, fork, c->ev_join);
+      const adc_status hst = hss_level_update(c, o, h_m, d_m, nm, B, t, rep, &flops, &bytes, fork, c->ev_join);
       fork();                                         // when the update returned before sampling
       HIP_OK(hipStreamWaitEvent(st, c->ev_join, 0));  // joined even when the update failed
       HIP_OK(hipGetLastError());
-      ADC_TRY(hs);
+      ADC_TRY(hst);
     }
-    HIP_OK(hipStreamSynchronize(st));  // staging buffer reused by the next level
-    c->up_reset();
-    c->timer.collect(rep);
-    c->ktimer.collect(rep);
 
     if (rep && t < 64) {
       rep->n_per_level[t] = nsum;
