@@ -523,10 +523,37 @@ struct ProbArena {
     double flops, bytes;
   };
   std::vector<Launch> launches;  // in order of issue
+  size_t uploaded = 0, issued = 0;  // problems uploaded, launches issued
 };
 
-static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops, ProbArena& ar) {
-  if (probs.empty()) return ADC_OK;
+// Upload the problems staged since the last issue (one copy) and launch the
+// staged groups in order.
+static adc_status issue_probs(adc_ctx c, ProbArena& ar) {
+  hipStream_t st = c->stream;
+  if (ar.used > ar.uploaded)
+    ADC_TRY(c->upload(ar.d + ar.uploaded, ar.h + ar.uploaded, (ar.used - ar.uploaded) * sizeof(GemmProb)));
+  ar.uploaded = ar.used;
+  for (; ar.issued < ar.launches.size(); ++ar.issued) {
+    const auto& l = ar.launches[ar.issued];
+    const GemmProb* dp = ar.d + l.off;
+    c->ktimer.pre(st);
+    if (l.cls == 0)
+      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
+    else if (l.cls == 1)
+      hipLaunchKernelGGL(k_gemm_f64_n96, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
+    else
+      hipLaunchKernelGGL(k_gemm_f64, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
+    c->ktimer.post(st, l.cls == 0 ? KT_GEMM64 : l.cls == 1 ? KT_GEMM96 : KT_GEMM, l.flops, l.bytes);
+  }
+  HIP_OK(hipGetLastError());
+  return ADC_OK;
+}
+
+// Stage one group of independent products (split by tile width), issued at
+// once with now, else at the next issue_probs.
+static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* flops, ProbArena& ar,
+                               bool now) {
+  if (probs.empty()) return now ? issue_probs(c, ar) : ADC_OK;
   // tile width by the product width: 64, 96 or 128 columns
   std::vector<GemmProb> cls[3];
   double pf[3] = {0.0, 0.0, 0.0}, pb[3] = {0.0, 0.0, 0.0};
@@ -541,9 +568,7 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
     pb[w] += by;
     cls[w].push_back(p);
   }
-  hipStream_t st = c->stream;
   static const int BN[3] = {64, 96, 128};
-  const size_t first = ar.used, nl0 = ar.launches.size();
   for (int w = 0; w < 3; ++w) {
     auto& L = cls[w];
     if (L.empty()) continue;
@@ -559,23 +584,7 @@ static adc_status launch_probs(adc_ctx c, std::vector<GemmProb>& probs, double* 
     ar.launches.push_back(ProbArena::Launch{w, ar.used, (int)L.size(), tiles, pf[w], pb[w]});
     ar.used += L.size();
   }
-  // issued at once (the descriptors through the pinned upload arena, so the
-  // host goes on building the next level's lists while these run)
-  ADC_TRY(c->upload(ar.d + first, ar.h + first, (ar.used - first) * sizeof(GemmProb)));
-  for (size_t li = nl0; li < ar.launches.size(); ++li) {
-    const auto& l = ar.launches[li];
-    const GemmProb* dp = ar.d + l.off;
-    c->ktimer.pre(st);
-    if (l.cls == 0)
-      hipLaunchKernelGGL(k_gemm_f64_n64, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
-    else if (l.cls == 1)
-      hipLaunchKernelGGL(k_gemm_f64_n96, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
-    else
-      hipLaunchKernelGGL(k_gemm_f64, dim3(l.tiles), dim3(512), 0, st, dp, l.count);
-    c->ktimer.post(st, l.cls == 0 ? KT_GEMM64 : l.cls == 1 ? KT_GEMM96 : KT_GEMM, l.flops, l.bytes);
-  }
-  HIP_OK(hipGetLastError());
-  return ADC_OK;
+  return now ? issue_probs(c, ar) : ADC_OK;
 }
 
 static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJob>& jobs, double* flops) {
@@ -786,7 +795,10 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         push_prob(probs, p);
       }
     }
-    ADC_TRY(launch_probs(c, probs, flops, ar));
+    // the first group at once (the GPU starts on it while the host builds
+    // the others), the rest staged and issued together after the leaf step's
+    // group: one upload, and the launches queued back to back
+    ADC_TRY(launch_probs(c, probs, flops, ar, l == Lmax));
   }
   // downsweep, one launch per level l: for every node q at level l above
   // the leaves, its children's incoming blocks [E_c1 E_c2] = [G_sib(q) E_q]
@@ -831,7 +843,7 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
         push_prob(probs, p);
       }
     }
-    ADC_TRY(launch_probs(c, probs, flops, ar));
+    ADC_TRY(launch_probs(c, probs, flops, ar, false));
   }
   // leaves: out(:, t_i) = X(:, t_i) D_i + H_i V_i^T
   probs.clear();
@@ -875,7 +887,7 @@ static adc_status batch_apply(adc_ctx c, HssBatch& hb, const std::vector<ApplyJo
       push_prob(probs, p);
     }
   }
-  ADC_TRY(launch_probs(c, probs, flops, ar));
+  ADC_TRY(launch_probs(c, probs, flops, ar, true));
   return ADC_OK;
 }
 
