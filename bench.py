@@ -41,19 +41,19 @@ sys.path.insert(0, ROOT)
 # kernel and its launches are unchanged (first 16 hex digits of their
 # SHA-256); otherwise the traffic is reported as null.
 TRAFFIC = {
-    "k_gemm_f64": {"bytes_per_launch": 1657.5e6,
-                   "sources": {"gemm.hip": "9610f870382e35e7", "hss.hip": "a4937ee8bbf0ad9a"}},
+    "k_gemm_f64": {"bytes_per_launch": 1657.6e6,
+                   "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
     "k_gemm_f64_n64": {"bytes_per_launch": 841.0e6,
-                       "sources": {"gemm.hip": "9610f870382e35e7", "hss.hip": "a4937ee8bbf0ad9a"}},
+                       "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
     "k_gemm_f64_n96": {"bytes_per_launch": 356.2e6,
-                       "sources": {"gemm.hip": "9610f870382e35e7", "hss.hip": "a4937ee8bbf0ad9a"}},
-    "k_pack_rot": {"bytes_per_launch": 2302.9e6,
-                   "sources": {"merge.hip": "f2b55955ab0de7a1", "dc.hip": "a5fcdd6c937bbfbc"}},
+                       "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
+    "k_pack_rot": {"bytes_per_launch": 2301.7e6,
+                   "sources": {"merge.hip": "052b4e73f667add7", "dc.hip": "a5bce1379c2a38f7"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 29035.4e6,
-                       "sources": {"gemm.hip": "9610f870382e35e7", "dc.hip": "a5fcdd6c937bbfbc"}},
+    "k_gemm_f64_big": {"bytes_per_launch": 29052.8e6,
+                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "a5bce1379c2a38f7"}},
 }
 
 
