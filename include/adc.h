@@ -206,10 +206,15 @@ adc_status adc_stedc(adc_ctx ctx, int64_t n, const double* diag, const double* o
  *   diag, offdiag, w, Z   : host arrays of `count` device pointers
  *   ldz[count]            : host array of leading dimensions
  * Every DC level of every matrix runs as one launch per merge phase over a
- * device work queue; with opts->force_dense = 1 (or all K < hss_min_k) the
- * level sequence is captured once in a HIP graph keyed by the size set and
- * replayed by later calls with the same sizes.  reps may be NULL (one report
- * for the whole batch otherwise). */
+ * device work queue.  The matrices whose merges cannot take the HSS update
+ * (all of them with opts->force_dense = 1) form one level sequence that is
+ * captured once in a HIP graph keyed by their size set and replayed by later
+ * calls with the same sizes.  The matrices that may reach an HSS merge
+ * (n >= hss_min_k and a top-merge dense update of at least hss_min_flops)
+ * are solved together in a second level-batched pass that takes the HSS
+ * route where it applies (Section 4.3), with host decisions at its HSS
+ * levels.  rep may be NULL (one report for the whole batch otherwise;
+ * rep->info_index is the index of the matrix that failed). */
 adc_status adc_stedc_batched(adc_ctx ctx, int32_t count, const int64_t* n,
                              const double* const* diag, const double* const* offdiag,
                              double* const* w, double* const* Z, const int64_t* ldz,

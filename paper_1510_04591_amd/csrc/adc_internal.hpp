@@ -226,6 +226,11 @@ struct Arena {
 
 adc_status check_finite(adc_ctx c, const double* x, int64_t n, bool* ok);
 int pick_waves(int64_t K);
+// Several matrices (count, arrays indexed by matrix) in one level-batched
+// solve with the HSS route where it applies; dc.hip.
+adc_status stedc_forest(adc_ctx c, int count, const int64_t* n, const double* const* diag,
+                        const double* const* offdiag, double* const* w, double* const* Z, const int64_t* ldz,
+                        const adc_opts& o, adc_report* rep);
 void mlp_release(adc_ctx c);
 void batch_release(adc_ctx c);
 

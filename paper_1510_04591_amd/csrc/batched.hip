@@ -16,9 +16,11 @@
 // with the same sizes replay.  Caller pointers live in device descriptor arrays refreshed before
 // each replay, so they may change between calls.
 //
-// The update is the dense one (merges up to a few thousand, where HSS does
-// not pay); matrices large enough for an HSS merge are solved one by one
-// through adc_stedc unless opts.force_dense is set.
+// The update here is the dense one (merges up to a few thousand, where HSS
+// does not pay); matrices large enough for an HSS merge (unless
+// opts.force_dense is set) are solved together by the single-matrix level
+// loop over all of them (stedc_forest), which takes the HSS route at the
+// levels where it applies.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -622,12 +624,32 @@ extern "C" adc_status adc_stedc_batched(adc_ctx c, int32_t count, const int64_t*
     if (hss_possible && n[i] >= o.hss_min_k && top_f >= o.hss_min_flops) solo.push_back(i);
     else batch.push_back(i);
   }
-  for (int i : solo) {
+  if (!solo.empty()) {
+    // together, level-batched, with the single-matrix sequencing
+    std::vector<int64_t> sn, sl;
+    std::vector<const double*> sd, so;
+    std::vector<double*> sw, sz;
+    for (int i : solo) {
+      sn.push_back(n[i]);
+      sd.push_back(diag[i]);
+      so.push_back(offdiag[i]);
+      sw.push_back(w[i]);
+      sz.push_back(Z[i]);
+      sl.push_back(ldz[i]);
+    }
     adc_report r1;
-    const adc_status st = adc_stedc(c, n[i], diag[i], offdiag[i], w[i], Z[i], ldz[i], nullptr, 0, &o,
-                                    rep ? &r1 : nullptr);
+    const adc_status st = stedc_forest(c, (int)solo.size(), sn.data(), sd.data(), so.data(), sw.data(), sz.data(),
+                                       sl.data(), o, &r1);
     if (st != ADC_OK) {
-      if (rep) rep->info_index = i;
+      if (rep) {
+        // the matrix that holds the reported global row
+        rep->info_index = solo[0];
+        int64_t g0 = 0;
+        for (size_t u = 0; u < solo.size(); ++u) {
+          if (r1.info_index >= g0 && r1.info_index < g0 + sn[u]) rep->info_index = solo[u];
+          g0 += sn[u];
+        }
+      }
       return st;
     }
     if (rep) {

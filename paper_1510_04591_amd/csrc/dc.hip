@@ -84,6 +84,7 @@ constexpr int LSTAT = 8;  // doubles of per-level counts
 struct Node {
   int64_t s0;
   int32_t n;
+  int32_t mat;  // matrix of the solve
 };
 
 struct Plan {
@@ -93,14 +94,21 @@ struct Plan {
   std::vector<int64_t> leaf_s0;
   std::vector<int32_t> leaf_m;
   std::vector<int32_t> leaf_depth;
+  std::vector<int32_t> leaf_mat;
   std::vector<int64_t> splits;
 };
 
-Plan make_plan(int64_t N, int leaf) {
+// The trees of every matrix of a solve (matrix i owns the global rows
+// [g0_i, g0_i + n_i)); depth counts from each matrix's root, so the merges
+// of one depth of every matrix form one level.
+Plan make_plan(const std::vector<int64_t>& g0, const std::vector<int64_t>& nn, int leaf) {
   Plan p;
-  p.N = N;
   p.leaf = leaf;
-  std::vector<Node> cur{{0, (int32_t)N}};
+  std::vector<Node> cur;
+  for (size_t i = 0; i < nn.size(); ++i) {
+    if (nn[i] > 0) cur.push_back(Node{g0[i], (int32_t)nn[i], (int32_t)i});
+    p.N += nn[i];
+  }
   int depth = 0;
   while (!cur.empty()) {
     std::vector<Node> nxt, merges;
@@ -109,12 +117,13 @@ Plan make_plan(int64_t N, int leaf) {
         merges.push_back(nd);
         const int32_t h = nd.n / 2;
         p.splits.push_back(nd.s0 + h - 1);
-        nxt.push_back({nd.s0, h});
-        nxt.push_back({nd.s0 + h, nd.n - h});
+        nxt.push_back({nd.s0, h, nd.mat});
+        nxt.push_back({nd.s0 + h, nd.n - h, nd.mat});
       } else {
         p.leaf_s0.push_back(nd.s0);
         p.leaf_m.push_back(nd.n);
         p.leaf_depth.push_back(depth);
+        p.leaf_mat.push_back(nd.mat);
       }
     }
     if (!merges.empty()) p.merge_levels.push_back(merges);
@@ -133,10 +142,15 @@ struct WsLayout {
   double *pk, *qc;
   int* noconv;
   double* lstat;  // per-level counts of the levels sequenced on the device
+  double *din, *offg, *wg;  // several matrices: gathered inputs, eigenvalues
   size_t bytes;
 };
 
-WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
+// N rows in all; zb_elems doubles of second eigenvector buffers (n_i^2 per
+// matrix with merges); pk_elems doubles per packed operand and Cauchy matrix
+// (N x the largest n); gather: the inputs and eigenvalues of several
+// matrices in one index space.  One matrix: zb_elems = pk_elems = n^2.
+WsLayout layout_ws(char* base, int64_t N, size_t zb_elems, size_t pk_elems, bool gather) {
   Arena ar{base, 0, 0};
   WsLayout L{};
   L.a = ar.take<double>(N);
@@ -170,9 +184,12 @@ WsLayout layout_ws(char* base, int64_t N, bool need_zb) {
   L.lcnt = ar.take<int32_t>(N);
   L.noconv = ar.take<int>(64);
   L.lstat = ar.take<double>(64 * LSTAT);
-  L.Zb = need_zb ? ar.take<double>((size_t)N * N) : nullptr;
-  L.pk = ar.take<double>((size_t)N * N);
-  L.qc = ar.take<double>((size_t)N * N);
+  L.din = gather ? ar.take<double>(N) : nullptr;
+  L.offg = gather ? ar.take<double>(N) : nullptr;
+  L.wg = gather ? ar.take<double>(N) : nullptr;
+  L.Zb = zb_elems ? ar.take<double>(zb_elems) : nullptr;
+  L.pk = ar.take<double>(pk_elems);
+  L.qc = ar.take<double>(pk_elems);
   L.bytes = ar.off + 256;
   return L;
 }
@@ -227,40 +244,58 @@ adc_status dense_sorted_update(adc_ctx c, const MergeDev* d_m, int g, const Merg
 extern "C" adc_status adc_workspace_query(adc_ctx c, int64_t n, const adc_opts* opts, size_t* bytes) {
   if (!c || n < 0 || !bytes) return ADC_ERR_ARG;
   (void)opts;
-  *bytes = layout_ws(nullptr, std::max<int64_t>(n, 1), true).bytes;
+  const size_t n2 = (size_t)std::max<int64_t>(n, 1) * (size_t)std::max<int64_t>(n, 1);
+  *bytes = layout_ws(nullptr, std::max<int64_t>(n, 1), n2, n2, false).bytes;
   return ADC_OK;
 }
 
 // ---------------------------------------------------------------------------
-extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const double* offdiag, double* w,
-                                double* Z, int64_t ldz, void* ws, size_t ws_bytes, const adc_opts* opts_in,
-                                adc_report* rep) {
-  if (!c || n < 0) return ADC_ERR_ARG;
-  if (n == 0) return ADC_OK;
-  if (!diag || !w || !Z || ldz < n || (n > 1 && !offdiag)) return ADC_ERR_ARG;
-  if (n > 1000000) return ADC_ERR_UNSUPPORTED;
-  adc_opts o;
-  if (opts_in) o = *opts_in;
-  else adc_opts_default(&o);
-  ADC_TRY(validate_opts_ext(o));
-  DeviceGuard g(c->device);
+// The matrices of one solve.  One matrix: the caller's arrays are used in
+// place.  Several: they are laid side by side in one index space (matrix i
+// owns the global rows [g0_i, g0_i + n_i)), their inputs gathered into the
+// workspace and their eigenvalues scattered back at the end; every tree
+// level then runs over the merges of all matrices at once.
+struct Forest {
+  std::vector<int64_t> n, g0;
+  std::vector<const double*> diag, off;
+  std::vector<double*> w, Z;
+  std::vector<int64_t> ldz;
+};
+
+static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_bytes, const adc_opts& o,
+                               adc_report* rep) {
+  const int count = (int)F.n.size();
   const auto t_start = std::chrono::steady_clock::now();
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
     rep->info_index = -1;
   }
-  bool ok = true;
-  ADC_TRY(check_finite(c, diag, n, &ok));
-  if (!ok) return ADC_ERR_ARG;
-  if (n > 1) {
-    ADC_TRY(check_finite(c, offdiag, n - 1, &ok));
+  for (int i = 0; i < count; ++i) {
+    bool ok = true;
+    ADC_TRY(check_finite(c, F.diag[i], F.n[i], &ok));
     if (!ok) return ADC_ERR_ARG;
+    if (F.n[i] > 1) {
+      ADC_TRY(check_finite(c, F.off[i], F.n[i] - 1, &ok));
+      if (!ok) return ADC_ERR_ARG;
+    }
   }
 
-  const Plan plan = make_plan(n, o.dc_leaf);
+  const Plan plan = make_plan(F.g0, F.n, o.dc_leaf);
+  const int64_t n = plan.N;  // rows of the whole solve
   const int nlev = (int)plan.merge_levels.size();
-  const bool need_zb = nlev > 0;
-  const size_t need = layout_ws(nullptr, n, need_zb).bytes;
+  const bool gather = count > 1;
+  // second eigenvector buffers (matrices with merges) and the packed operand
+  std::vector<size_t> zb_off(count, 0);
+  size_t zb_elems = 0;
+  int64_t nbig = 1;
+  for (int i = 0; i < count; ++i)
+    if (F.n[i] > o.dc_leaf) {
+      zb_off[i] = zb_elems;
+      zb_elems += (size_t)F.n[i] * (size_t)F.n[i];
+      nbig = std::max(nbig, F.n[i]);
+    }
+  const size_t pk_elems = (size_t)n * (size_t)nbig;
+  const size_t need = layout_ws(nullptr, n, zb_elems, pk_elems, gather).bytes;
   char* base;
   if (ws) {
     if (ws_bytes < need) return ADC_ERR_ARG;
@@ -268,8 +303,34 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
   } else {
     ADC_TRY(c->buffer(SLOT_WS, need, (void**)&base));
   }
-  WsLayout L = layout_ws(base, n, need_zb);
+  WsLayout L = layout_ws(base, n, zb_elems, pk_elems, gather);
   hipStream_t st = c->stream;
+  const double* diag = F.diag[0];
+  const double* offdiag = F.off[0];
+  double* w = F.w[0];
+  if (gather) {
+    // the entry after each matrix's last row stays zero (never read)
+    HIP_OK(hipMemsetAsync(L.offg, 0, (size_t)n * 8, st));
+    for (int i = 0; i < count; ++i) {
+      if (F.n[i] == 0) continue;
+      HIP_OK(hipMemcpyAsync(L.din + F.g0[i], F.diag[i], F.n[i] * 8, hipMemcpyDeviceToDevice, st));
+      if (F.n[i] > 1)
+        HIP_OK(hipMemcpyAsync(L.offg + F.g0[i], F.off[i], (F.n[i] - 1) * 8, hipMemcpyDeviceToDevice, st));
+    }
+    diag = L.din;
+    offdiag = L.offg;
+    w = L.wg;
+  }
+  // per merge: the matrix's output and second buffer at the merge's corner
+  auto zbuf = [&](int mat, int parity, int64_t s0, int64_t* ld) -> double* {
+    const int64_t r = s0 - F.g0[mat];
+    if (parity == 0) {
+      *ld = F.ldz[mat];
+      return F.Z[mat] + r + r * F.ldz[mat];
+    }
+    *ld = F.n[mat];
+    return L.Zb + zb_off[mat] + r + r * F.n[mat];
+  };
 
   // --- host staging for descriptors
   const int64_t nleaf = (int64_t)plan.leaf_s0.size();
@@ -306,21 +367,14 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     LeafOut* h_lo = ha.take<LeafOut>(nleaf);
     LeafOut* d_lo = da.take<LeafOut>(nleaf);
     if (!plan.splits.empty()) std::memcpy(h_sp, plan.splits.data(), plan.splits.size() * 8);
-    // leaves grouped by the buffer they go to (depth parity)
-    std::vector<int64_t> ls[2];
-    std::vector<int32_t> lm[2];
+    // each leaf writes to its matrix's buffer of its depth's parity
     for (int64_t i = 0; i < nleaf; ++i) {
-      const int par = plan.leaf_depth[i] & 1;
-      ls[par].push_back(plan.leaf_s0[i]);
-      lm[par].push_back(plan.leaf_m[i]);
+      h_ls[i] = plan.leaf_s0[i];
+      h_lm[i] = plan.leaf_m[i];
+      int64_t ld;
+      double* zp = zbuf(plan.leaf_mat[i], plan.leaf_depth[i] & 1, plan.leaf_s0[i], &ld);
+      h_lo[i] = LeafOut{zp, ld};
     }
-    const size_t n0 = ls[0].size();
-    std::memcpy(h_ls, ls[0].data(), n0 * 8);
-    std::memcpy(h_ls + n0, ls[1].data(), ls[1].size() * 8);
-    std::memcpy(h_lm, lm[0].data(), n0 * 4);
-    std::memcpy(h_lm + n0, lm[1].data(), lm[1].size() * 4);
-    for (size_t i = 0; i < n0; ++i) h_lo[i] = LeafOut{Z + ls[0][i] + ls[0][i] * ldz, ldz};
-    for (size_t i = 0; i < ls[1].size(); ++i) h_lo[n0 + i] = LeafOut{L.Zb + ls[1][i] + ls[1][i] * n, n};
     if (ha.off > desc_bytes) return ADC_ERR_UNSUPPORTED;
     ADC_TRY(c->upload(dd, img.data(), ha.off));
     c->ktimer.begin(rep != nullptr);
@@ -399,11 +453,12 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     B.w_in = L.win;
     B.w_out = w;
     B.off = offdiag;
-    const bool out_user = (t % 2) == 0;
-    double* Znew = out_user ? Z : L.Zb;
-    const int64_t ldn = out_user ? ldz : n;
-    const double* Zold = out_user ? L.Zb : Z;
-    const int64_t ldo = out_user ? n : ldz;
+    // results of depth t in buffer t mod 2 of their matrix, the children's in the other
+    const int par_new = t & 1;
+    auto set_z = [&](MergeDev& M, int mat) {
+      M.zn = zbuf(mat, par_new, M.s0, &M.ldn);
+      M.zo = zbuf(mat, par_new ^ 1, M.s0, &M.ldo);
+    };
     B.dsort = L.dsort;
     B.zsort = L.zsort;
     B.src = L.src;
@@ -474,10 +529,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
         M.gbase = lev[g2].s0;
         M.n = lev[g2].n;
         M.n1 = lev[g2].n / 2;
-        M.zo = Zold + M.s0 + M.s0 * ldo;
-        M.zn = Znew + M.s0 + M.s0 * ldn;
-        M.ldo = ldo;
-        M.ldn = ldn;
+        set_z(M, lev[g2].mat);
         M.zoff = M.s0 * (int64_t)nmax;
         M.mode = 0;
         for (int i0 = 0; i0 < M.n; i0 += 256) hob[iob++] = RootBlock{g2, i0};
@@ -569,10 +621,7 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
       M.gbase = lev[g2].s0;
       M.n = lev[g2].n;
       M.n1 = lev[g2].n / 2;
-      M.zo = Zold + M.s0 + M.s0 * ldo;
-      M.zn = Znew + M.s0 + M.s0 * ldn;
-      M.ldo = ldo;
-      M.ldn = ldn;
+      set_z(M, lev[g2].mat);
       M.zoff = M.s0 * (int64_t)nmax;
     }
     for (int g2 = 0; g2 < nm; ++g2) {
@@ -788,6 +837,10 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     }
   }
 
+  if (gather)
+    for (int i = 0; i < count; ++i)
+      if (F.n[i] > 0)
+        HIP_OK(hipMemcpyAsync(F.w[i], L.wg + F.g0[i], F.n[i] * 8, hipMemcpyDeviceToDevice, st));
   int nc = INT32_MAX;
   HIP_OK(hipMemcpyAsync(&nc, L.noconv, sizeof(int), hipMemcpyDeviceToHost, st));
   ADC_TRY(fetch_pending());
@@ -810,4 +863,50 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
     return ADC_ERR_NOCONV;
   }
   return ADC_OK;
+}
+
+extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const double* offdiag, double* w,
+                                double* Z, int64_t ldz, void* ws, size_t ws_bytes, const adc_opts* opts_in,
+                                adc_report* rep) {
+  if (!c || n < 0) return ADC_ERR_ARG;
+  if (n == 0) return ADC_OK;
+  if (!diag || !w || !Z || ldz < n || (n > 1 && !offdiag)) return ADC_ERR_ARG;
+  if (n > 1000000) return ADC_ERR_UNSUPPORTED;
+  adc_opts o;
+  if (opts_in) o = *opts_in;
+  else adc_opts_default(&o);
+  ADC_TRY(validate_opts_ext(o));
+  DeviceGuard g(c->device);
+  Forest F;
+  F.n = {n};
+  F.g0 = {0};
+  F.diag = {diag};
+  F.off = {offdiag};
+  F.w = {w};
+  F.Z = {Z};
+  F.ldz = {ldz};
+  return solve_forest(c, F, ws, ws_bytes, o, rep);
+}
+
+// Several matrices in one level-batched solve with the single-matrix
+// sequencing (HSS levels by the host); arguments checked by the caller.
+adc_status stedc_forest(adc_ctx c, int count, const int64_t* n, const double* const* diag,
+                        const double* const* offdiag, double* const* w, double* const* Z, const int64_t* ldz,
+                        const adc_opts& o, adc_report* rep) {
+  Forest F;
+  int64_t g0 = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] == 0) continue;
+    F.n.push_back(n[i]);
+    F.g0.push_back(g0);
+    F.diag.push_back(diag[i]);
+    F.off.push_back(n[i] > 1 ? offdiag[i] : diag[i]);  // n = 1: never read
+    F.w.push_back(w[i]);
+    F.Z.push_back(Z[i]);
+    F.ldz.push_back(ldz[i]);
+    g0 += n[i];
+  }
+  if (F.n.empty()) return ADC_OK;
+  if (g0 > 1000000) return ADC_ERR_UNSUPPORTED;
+  return solve_forest(c, F, nullptr, 0, o, rep);
 }

@@ -149,3 +149,32 @@ def test_full_batch_256_matrices(ctx):
             ks = np.array([0, n // 2, n - 1])
             assert np.max(np.abs(wh[ks] - sturm.eigenvalues_by_index(a, b, ks))) <= 1e-13 * tn
         assert np.array_equal(wh, outs[0][0][i].cpu().numpy())
+
+
+def test_batch_with_hss_matrices_vs_oracle(ctx):
+    """A batch mixing matrices that take the HSS route (solved together, one
+    level loop over all of them) with small dense ones (graph path): every
+    result against the oracle / closed form, the HSS merges counted once per
+    merge, and the HSS-eligible matrices' level counts equal to solo solves
+    with the same options (the forest changes the launches, not the
+    deflation)."""
+    print("batch with HSS matrices", flush=True)
+    kw = dict(hss_min_k=512, hss_leaf=64, hss_levels=-1, hss_min_flops=0)
+    mats = [workloads.toeplitz(3000), workloads.random_uniform(300, 51), workloads.clement(2500),
+            workloads.toeplitz(4097), workloads.random_uniform(40, 52), workloads.legendre(2000)]
+    (ws, Zs, rep), = run_batch(ctx, mats, **kw)
+    assert rep["hss_merges"] > 0
+    hss_solo = 0
+    for (a, b), w, Zt in zip(mats, ws, Zs):
+        w = w.cpu().numpy()
+        Z = Zt.t().cpu().numpy()
+        n = len(a)
+        tn = odc.tnorm1(a, b)
+        w_o, _ = odc.stedc(a, b, leaf=32)
+        assert np.max(np.abs(w - w_o)) <= 1e-13 * tn, n
+        assert np.all(np.diff(w) >= 0)
+        assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12, n
+        if n >= 512:
+            ws1, Z1, r1 = adc.eigh_tridiagonal(ctx, cuda(a), cuda(b), **kw)
+            hss_solo += r1["hss_merges"]
+    assert rep["hss_merges"] == hss_solo
