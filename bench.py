@@ -18,7 +18,8 @@ headline), the roofline of the dominant kernel (HIP-event durations recorded
 by the library on its stream inside the timed steps), Algorithm 3 against its
 least-traffic model, the other configurations (random N = 8192, the headline
 with HSS at exactly the top three levels, the learned rank predictor on a
-prescribed spectrum, the 256-matrix batch) and the CPU oracle timed on a
+prescribed spectrum, the 256-matrix batch, a batch of 16 matrices that take
+the HSS route) and the CPU oracle timed on a
 bounded sample, with the GPU time at the same size.
 """
 import argparse
@@ -210,6 +211,69 @@ def run_batched(torch, adc, ctx, steps, warmup, sequential=True):
     del Zs
     torch.cuda.empty_cache()
     return out
+
+
+def run_batched_hss(torch, adc, ctx, steps):
+    """16 matrices large enough for HSS merges, N ~ U{4000..8000} (seed 11),
+    alternately Toeplitz(2,1) and random U(-1,1)/U(0,1), the headline
+    options: one adc_stedc_batched call (those matrices are solved together,
+    level-batched with the HSS route where it applies) against the same
+    matrices through adc_stedc one at a time.  Median of `steps` timed calls
+    after one untimed call each; every matrix's residual checked."""
+    from paper_1510_04591_amd import workloads
+    rng = np.random.default_rng(11)
+    sizes = [int(x) for x in rng.integers(4000, 8001, 16)]
+    mats = [workloads.toeplitz(n) if i % 2 == 0 else workloads.random_uniform(n, 60 + i)
+            for i, n in enumerate(sizes)]
+    ds = [torch.from_numpy(a).cuda() for a, _ in mats]
+    os_ = [torch.from_numpy(b).cuda() for _, b in mats]
+    ws = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+    Zs = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n in sizes]
+    o = adc.opts(**HEADLINE)
+
+    def batched():
+        rep = adc.adc_report()
+        st = adc.adc_stedc_batched(ctx.h, sizes, ds, os_, ws, Zs, sizes, o, rep)
+        if st != adc.ADC_OK:
+            raise adc.AdcError(st, "adc_stedc_batched")
+        return rep
+
+    def one_by_one():
+        for d_, o_, w_, Z_, n in zip(ds, os_, ws, Zs, sizes):
+            st = adc.adc_stedc(ctx.h, n, d_, o_, w_, Z_, n, None, 0, o, None)
+            if st != adc.ADC_OK:
+                raise adc.AdcError(st, "adc_stedc")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    t_seq = timed(one_by_one)
+    t_b = timed(batched)
+    rep = batched().as_dict()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (a, b), w, Zt, n in zip(mats, ws, Zs, sizes):
+        ad, bd = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        Z = Zt.t()
+        TZ = ad[:, None] * Z
+        TZ[:-1] += bd[:, None] * Z[1:]
+        TZ[1:] += bd[:, None] * Z[:-1]
+        tn = float(np.max(np.abs(a) + np.concatenate([[0], np.abs(b)]) + np.concatenate([np.abs(b), [0]])))
+        worst = max(worst, float(torch.linalg.norm(TZ - Z * w[None, :])) / (n * tn))
+    del Zs
+    torch.cuda.empty_cache()
+    return {"workload": "16 tridiagonal matrices, N ~ U{4000..8000} (sum %d), alternately Toeplitz(2,1) and "
+                        "random U(-1,1)/U(0,1), seed 11, headline HSS options" % sum(sizes),
+            "value": 16.0 / t_b, "unit": "matrices/s", "s_per_batch": t_b, "steps": steps,
+            "one_by_one_matrices_per_s": 16.0 / t_seq, "hss_merges": rep["hss_merges"], "max_resid": worst}
 
 
 def recorded_traffic(kernel, table=None):
@@ -485,7 +549,8 @@ def main():
         return
     if args.batched_only:
         ctx = adc.Context(0)
-        print(json.dumps({"batched": run_batched(torch, adc, ctx, args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"batched": run_batched(torch, adc, ctx, args.steps, args.warmup),
+                          "batched_hss": run_batched_hss(torch, adc, ctx, max(args.steps, 3))}), flush=True)
         ctx.close()
         return
 
@@ -638,6 +703,9 @@ def main():
     if not args.no_batched:
         res["batched"] = run_batched(torch, adc, ctx, max(args.steps, 3), 1)
         print(f"# batched: {res['batched']['value']:.1f} matrices/s", flush=True)
+        res["batched_hss"] = run_batched_hss(torch, adc, ctx, 3)
+        print(f"# batched with HSS: {res['batched_hss']['value']:.1f} matrices/s "
+              f"(one by one {res['batched_hss']['one_by_one_matrices_per_s']:.1f})", flush=True)
     if not args.no_cpu:
         cb = cpu_baseline()
         cb["gpu_s_same_size"] = gpu_time_at(torch, adc, ctx, cb["measured_n"])
