@@ -336,14 +336,30 @@ __global__ __launch_bounds__(128) void k_fmm_leaf(const HssMerge* __restrict__ m
         }
         __syncthreads();
         if (active) {
-          for (int j = 0; j < nj; ++j) {
+          // both forms of each difference are formed and one is selected (no
+          // branch per source); two sources per step, so that two reciprocal
+          // chains are in flight
+          auto diff = [&](int j) {
             const int gj = j0 + j;
-            double df;
-            if (jb.side == 0)  // target pole i, source root gj: d_i - lam_gj
-              df = (i <= gj) ? (td - s0[j]) - s1[j] : (td - s2[j]) + s3[j];
-            else  // target root i, source pole gj: d_gj - lam_i
-              df = (gj <= i) ? (s0[j] - td) - tg : (s0[j] - tdn) + tm;
-            const double inv = rcp_refined(df);
+            if (jb.side == 0) {  // target pole i, source root gj: d_i - lam_gj
+              const double a = (td - s0[j]) - s1[j];
+              const double b = (td - s2[j]) + s3[j];
+              return (i <= gj) ? a : b;
+            }
+            // target root i, source pole gj: d_gj - lam_i
+            const double a = (s0[j] - td) - tg;
+            const double b = (s0[j] - tdn) + tm;
+            return (gj <= i) ? a : b;
+          };
+          int j = 0;
+          for (; j + 1 < nj; j += 2) {
+            const double inv0 = rcp_refined(diff(j));
+            const double inv1 = rcp_refined(diff(j + 1));
+#pragma unroll
+            for (int c = 0; c < CW; ++c) acc[c] = fma(inv1, qs[(j + 1) * CW + c], fma(inv0, qs[j * CW + c], acc[c]));
+          }
+          if (j < nj) {
+            const double inv = rcp_refined(diff(j));
 #pragma unroll
             for (int c = 0; c < CW; ++c) acc[c] = fma(inv, qs[j * CW + c], acc[c]);
           }
