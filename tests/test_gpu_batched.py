@@ -151,19 +151,32 @@ def test_full_batch_256_matrices(ctx):
         assert np.array_equal(wh, outs[0][0][i].cpu().numpy())
 
 
-def test_batch_with_hss_matrices_vs_oracle(ctx):
+@pytest.mark.parametrize("variant", ["default", "direct_sampling", "retries", "fallback"])
+def test_batch_with_hss_matrices_vs_oracle(ctx, variant):
     """A batch mixing matrices that take the HSS route (solved together, one
     level loop over all of them) with small dense ones (graph path): every
     result against the oracle / closed form, the HSS merges counted once per
     merge, and the HSS-eligible matrices' level counts equal to solo solves
     with the same options (the forest changes the launches, not the
     deflation)."""
-    print("batch with HSS matrices", flush=True)
+    print(f"batch with HSS matrices ({variant})", flush=True)
     kw = dict(hss_min_k=512, hss_leaf=64, hss_levels=-1, hss_min_flops=0)
+    if variant == "direct_sampling":
+        kw["sample_mode"] = adc.ADC_SAMPLE_DIRECT
+    elif variant == "retries":
+        # too few samples: merges of the forest fail the check and are rebuilt
+        kw.update(rank_mode=adc.ADC_RANK_FIXED, fixed_rank=4, oversample=0, max_retries=6)
+    elif variant == "fallback":
+        # two samples, no retry: every HSS merge falls back to the dense update
+        kw.update(rank_mode=adc.ADC_RANK_FIXED, fixed_rank=2, oversample=0, max_retries=0)
     mats = [workloads.toeplitz(3000), workloads.random_uniform(300, 51), workloads.clement(2500),
             workloads.toeplitz(4097), workloads.random_uniform(40, 52), workloads.legendre(2000)]
     (ws, Zs, rep), = run_batch(ctx, mats, **kw)
     assert rep["hss_merges"] > 0
+    if variant == "retries":
+        assert rep["retries"] > 0
+    if variant == "fallback":
+        assert rep["hss_fallbacks"] == rep["hss_merges"]
     hss_solo = 0
     for (a, b), w, Zt in zip(mats, ws, Zs):
         w = w.cpu().numpy()
