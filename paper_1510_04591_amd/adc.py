@@ -124,7 +124,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"libadc.so not found at {LIB_PATH}: run __graft_entry__.build()")
+            raise ImportError(f"libadc.so not found at {LIB_PATH}: build it with python -m paper_1510_04591_amd.build")
         L = C.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
