@@ -49,12 +49,12 @@ TRAFFIC = {
     "k_gemm_f64_n96": {"bytes_per_launch": 356.2e6,
                        "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
     "k_pack_rot": {"bytes_per_launch": 2301.7e6,
-                   "sources": {"merge.hip": "052b4e73f667add7", "dc.hip": "a5bce1379c2a38f7"}},
+                   "sources": {"merge.hip": "052b4e73f667add7", "dc.hip": "71e71bf5b62ae6c2"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 29052.8e6,
-                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "a5bce1379c2a38f7"}},
+    "k_gemm_f64_big": {"bytes_per_launch": 29052.5e6,
+                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "71e71bf5b62ae6c2"}},
 }
 
 
