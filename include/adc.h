@@ -118,6 +118,12 @@ typedef struct adc_opts {
                             not span the block) fails its check like a large
                             probe error: its samples double and it is rebuilt;
                             0: saturated merges are only counted            */
+  double  batch_bytes;   /* [0] adc_stedc_batched: device bytes one group of
+                            HSS-eligible matrices solved together may take
+                            (second eigenvector buffers n^2 per matrix plus
+                            two packed operands of rows x largest n, 8 bytes
+                            each); a larger set is split into consecutive
+                            groups; 0 means 32 GiB                         */
 } adc_opts;
 
 /* Report of one solve (host struct, optional). */

@@ -38,6 +38,7 @@ class adc_opts(C.Structure):
         ("shift_max", C.c_int32), ("shift_thresh", C.c_double), ("r_cap", C.c_int32),
         ("rank_eps", C.c_double), ("hss_min_flops", C.c_double), ("sample_mode", C.c_int32),
         ("fmm_order", C.c_int32), ("sat_guard", C.c_int32),
+        ("batch_bytes", C.c_double),
     ]
 
 

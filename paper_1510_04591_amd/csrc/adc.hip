@@ -81,6 +81,7 @@ extern "C" adc_status adc_opts_default(adc_opts* o) {
   o->sample_mode = ADC_SAMPLE_FMM;
   o->fmm_order = 20;
   o->sat_guard = 0;
+  o->batch_bytes = 0.0;
   return ADC_OK;
 }
 
@@ -95,6 +96,7 @@ adc_status validate_opts_ext(const adc_opts& o) {
   if (o.shift_max < 0 || o.shift_max > 64) return ADC_ERR_ARG;
   if (o.rank_mode < 0 || o.rank_mode > 2) return ADC_ERR_ARG;
   if (o.sat_guard < 0 || o.sat_guard > 1) return ADC_ERR_ARG;
+  if (!(o.batch_bytes >= 0.0) || !std::isfinite(o.batch_bytes)) return ADC_ERR_ARG;
   return ADC_OK;
 }
 

@@ -273,10 +273,11 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
   for (int i = 0; i < count; ++i) {
     bool ok = true;
     ADC_TRY(check_finite(c, F.diag[i], F.n[i], &ok));
-    if (!ok) return ADC_ERR_ARG;
-    if (F.n[i] > 1) {
-      ADC_TRY(check_finite(c, F.off[i], F.n[i] - 1, &ok));
-      if (!ok) return ADC_ERR_ARG;
+    if (ok && F.n[i] > 1) ADC_TRY(check_finite(c, F.off[i], F.n[i] - 1, &ok));
+    if (!ok) {
+      // several matrices: a row of the offending one
+      if (rep && count > 1) rep->info_index = (int32_t)F.g0[i];
+      return ADC_ERR_ARG;
     }
   }
 
@@ -888,25 +889,89 @@ extern "C" adc_status adc_stedc(adc_ctx c, int64_t n, const double* diag, const 
   return solve_forest(c, F, ws, ws_bytes, o, rep);
 }
 
-// Several matrices in one level-batched solve with the single-matrix
-// sequencing (HSS levels by the host); arguments checked by the caller.
+namespace {
+
+// Adds the figures of one forest solve to a running report.
+void report_add(adc_report* a, const adc_report& b) {
+  a->levels = std::max(a->levels, b.levels);
+  a->merges += b.merges;
+  a->hss_merges += b.hss_merges;
+  a->retries += b.retries;
+  a->hss_fallbacks += b.hss_fallbacks;
+  a->max_rank = std::max(a->max_rank, b.max_rank);
+  a->samples = std::max(a->samples, b.samples);
+  a->hss_saturated += b.hss_saturated;
+  a->hss_sat_nodes += b.hss_sat_nodes;
+  a->check_err_max = std::max(a->check_err_max, b.check_err_max);
+  a->flops_model += b.flops_model;
+  a->bytes_model += b.bytes_model;
+  for (int t = 0; t < 64; ++t) {
+    a->n_per_level[t] += b.n_per_level[t];
+    a->K_per_level[t] += b.K_per_level[t];
+    a->hss_per_level[t] += b.hss_per_level[t];
+  }
+  for (int p = 0; p < 12; ++p) {
+    a->t_phase[p] += b.t_phase[p];
+    a->phase_flops[p] += b.phase_flops[p];
+    a->phase_bytes[p] += b.phase_bytes[p];
+    a->phase_launches[p] += b.phase_launches[p];
+    a->kern_time[p] += b.kern_time[p];
+    a->kern_flops[p] += b.kern_flops[p];
+    a->kern_bytes[p] += b.kern_bytes[p];
+    a->kern_launches[p] += b.kern_launches[p];
+  }
+}
+
+}  // namespace
+
+// Several matrices in level-batched solves with the single-matrix sequencing
+// (HSS levels by the host); arguments checked by the caller.  The matrices
+// are taken in order into forests of at most 10^6 rows whose workspace
+// (second eigenvector buffers, n^2 per matrix, and two packed operands of
+// rows x largest n) stays within opts.batch_bytes; a matrix that alone
+// exceeds it forms a forest of its own.  On failure rep->info_index is a row of the failing matrix
+// in the concatenation of the nonempty matrices.
 adc_status stedc_forest(adc_ctx c, int count, const int64_t* n, const double* const* diag,
                         const double* const* offdiag, double* const* w, double* const* Z, const int64_t* ldz,
                         const adc_opts& o, adc_report* rep) {
-  Forest F;
-  int64_t g0 = 0;
-  for (int i = 0; i < count; ++i) {
-    if (n[i] == 0) continue;
-    F.n.push_back(n[i]);
-    F.g0.push_back(g0);
-    F.diag.push_back(diag[i]);
-    F.off.push_back(n[i] > 1 ? offdiag[i] : diag[i]);  // n = 1: never read
-    F.w.push_back(w[i]);
-    F.Z.push_back(Z[i]);
-    F.ldz.push_back(ldz[i]);
-    g0 += n[i];
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->info_index = -1;
   }
-  if (F.n.empty()) return ADC_OK;
-  if (g0 > 1000000) return ADC_ERR_UNSUPPORTED;
-  return solve_forest(c, F, nullptr, 0, o, rep);
+  const double budget = o.batch_bytes > 0.0 ? o.batch_bytes : 32.0 * 1073741824.0;
+  int64_t row0 = 0;  // first row of the current forest in the concatenation
+  int i = 0;
+  while (i < count) {
+    Forest F;
+    int64_t g0 = 0, nbig = 0;
+    double sumsq = 0.0;
+    for (; i < count; ++i) {
+      if (n[i] == 0) continue;
+      const int64_t nb = std::max(nbig, n[i]);
+      const double sq = sumsq + (double)n[i] * (double)n[i];
+      const double bytes = 8.0 * (sq + 2.0 * (double)(g0 + n[i]) * (double)nb) + 256.0 * (double)(g0 + n[i]);
+      if (!F.n.empty() && (g0 + n[i] > 1000000 || bytes > budget)) break;
+      F.n.push_back(n[i]);
+      F.g0.push_back(g0);
+      F.diag.push_back(diag[i]);
+      F.off.push_back(n[i] > 1 ? offdiag[i] : diag[i]);  // n = 1: never read
+      F.w.push_back(w[i]);
+      F.Z.push_back(Z[i]);
+      F.ldz.push_back(ldz[i]);
+      g0 += n[i];
+      nbig = nb;
+      sumsq = sq;
+    }
+    if (F.n.empty()) break;
+    adc_report r1;
+    const adc_status st = solve_forest(c, F, nullptr, 0, o, rep ? &r1 : nullptr);
+    if (rep) {
+      const int32_t info = r1.info_index;
+      report_add(rep, r1);
+      if (st != ADC_OK) rep->info_index = (int32_t)(row0 + std::max<int32_t>(info, 0));
+    }
+    if (st != ADC_OK) return st;
+    row0 += g0;
+  }
+  return ADC_OK;
 }

@@ -151,7 +151,7 @@ def test_full_batch_256_matrices(ctx):
         assert np.array_equal(wh, outs[0][0][i].cpu().numpy())
 
 
-@pytest.mark.parametrize("variant", ["default", "direct_sampling", "retries", "fallback"])
+@pytest.mark.parametrize("variant", ["default", "direct_sampling", "retries", "fallback", "split"])
 def test_batch_with_hss_matrices_vs_oracle(ctx, variant):
     """A batch mixing matrices that take the HSS route (solved together, one
     level loop over all of them) with small dense ones (graph path): every
@@ -169,6 +169,11 @@ def test_batch_with_hss_matrices_vs_oracle(ctx, variant):
     elif variant == "fallback":
         # two samples, no retry: every HSS merge falls back to the dense update
         kw.update(rank_mode=adc.ADC_RANK_FIXED, fixed_rank=2, oversample=0, max_retries=0)
+    elif variant == "split":
+        # a group bound of 400 MB: the HSS-eligible matrices form three
+        # groups (3000 + 2500, then 4097 alone although it exceeds the bound,
+        # then 2000)
+        kw["batch_bytes"] = 400e6
     mats = [workloads.toeplitz(3000), workloads.random_uniform(300, 51), workloads.clement(2500),
             workloads.toeplitz(4097), workloads.random_uniform(40, 52), workloads.legendre(2000)]
     (ws, Zs, rep), = run_batch(ctx, mats, **kw)

@@ -54,6 +54,22 @@ def test_nonfinite_input_is_rejected(ctx):
     st = adc.adc_stedc_batched(ctx.h, ns, ds, es, ws, Zs, ns, adc.opts(force_dense=1))
     assert st == adc.ADC_ERR_ARG, adc.status_string(st)
     torch.cuda.synchronize()
+    # matrices that take the HSS route are solved together (one group, or
+    # one group per matrix with a tiny batch_bytes): the report names the bad one
+    ns = [900, 64, 700, 800]
+    mats = [workloads.toeplitz(k) for k in ns]
+    ds = [cuda(m[0]) for m in mats]
+    es = [cuda(m[1]) for m in mats]
+    ds[2][300] = float("inf")
+    ws = [torch.empty(k, dtype=torch.float64, device="cuda") for k in ns]
+    Zs = [torch.empty(k * k, dtype=torch.float64, device="cuda") for k in ns]
+    for split in (0.0, 1.0):
+        rep = adc.adc_report()
+        o = adc.opts(hss_min_k=256, hss_min_flops=0, batch_bytes=split)
+        st = adc.adc_stedc_batched(ctx.h, ns, ds, es, ws, Zs, ns, o, rep)
+        assert st == adc.ADC_ERR_ARG, adc.status_string(st)
+        assert rep.info_index == 2, (split, rep.info_index)
+    torch.cuda.synchronize()
     still_solves(ctx)
 
 
@@ -85,7 +101,8 @@ def test_sizes_pointers_and_workspace(ctx):
 @pytest.mark.parametrize("field,value", [("dc_leaf", 1), ("dc_leaf", 65), ("hss_leaf", 8), ("hss_leaf", 512),
                                          ("nprobe", 0), ("nprobe", 33), ("fmm_order", 3), ("fmm_order", 33),
                                          ("shift_max", 65), ("rank_mode", 3), ("max_iter", 0),
-                                         ("sample_mode", 2), ("oversample", -1)])
+                                         ("sample_mode", 2), ("oversample", -1), ("batch_bytes", -1.0),
+                                         ("batch_bytes", float("nan"))])
 def test_invalid_option_is_rejected(ctx, field, value):
     n = 64
     a, b = workloads.toeplitz(n)
@@ -118,4 +135,19 @@ def test_nonconvergence_is_reported(ctx, dense):
                                adc.opts(max_iter=1, force_dense=1))
     torch.cuda.synchronize()
     assert st == adc.ADC_ERR_NOCONV, adc.status_string(st)
+    if not dense:
+        # HSS-eligible matrices, solved together and in one group each:
+        # the report names a matrix of the batch
+        ns = [40, 1500, 1200]
+        mats = [workloads.toeplitz(k) for k in ns]
+        ws = [torch.empty(k, dtype=torch.float64, device="cuda") for k in ns]
+        Zs = [torch.empty(k * k, dtype=torch.float64, device="cuda") for k in ns]
+        for split in (0.0, 1.0):
+            rep = adc.adc_report()
+            o = adc.opts(max_iter=1, hss_min_k=256, hss_min_flops=0, hss_leaf=64, batch_bytes=split)
+            st = adc.adc_stedc_batched(ctx.h, ns, [cuda(m[0]) for m in mats], [cuda(m[1]) for m in mats], ws, Zs,
+                                       ns, o, rep)
+            torch.cuda.synchronize()
+            assert st == adc.ADC_ERR_NOCONV, adc.status_string(st)
+            assert rep.info_index in (0, 1, 2), (split, rep.info_index)
     still_solves(ctx)
