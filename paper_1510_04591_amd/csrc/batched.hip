@@ -489,9 +489,8 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
   char* d = e->desc;
   hipLaunchKernelGGL(k_tear, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, e->din, e->offg,
                      (const int64_t*)(d + e->o_sp), e->nsplit, e->a, tot);
-  if (e->nleaf)
-    hipLaunchKernelGGL(k_leaf_jacobi, dim3(e->nleaf), dim3(256), 0, st, e->a, e->offg, (const int64_t*)(d + e->o_ls),
-                       (const int32_t*)(d + e->o_lm), e->w, (const LeafOut*)(d + e->o_lo), 40);
+  launch_leaf_jacobi(st, e->nleaf, e->leaf, e->a, e->offg, (const int64_t*)(d + e->o_ls),
+                     (const int32_t*)(d + e->o_lm), e->w, (const LeafOut*)(d + e->o_lo), 40);
   HIP_OK(hipGetLastError());
   const LevelBufs B = level_bufs(e);
   hipEvent_t ev[2] = {nullptr, nullptr};

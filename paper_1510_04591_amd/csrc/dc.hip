@@ -383,9 +383,7 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_tear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag, offdiag, d_sp,
                        (int)plan.splits.size(), L.a, n);
-    if (nleaf)
-      hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)nleaf), dim3(256), 0, st, L.a, offdiag, d_ls, d_lm, w,
-                         (const LeafOut*)d_lo, 40);
+    launch_leaf_jacobi(st, nleaf, plan.leaf, L.a, offdiag, d_ls, d_lm, w, (const LeafOut*)d_lo, 40);
     HIP_OK(hipGetLastError());
     c->timer.mark(st, 0);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, L.noconv, INT32_MAX);

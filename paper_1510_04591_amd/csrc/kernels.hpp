@@ -102,9 +102,10 @@ struct LevelBufs {
 };
 
 // ---- kernels
-__global__ void k_leaf_jacobi(const double* __restrict__ a, const double* __restrict__ b,
-                              const int64_t* __restrict__ leaf_s0, const int32_t* __restrict__ leaf_m,
-                              double* __restrict__ w, const LeafOut* __restrict__ outs, int max_sweeps);
+// leaf eigensolves (sizes <= leaf_max <= 64) into w and each leaf's block
+void launch_leaf_jacobi(hipStream_t st, int64_t nleaf, int leaf_max, const double* a, const double* b,
+                        const int64_t* leaf_s0, const int32_t* leaf_m, double* w, const LeafOut* outs,
+                        int max_sweeps);
 
 __global__ void k_merge_sort(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,
                              LevelBufs B);
