@@ -580,8 +580,7 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
       hipLaunchKernelGGL(k_final_order, dim3(nob), dim3(256), 0, st, d_m, B, d_ob);
       Pending p{t, nm, nsum, 0, 0};
       c->ktimer.pre(st);
-      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)std::min(njob, 2 * c->num_cu)), dim3(256), 0, st, d_m, d_cm,
-                         d_cc, B, njob);
+      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)((njob + 3) / 4)), dim3(256), 0, st, d_m, d_cm, d_cc, B, njob);
       c->ktimer.post(st, KT_PACK, 0.0, 0.0);
       p.k_pack = c->ktimer.last();
       hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, st, d_m, d_tm, d_tc, B, 8, 1);
@@ -789,8 +788,8 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
     // the packed operand.
     auto pack = [&](hipStream_t sp) {
       c->ktimer.pre(sp);
-      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)std::min(njob, 2 * c->num_cu)), dim3(256), 0, sp, d_m, d_cm,
-                         d_cc, B, njob);
+      hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)std::min((njob + 3) / 4, 2 * c->num_cu)), dim3(256), 0, sp,
+                         d_m, d_cm, d_cc, B, njob);
       c->ktimer.post(sp, KT_PACK, 0.0, pack_by);
       if (ntile) hipLaunchKernelGGL(k_cauchy, dim3(ntile), dim3(256), 0, sp, d_m, d_tm, d_tc, B, ncols, 1);
     };

@@ -621,14 +621,15 @@ __global__ void __launch_bounds__(256) k_zero_unsupported(const MergeDev* __rest
 // support are the zeros of diag(Q1, Q2).
 __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges,
                                              const int32_t* __restrict__ col_merge,
-                                             const int32_t* __restrict__ col_idx, const LevelBufs& B, int job) {
+                                             const int32_t* __restrict__ col_idx, const LevelBufs& B, int job,
+                                             int tid, int bs) {
   constexpr int CHMAX = 8;  // rotation steps held in registers
-  constexpr int RU = 4;     // rows per lane and iteration (loads in flight)
+  constexpr int RU = 4;     // rows per lane and iteration of a chain (loads in flight)
+  constexpr int RC = 8;     // the same for a plain copy
   const MergeDev& M = merges[col_merge[job]];
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1;
   const int p = col_idx[job];
-  const int bs = blockDim.x, tid = threadIdx.x;
   if (B.rot_j_of[s0 + p] >= 0) return;  // inside a chain: done by its head
   auto dst_of = [&](int pos) -> double* {
     const int role = B.pidx[s0 + pos];
@@ -657,12 +658,12 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
       for (int r = hi + tid; r < n; r += bs) dc[r] = 0.0;
     }
     int r = lo + tid;
-    for (; r + (RU - 1) * bs < hi; r += RU * bs) {
-      double x[RU];
+    for (; r + (RC - 1) * bs < hi; r += RC * bs) {
+      double x[RC];
 #pragma unroll
-      for (int v = 0; v < RU; ++v) x[v] = sc[r + v * bs];
+      for (int v = 0; v < RC; ++v) x[v] = sc[r + v * bs];
 #pragma unroll
-      for (int v = 0; v < RU; ++v) dc[r + v * bs] = x[v];
+      for (int v = 0; v < RC; ++v) dc[r + v * bs] = x[v];
     }
     for (; r < hi; r += bs) dc[r] = sc[r];
     return;
@@ -756,14 +757,19 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
   }
 }
 
-// Jobs strided over the grid: with fewer workgroups than jobs the packing
-// leaves room on the CUs for a kernel that needs a whole CU's LDS (the node
-// compression, which runs beside the packing at HSS levels; the solver
-// launches two workgroups per CU).
+// One wavefront per job (a short column is a few rows per lane, a long one
+// keeps eight loads per lane in flight); jobs strided over the grid's
+// wavefronts: with fewer workgroups than jobs the packing leaves room on the
+// CUs for a kernel that needs a whole CU's LDS (the node compression, which
+// runs beside the packing at HSS levels; the solver launches two workgroups
+// per CU there).
 __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
                                                   const int32_t* __restrict__ col_merge,
                                                   const int32_t* __restrict__ col_idx, LevelBufs B, int njob) {
-  for (int job = blockIdx.x; job < njob; job += gridDim.x) pack_rot_job(merges, col_merge, col_idx, B, job);
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int job = blockIdx.x * nw + wave_index(); job < njob; job += gridDim.x * nw)
+    pack_rot_job(merges, col_merge, col_idx, B, job, lane, 64);
 }
 
 // ---------------------------------------------------------------------------
