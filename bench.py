@@ -75,7 +75,8 @@ def parse():
     p.add_argument("--dense-steps", type=int, default=3)
     p.add_argument("--dense-warmup", type=int, default=1)
     p.add_argument("--no-extra", action="store_true",
-                   help="skip the other configurations (random 8192, top three levels, predictor)")
+                   help="skip the other configurations (random 8192, top three levels, predictor, "
+                        "the five families at 25000)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-validate", action="store_true")
     p.add_argument("--mode", choices=["both", "hss", "dense"], default="both")
@@ -132,7 +133,7 @@ def host_info():
     return nproc, model
 
 
-def cpu_baseline(n=5120):
+def cpu_baseline(n=7168):
     """The oracle (plain fp64 numpy DC) timed on a bounded sample: the full
     dense DC of the same Toeplitz family at order n on the host cores.  The
     value in the metric's unit is that measurement times (32768/n)^3 (the
@@ -515,6 +516,8 @@ def run_extra(torch, adc, ctx, args):
               f"retries {c5[name]['retries']}, saturated {c5[name]['saturated_merges']}, "
               f"orth {c5[name]['validation']['orth']:.1e}", flush=True)
     out["prescribed_uniform_32768"] = c5
+    # Example 3 / Table 5 at its largest order: the five families against dense DC
+    out["families_25000"] = run_families(torch, adc, ctx, [25000], 3)
     return out
 
 
