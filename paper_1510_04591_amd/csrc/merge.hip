@@ -619,10 +619,12 @@ __global__ void __launch_bounds__(256) k_zero_unsupported(const MergeDev* __rest
 // the merged block and the last (surviving) column into the packed operand;
 // the other chain members do nothing.  Rows outside a column's original
 // support are the zeros of diag(Q1, Q2).
-__device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges,
+// With heads = false a plain position is copied and a chain head only
+// reported (true); with heads = true the chain of a head is carried.
+__device__ __forceinline__ bool pack_rot_job(const MergeDev* __restrict__ merges,
                                              const int32_t* __restrict__ col_merge,
                                              const int32_t* __restrict__ col_idx, const LevelBufs& B, int job,
-                                             int tid, int bs) {
+                                             int tid, int bs, bool heads) {
   constexpr int CHMAX = 8;  // rotation steps held in registers
   constexpr int RU = 4;     // rows per lane and iteration of a chain (loads in flight)
   constexpr int RC = 8;     // the same for a plain copy
@@ -630,7 +632,7 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1;
   const int p = col_idx[job];
-  if (B.rot_j_of[s0 + p] >= 0) return;  // inside a chain: done by its head
+  if (B.rot_j_of[s0 + p] >= 0) return false;  // inside a chain: done by its head
   auto dst_of = [&](int pos) -> double* {
     const int role = B.pidx[s0 + pos];
     if (role >= 0) {
@@ -643,6 +645,7 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
   auto src_of = [&](int pos) -> const double* { return M.zo + B.src[s0 + pos] * M.ldo; };
   auto supp_of = [&](int pos) { return (B.src[s0 + pos] < n1) ? 1 : 2; };
   const int t0 = B.rot_i_of[s0 + p];
+  if (t0 >= 0 && !heads) return true;
   if (t0 < 0) {
     const double* __restrict__ sc = src_of(p);
     double* __restrict__ dc = dst_of(p);
@@ -666,7 +669,7 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
       for (int v = 0; v < RC; ++v) dc[r + v * bs] = x[v];
     }
     for (; r < hi; r += bs) dc[r] = sc[r];
-    return;
+    return false;
   }
   // chain t0, t0+1, ... while rot_i[t+1] == rot_j[t]
   const int nrot = M.nrot;
@@ -741,7 +744,7 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
         dlast[r] = a;
       }
     }
-    return;
+    return false;
   }
   for (int r = tid; r < n; r += bs) {
     const int bit = (r < n1) ? 1 : 2;
@@ -755,21 +758,34 @@ __device__ __forceinline__ void pack_rot_job(const MergeDev* __restrict__ merges
     }
     dst_of(B.rot_j[s0 + t1])[r] = a;
   }
+  return false;
 }
 
-// One wavefront per job (a short column is a few rows per lane, a long one
-// keeps eight loads per lane in flight); jobs strided over the grid's
-// wavefronts: with fewer workgroups than jobs the packing leaves room on the
+// Four consecutive jobs per workgroup, one wavefront each for a plain copy
+// (a short column is a few rows per lane, a long one keeps eight loads per
+// lane in flight); the heads of rotation chains among them are then carried
+// by the whole workgroup, one after the other (a chain's steps are
+// sequential per row, so its rows need every lane).  Jobs are strided over
+// the grid: with fewer workgroups than jobs the packing leaves room on the
 // CUs for a kernel that needs a whole CU's LDS (the node compression, which
 // runs beside the packing at HSS levels; the solver launches two workgroups
 // per CU there).
 __global__ void __launch_bounds__(256) k_pack_rot(const MergeDev* __restrict__ merges,
                                                   const int32_t* __restrict__ col_merge,
                                                   const int32_t* __restrict__ col_idx, LevelBufs B, int njob) {
-  const int nw = blockDim.x >> 6;
-  const int lane = threadIdx.x & 63;
-  for (int job = blockIdx.x * nw + wave_index(); job < njob; job += gridDim.x * nw)
-    pack_rot_job(merges, col_merge, col_idx, B, job, lane, 64);
+  __shared__ int s_head[4];
+  const int wv = wave_index(), lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * 4; base < njob; base += gridDim.x * 4) {
+    const int job = base + wv;
+    const bool head = job < njob && pack_rot_job(merges, col_merge, col_idx, B, job, lane, 64, false);
+    if (lane == 0) s_head[wv] = head ? job : -1;
+    __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+      const int hj = s_head[u];
+      if (hj >= 0) pack_rot_job(merges, col_merge, col_idx, B, hj, (int)threadIdx.x, 256, true);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
