@@ -147,6 +147,8 @@ void launch_leaf_jacobi(hipStream_t st, int64_t nleaf, int leaf_max, const doubl
                         int max_sweeps) {
   if (nleaf <= 0) return;
   const size_t lds = (size_t)2 * leaf_max * (leaf_max + 1) * sizeof(double);
+  // leaves above 63 rows take more than the default 64 KiB of dynamic LDS
+  if (lds > 65536) hipFuncSetAttribute((const void*)k_leaf_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)nleaf), dim3(NT), lds, st, a, b, leaf_s0, leaf_m, w, outs,
                      max_sweeps);
 }

@@ -57,6 +57,34 @@ def glued(copies, m=20, glue=1e-10, seed=7):
     return a, b
 
 
+@pytest.mark.parametrize("leaf", [2, 3, 17, 63, 64])
+def test_leaf_sizes_vs_oracle(ctx, leaf):
+    """The DC leaf sizes the options allow, at both ends and between: the leaf
+    eigensolves (their LDS sized to the leaf; above 63 rows more than the
+    default dynamic LDS) and the tree above them against the oracle with the
+    same leaf size, with equal deflation counts per level; a matrix that is a
+    single leaf against its closed form."""
+    print(f"leaf size {leaf}", flush=True)
+    a, b = workloads.random_uniform(700, 9)
+    w, Z, rep = solve(ctx, a, b, force_dense=1, dc_leaf=leaf)
+    rep_o = {}
+    w_o, _ = odc.stedc(a, b, leaf=leaf, report=rep_o)
+    check_result(a, b, w, Z, w_o)
+    lev = odc.split_tree(len(a), leaf)
+    idx = 0
+    for t in range(len(lev) - 1, -1, -1):
+        cnt = sum(1 for (s0, m) in lev[t] if m > leaf)
+        if cnt:
+            k = sum(rep_o["merges"][idx + u]["K"] for u in range(cnt))
+            assert rep["K_per_level"][t] == k, (t, rep["K_per_level"][t], k)
+            idx += cnt
+    a, b = workloads.toeplitz(leaf)
+    w, Z, rep = solve(ctx, a, b, force_dense=1, dc_leaf=leaf)
+    assert rep["merges"] == 0
+    k = np.arange(1, leaf + 1)
+    check_result(a, b, w, Z, np.sort(2 + 2 * np.cos(k * np.pi / (leaf + 1))))
+
+
 @pytest.mark.parametrize("kind", ["toeplitz", "random", "glued"])
 def test_deflation_counts_match_oracle(ctx, kind):
     """Integer parity: the number of survivors of deflation, summed per tree
