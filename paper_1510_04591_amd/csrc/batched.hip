@@ -504,7 +504,7 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
     MergeDev* dm = (MergeDev*)(d + L.o_m);
     HIP_OK(hipMemcpyAsync(e->win, e->w, (size_t)tot * 8, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_merge_sort, dim3(L.nob), dim3(256), 0, st, dm, (const RootBlock*)(d + L.o_ob), B);
-    hipLaunchKernelGGL(k_merge_prep, dim3(L.nm), dim3(1024), 0, st, dm, B);
+    hipLaunchKernelGGL(k_merge_prep, dim3(L.nm), dim3(prep_threads(L.nmax)), 0, st, dm, B);
     const auto key = std::make_tuple(L.nm, L.nmax, (int64_t)L.njob);
     if (tune && !L.tuned) {
       auto it = bc->tune.find(key);

@@ -566,7 +566,7 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
       HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
       c->timer.start(st, rep != nullptr);
       hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);
-      hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
+      hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(prep_threads(nmax)), 0, st, d_m, B);
       hipLaunchKernelGGL(k_level_stats, dim3(1), dim3(256), 0, st, d_m, nm, L.lstat + (size_t)t * LSTAT);
       c->timer.mark(st, 1);
       c->ktimer.pre(st);
@@ -631,7 +631,7 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
     HIP_OK(hipMemcpyAsync(dd, ha.base, first_bytes, hipMemcpyHostToDevice, st));
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);
-    hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(1024), 0, st, d_m, B);
+    hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(prep_threads(nmax)), 0, st, d_m, B);
     HIP_OK(hipGetLastError());
     c->timer.mark(st, 1);
     HIP_OK(hipMemcpyAsync(h_m, d_m, nm * sizeof(MergeDev), hipMemcpyDeviceToHost, st));

@@ -107,6 +107,15 @@ void launch_leaf_jacobi(hipStream_t st, int64_t nleaf, int leaf_max, const doubl
                         const int64_t* leaf_s0, const int32_t* leaf_m, double* w, const LeafOut* outs,
                         int max_sweeps);
 
+// k_merge_prep: one workgroup per merge, any power of two from 64 to
+// PREP_VL threads (the results do not depend on it); prep_threads picks the
+// smallest that gives every element of the level's largest merge a lane.
+constexpr int PREP_VL = 1024;
+inline int prep_threads(int nmax) {
+  int t = 64;
+  while (t < nmax && t < PREP_VL) t <<= 1;
+  return t;
+}
 __global__ void k_merge_sort(const MergeDev* __restrict__ merges, const RootBlock* __restrict__ blocks,
                              LevelBufs B);
 __global__ void k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B);

@@ -112,20 +112,32 @@ __global__ void __launch_bounds__(256) k_merge_sort(const MergeDev* __restrict__
 }
 
 __global__ void __launch_bounds__(1024) k_merge_prep(MergeDev* __restrict__ merges, LevelBufs B) {
-  __shared__ double sh[1025];
+  __shared__ double sh[PREP_VL + 1];
   MergeDev& M = merges[blockIdx.x];
   const int64_t s0 = M.s0;
   const int n = M.n, n1 = M.n1;
   const double beta = B.off[s0 + n1 - 1];
   const int tid = threadIdx.x;
 
-  // ||u||^2 over the merged order (k_merge_sort placed u unnormalised)
-  double ss = 0.0;
-  for (int p = tid; p < n; p += blockDim.x) {
-    const double u = B.zsort[s0 + p];
-    ss += u * u;
+  // ||u||^2 over the merged order (k_merge_sort placed u unnormalised), in
+  // one fixed order whatever the block size: 1024 partial sums, partial v
+  // over the entries v, v + 1024, ..., then added pairwise (v, v + 512),
+  // (v, v + 256), ...; so every launch shape gives the same bits.
+  for (int v = tid; v < PREP_VL; v += blockDim.x) {
+    double ss = 0.0;
+    for (int p = v; p < n; p += PREP_VL) {
+      const double u = B.zsort[s0 + p];
+      ss += u * u;
+    }
+    sh[v] = ss;
   }
-  const double nu2 = block_reduce(ss, sh, OpAdd());
+  __syncthreads();
+  for (int st = PREP_VL / 2; st > 0; st >>= 1) {
+    for (int v = tid; v < st; v += blockDim.x) sh[v] += sh[v + st];
+    __syncthreads();
+  }
+  const double nu2 = sh[0];
+  __syncthreads();
   const double rho = fabs(beta) * nu2;
   const double inv = (nu2 > 0.0) ? 1.0 / sqrt(nu2) : 0.0;
 
