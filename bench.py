@@ -42,19 +42,19 @@ sys.path.insert(0, ROOT)
 # kernel and its launches are unchanged (first 16 hex digits of their
 # SHA-256); otherwise the traffic is reported as null.
 TRAFFIC = {
-    "k_gemm_f64": {"bytes_per_launch": 1657.9e6,
+    "k_gemm_f64": {"bytes_per_launch": 1657.8e6,
                    "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
     "k_gemm_f64_n64": {"bytes_per_launch": 841.0e6,
                        "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
     "k_gemm_f64_n96": {"bytes_per_launch": 356.2e6,
                        "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
-    "k_pack_rot": {"bytes_per_launch": 2302.0e6,
-                   "sources": {"merge.hip": "5c74bbf48e4219ba", "dc.hip": "163d8c8d32f85627"}},
+    "k_pack_rot": {"bytes_per_launch": 2302.2e6,
+                   "sources": {"merge.hip": "039045ecc7c2eae4", "dc.hip": "87b26304af1b8410"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 29053.0e6,
-                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "163d8c8d32f85627"}},
+    "k_gemm_f64_big": {"bytes_per_launch": 29052.9e6,
+                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "87b26304af1b8410"}},
 }
 
 
