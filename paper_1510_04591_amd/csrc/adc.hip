@@ -119,6 +119,7 @@ extern "C" adc_status adc_create(adc_ctx* out, int device, void* stream) {
   {
     DeviceGuard g(device);
     c->noalloc_scratch = noalloc_scratch_init(device);  // null: the no-alloc entry reports ADC_ERR_HIP
+    leaf_init();
   }
   *out = c;
   return ADC_OK;

@@ -102,7 +102,9 @@ struct LevelBufs {
 };
 
 // ---- kernels
-// leaf eigensolves (sizes <= leaf_max <= 64) into w and each leaf's block
+// leaf eigensolves (sizes <= leaf_max <= 64) into w and each leaf's block;
+// leaf_init once per device (the LDS limit for 64-row leaves)
+void leaf_init();
 void launch_leaf_jacobi(hipStream_t st, int64_t nleaf, int leaf_max, const double* a, const double* b,
                         const int64_t* leaf_s0, const int32_t* leaf_m, double* w, const LeafOut* outs,
                         int max_sweeps);

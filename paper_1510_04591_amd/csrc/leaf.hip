@@ -142,13 +142,19 @@ __global__ void __launch_bounds__(NT) k_leaf_jacobi(const double* __restrict__ a
 
 }  // namespace
 
+// Leaves above 63 rows take more than the default 64 KiB of dynamic LDS:
+// raised once for the largest leaf (64 rows) with the device current, at
+// context creation, outside any stream capture.
+void leaf_init() {
+  hipFuncSetAttribute((const void*)k_leaf_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      2 * 64 * 65 * (int)sizeof(double));
+}
+
 void launch_leaf_jacobi(hipStream_t st, int64_t nleaf, int leaf_max, const double* a, const double* b,
                         const int64_t* leaf_s0, const int32_t* leaf_m, double* w, const LeafOut* outs,
                         int max_sweeps) {
   if (nleaf <= 0) return;
   const size_t lds = (size_t)2 * leaf_max * (leaf_max + 1) * sizeof(double);
-  // leaves above 63 rows take more than the default 64 KiB of dynamic LDS
-  if (lds > 65536) hipFuncSetAttribute((const void*)k_leaf_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_leaf_jacobi, dim3((unsigned)nleaf), dim3(NT), lds, st, a, b, leaf_s0, leaf_m, w, outs,
                      max_sweeps);
 }

@@ -50,6 +50,23 @@ def test_mixed_small_batch_vs_oracle(ctx):
         assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12, n
 
 
+def test_leaf_64_batch_and_replay(ctx):
+    """The largest leaf size through the batched solver: the leaves' LDS
+    above the default dynamic limit, eager call and graph replay, against the
+    oracle with the same leaf size."""
+    print("batched leaf 64", flush=True)
+    mats = [workloads.random_uniform(500, 61), workloads.toeplitz(64), workloads.random_uniform(129, 62)]
+    outs = run_batch(ctx, mats, reps=2, force_dense=1, dc_leaf=64)
+    for i, (a, b) in enumerate(mats):
+        w = outs[0][0][i].cpu().numpy()
+        Z = outs[0][1][i].t().cpu().numpy()
+        w_o, _ = odc.stedc(a, b, leaf=64)
+        assert np.max(np.abs(w - w_o)) <= 1e-13 * odc.tnorm1(a, b)
+        assert odc.residual(a, b, w, Z) <= 1e-13 and odc.orthogonality(Z) <= 1e-12
+        assert np.array_equal(w, outs[1][0][i].cpu().numpy())
+        assert np.array_equal(outs[0][1][i].cpu().numpy(), outs[1][1][i].cpu().numpy())
+
+
 def test_deflation_counts_match_oracle(ctx):
     """Integer parity: survivors of deflation summed per tree depth over the
     batch equal the oracle's."""
