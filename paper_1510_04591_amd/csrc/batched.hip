@@ -115,7 +115,7 @@ struct BEntry {
   char* dev = nullptr;
   size_t dev_bytes = 0;
   // global vectors
-  double *din, *offg, *a, *w, *win, *dsort, *zsort, *dS, *zS, *lam, *gam, *mu, *uh, *v, *rot_c, *rot_s;
+  double *din, *offg, *a, *w, *dsort, *zsort, *dS, *zS, *lam, *gam, *mu, *uh, *v, *rot_c, *rot_s;
   int32_t *src, *supp, *surv, *defl, *gorder, *rot_i, *rot_j, *rot_f, *posR, *posD, *pidx, *ginv, *rot_i_of,
       *rot_j_of;
   int* flags;  // [0] noconv, [1] non-finite input
@@ -206,7 +206,7 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
     return o;
   };
   const size_t V8 = (size_t)tot * 8, V4 = (size_t)tot * 4;
-  std::vector<size_t> ov8(16), ov4(14);
+  std::vector<size_t> ov8(15), ov4(14);
   for (auto& x : ov8) x = take(V8);
   for (auto& x : ov4) x = take(V4);
   const size_t o_flags = take(64);
@@ -278,9 +278,9 @@ adc_status build_entry(const std::vector<int64_t>& N, int leaf, int max_iter, BE
     return ADC_ERR_NOMEM;
   }
   char* b = e->dev;
-  double** v8[16] = {&e->din, &e->offg, &e->a, &e->w, &e->win, &e->dsort, &e->zsort, &e->dS,
+  double** v8[15] = {&e->din, &e->offg, &e->a, &e->w, &e->dsort, &e->zsort, &e->dS,
                      &e->zS, &e->lam, &e->gam, &e->mu, &e->uh, &e->v, &e->rot_c, &e->rot_s};
-  for (int q = 0; q < 16; ++q) *v8[q] = (double*)(b + ov8[q]);
+  for (int q = 0; q < 15; ++q) *v8[q] = (double*)(b + ov8[q]);
   int32_t** v4[14] = {&e->src, &e->supp, &e->surv, &e->defl, &e->gorder, &e->rot_i, &e->rot_j,
                       &e->rot_f, &e->posR, &e->posD, &e->pidx, &e->ginv, &e->rot_i_of, &e->rot_j_of};
   for (int q = 0; q < 14; ++q) *v4[q] = (int32_t*)(b + ov4[q]);
@@ -404,7 +404,7 @@ void fill_pointers(BEntry* e, const double* const* diag, const double* const* of
 
 LevelBufs level_bufs(BEntry* e) {
   LevelBufs B{};
-  B.w_in = e->win;
+  B.w_in = e->w;
   B.w_out = e->w;
   B.off = e->offg;
   B.dsort = e->dsort;
@@ -502,7 +502,6 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
   for (int t = (int)e->levels.size() - 1; t >= 0 && status == ADC_OK; --t) {
     BLevel& L = e->levels[t];
     MergeDev* dm = (MergeDev*)(d + L.o_m);
-    HIP_OK(hipMemcpyAsync(e->win, e->w, (size_t)tot * 8, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_merge_sort, dim3(L.nob), dim3(256), 0, st, dm, (const RootBlock*)(d + L.o_ob), B);
     hipLaunchKernelGGL(k_merge_prep, dim3(L.nm), dim3(prep_threads(L.nmax)), 0, st, dm, B);
     const auto key = std::make_tuple(L.nm, L.nmax, (int64_t)L.njob);

@@ -135,7 +135,7 @@ Plan make_plan(const std::vector<int64_t>& g0, const std::vector<int64_t>& nn, i
 }
 
 struct WsLayout {
-  double *a, *win, *Zb;
+  double *a, *Zb;
   double *dsort, *zsort, *dS, *zS, *lam, *gam, *mu, *uh, *v, *rot_c, *rot_s;
   int32_t *src, *supp, *surv, *defl, *gorder, *rot_i, *rot_j, *rot_f, *posR, *posD, *colmerge;
   int32_t *pidx, *ginv, *rot_i_of, *rot_j_of, *lcnt;
@@ -154,7 +154,6 @@ WsLayout layout_ws(char* base, int64_t N, size_t zb_elems, size_t pk_elems, bool
   Arena ar{base, 0, 0};
   WsLayout L{};
   L.a = ar.take<double>(N);
-  L.win = ar.take<double>(N);
   L.dsort = ar.take<double>(N);
   L.zsort = ar.take<double>(N);
   L.dS = ar.take<double>(N);
@@ -449,7 +448,7 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
     const std::vector<Node>& lev = plan.merge_levels[t];
     const int nm = (int)lev.size();
     LevelBufs B{};
-    B.w_in = L.win;
+    B.w_in = w;
     B.w_out = w;
     B.off = offdiag;
     // results of depth t in buffer t mod 2 of their matrix, the children's in the other
@@ -563,7 +562,6 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
       GemmProb* d_gp = (GemmProb*)(dd + ogp);
       int* d_gt = (int*)(dd + ogt);
       const int W = pick_waves(nmax);
-      HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
       c->timer.start(st, rep != nullptr);
       hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);
       hipLaunchKernelGGL(k_merge_prep, dim3(nm), dim3(prep_threads(nmax)), 0, st, d_m, B);
@@ -627,7 +625,6 @@ static adc_status solve_forest(adc_ctx c, const Forest& F, void* ws, size_t ws_b
       for (int i0 = 0; i0 < h_m[g2].n; i0 += 64) h_rb[nrb++] = RootBlock{g2, i0};
     }
     const size_t first_bytes = ha.off;
-    HIP_OK(hipMemcpyAsync(L.win, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(dd, ha.base, first_bytes, hipMemcpyHostToDevice, st));
     c->timer.start(st, rep != nullptr);
     hipLaunchKernelGGL(k_merge_sort, dim3(nob), dim3(256), 0, st, d_m, d_ob, B);

@@ -66,7 +66,8 @@ struct GemmProb {
 
 // Per-level scratch pointers shared by the merge kernels.
 struct LevelBufs {
-  const double* w_in;   // children's eigenvalues (copy of w)
+  const double* w_in;   // children's eigenvalues: w itself (only k_merge_sort reads it,
+                        // before the level's k_final_order writes w_out = w)
   double* w_out;        // merged eigenvalues
   const double* off;    // off-diagonal of T (b_k of every tear)
   double* dsort;        // d after merging the two runs (and rotation updates)
