@@ -48,13 +48,13 @@ TRAFFIC = {
                        "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
     "k_gemm_f64_n96": {"bytes_per_launch": 356.2e6,
                        "sources": {"gemm.hip": "1de54d48df37fd0d", "hss.hip": "8a7821e8e03d41b3"}},
-    "k_pack_rot": {"bytes_per_launch": 2302.2e6,
-                   "sources": {"merge.hip": "039045ecc7c2eae4", "dc.hip": "87b26304af1b8410"}},
+    "k_pack_rot": {"bytes_per_launch": 2302.1e6,
+                   "sources": {"merge.hip": "039045ecc7c2eae4", "dc.hip": "6b29df377f3fd2e0"}},
 }
 # the dense-update GEMM of the dense-DC run (bench.py --mode dense)
 TRAFFIC_DENSE = {
-    "k_gemm_f64_big": {"bytes_per_launch": 29052.9e6,
-                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "87b26304af1b8410"}},
+    "k_gemm_f64_big": {"bytes_per_launch": 29047.6e6,
+                       "sources": {"gemm.hip": "1de54d48df37fd0d", "dc.hip": "6b29df377f3fd2e0"}},
 }
 
 
