@@ -546,8 +546,8 @@ adc_status run_sequence(adc_ctx c, BCache* bc, BEntry* e, hipStream_t st, bool t
     hipLaunchKernelGGL(k_lowner, dim3(L.nrb), dim3(64 * L.W), 0, st, dm, rb, e->dS, e->zS, e->gam, e->mu, e->uh);
     hipLaunchKernelGGL(k_vnorm, dim3(L.nrb), dim3(64 * L.W), 0, st, dm, rb, e->dS, e->gam, e->mu, e->uh, e->v);
     hipLaunchKernelGGL(k_final_order, dim3(L.nob), dim3(256), 0, st, dm, B, (const RootBlock*)(d + L.o_ob));
-    hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)((L.njob + 3) / 4)), dim3(256), 0, st, dm, (const int32_t*)(d + L.o_cm),
-                       (const int32_t*)(d + L.o_cc), B, (int)L.njob);
+    hipLaunchKernelGGL(k_pack_rot, dim3((unsigned)((L.njob + 3) / 4)), dim3(256), 0, st, dm,
+                       (const int32_t*)(d + L.o_cm), (const int32_t*)(d + L.o_cc), B, (int)L.njob);
     hipLaunchKernelGGL(k_cauchy, dim3(L.ntile), dim3(256), 0, st, dm, (const int32_t*)(d + L.o_tm),
                        (const int32_t*)(d + L.o_tc), B, 8, 1);
     hipLaunchKernelGGL(k_build_probs, dim3((L.nm + 63) / 64), dim3(64), 0, st, dm, L.nm,
