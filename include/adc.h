@@ -219,8 +219,10 @@ adc_status adc_stedc(adc_ctx ctx, int64_t n, const double* diag, const double* o
  * (n >= hss_min_k and a top-merge dense update of at least hss_min_flops)
  * are solved together in a second level-batched pass that takes the HSS
  * route where it applies (Section 4.3), with host decisions at its HSS
- * levels.  rep may be NULL (one report for the whole batch otherwise;
- * rep->info_index is the index of the matrix that failed). */
+ * levels; they are taken in order in groups of at most 10^6 rows whose
+ * workspace fits opts->batch_bytes, one pass per group.  rep may be NULL
+ * (one report for the whole batch otherwise; rep->info_index is the index
+ * of the matrix that failed). */
 adc_status adc_stedc_batched(adc_ctx ctx, int32_t count, const int64_t* n,
                              const double* const* diag, const double* const* offdiag,
                              double* const* w, double* const* Z, const int64_t* ldz,
